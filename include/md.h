@@ -1,0 +1,195 @@
+/*
+ * md.h -- C ABI of the MI355X short-range molecular-dynamics hot path.
+ *
+ * The library computes, on one GPU, the steps of the cell-task method of
+ * R. Meyer, "Efficient Parallelization of Short-Range Molecular Dynamics
+ * Simulations on Many-Core Systems" (arXiv:1305.4196):
+ *   - particles binned into linked cells of width >= cutoff (Sec. II.A);
+ *   - Verlet neighbor lists generated cell by cell, each cell's work writing
+ *     only its own particles' lists (Sec. II.A, II.C);
+ *   - pair (Lennard-Jones) and many-body (Finnis-Sinclair-type EAM, the
+ *     potential family of Sec. II.C) forces, with no particle updated by two
+ *     workers at once (the invariant of Sec. II.A);
+ *   - the equations of motion as a per-particle loop (Sec. II.A), here
+ *     velocity Verlet;
+ *   - adjoints of forces and energy, and replica batches (the replica-carrying
+ *     functor of Sec. II.C).
+ *
+ * Conventions (all calls):
+ *   - Pointers are DEVICE pointers unless marked [host].
+ *   - Per-atom arrays are structure-of-arrays double[3][N]: all x, then all y,
+ *     then all z, in the caller's ("user") atom order.  The caller owns every
+ *     buffer it passes; the library never frees caller memory.
+ *   - Atoms of replica r are user indices [offsets[r], offsets[r+1]).  Each
+ *     replica is an orthorhombic periodic box with origin 0.
+ *   - Every call enqueues work on `stream` (a hipStream_t, passed as void*) and
+ *     returns without synchronising, except where marked "synchronises".
+ *   - Return values: MD_OK or a negative md_status.  Argument errors are found
+ *     on the host before anything is enqueued.  Conditions found on the device
+ *     (neighbor-list overflow, non-finite forces) set sticky flags that
+ *     md_get_status reports.
+ *   - One context per stream; contexts share no state.
+ */
+#ifndef MD_H
+#define MD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MD_OK = 0,
+    MD_ERR_ARG = -1,        /* bad argument (null pointer, n <= 0, non-finite or non-positive size) */
+    MD_ERR_BOX = -2,        /* some box edge is shorter than 2 (rc + skin): minimum image not unique */
+    MD_ERR_CAPACITY = -3,   /* neighbor list overflowed its per-atom capacity (see md_get_status) */
+    MD_ERR_NONFINITE = -4,  /* a force or position became NaN/Inf on the device */
+    MD_ERR_HIP = -5,        /* a HIP runtime call failed */
+    MD_ERR_STATE = -6       /* call out of order (e.g. forces before cells/list) */
+} md_status;
+
+typedef enum { MD_FP64 = 0, MD_MIXED = 1 } md_precision;
+/* MD_FP64: every operation in binary64.
+ * MD_MIXED: displacement, squared distance and every cutoff test in binary64;
+ *           pair arithmetic (potential, force magnitude, tables) in binary32;
+ *           per-atom accumulation, integration and global sums in binary64. */
+
+typedef enum { MD_LIST_FULL = 0, MD_LIST_HALF = 1 } md_list_kind;
+/* MD_LIST_FULL: every pair is stored with both atoms; each atom's force is
+ *               written only by the worker that owns the atom (no atomics).
+ * MD_LIST_HALF: Newton-3 list, each pair once (Sec. II.D.3), held by the atom
+ *               that comes first in the cell-sorted order; the partner's force
+ *               is accumulated with binary64 atomics (order not deterministic). */
+
+typedef enum { MD_POT_LJ = 0, MD_POT_EAM = 1 } md_pot_kind;
+
+/* Uniform-knot cubic table: on interval k (x in [x0 + k h, x0 + (k+1) h)),
+ * f(x) = a0 + a1 t + a2 t^2 + a3 t^3 with u = (x - x0)/h, k = min(floor(u), n_knots-2),
+ * t = u - k.  coef: DEVICE pointer to (n_knots - 1) x 4 doubles, row k = (a0..a3). */
+typedef struct {
+    int32_t n_knots;
+    double x0;
+    double h;
+    const double *coef;
+} md_spline;
+
+/* Potential description.
+ * LJ:  V(r) = 4 eps [(sigma/r)^12 - (sigma/r)^6] for r < rc, else 0 (unshifted);
+ *      lj_params is a DEVICE pointer to {eps, sigma}.
+ * EAM: E = sum_i F(rho_i) + sum_{i<j} phi(r_ij), rho_i = sum_{j!=i} rho(r_ij);
+ *      phi is zero for r >= rc_phi, rho zero for r >= rc_rho; F beyond its last
+ *      knot continues linearly.  rc must equal max(rc_phi, rc_rho). */
+typedef struct {
+    int32_t kind;             /* md_pot_kind */
+    double rc;                /* interaction cutoff; must equal the rc given to md_build_cells */
+    const double *lj_params;  /* LJ: device {eps, sigma} */
+    md_spline phi, rho, embed;/* EAM tables */
+    double rc_phi, rc_rho;    /* EAM cutoffs */
+} md_potential;
+
+typedef struct md_ctx md_ctx;
+
+/* Create a context for n_atoms_total atoms in n_replicas replicas.
+ * replica_offsets [host]: n_replicas + 1 int64, offsets[0] = 0,
+ * offsets[n_replicas] = n_atoms_total, non-decreasing with every replica
+ * non-empty.  Allocates the per-atom workspace on the current device.
+ * Errors: MD_ERR_ARG, MD_ERR_HIP. */
+int md_create(md_ctx **ctx, int64_t n_atoms_total, int32_t n_replicas,
+              const int64_t *replica_offsets);
+
+/* Free the context and all its workspace (synchronises the device). */
+void md_destroy(md_ctx *ctx);
+
+/* Linked cells (Sec. II.A).  pos: [3][N] user order (need not be wrapped).
+ * boxes [host]: n_replicas x 3 edge lengths.  Positions are wrapped into
+ * [0, L) (x - L floor(x/L); x >= L -> x - L; x < 0 -> 0), each replica gets
+ * n_c = floor(L_d / (rc + skin)) cells per dimension (width >= rc + skin),
+ * cell index x fastest, and the context's internal copy of the atoms is
+ * sorted by (cell, user index).  The cell grid is re-planned only when a box,
+ * rc or skin changes.  Errors: MD_ERR_ARG (rc <= 0, skin < 0, non-finite or
+ * non-positive L), MD_ERR_BOX (L_d < 2 (rc + skin)), MD_ERR_HIP. */
+int md_build_cells(md_ctx *ctx, const double *pos, const double *boxes_host, double rc,
+                   double skin, void *stream);
+
+/* Verlet lists from the cells (Sec. II.A): for each atom, the distinct cells
+ * of its 3x3x3 neighbourhood are scanned and every other atom with
+ * r2 < (rc + skin)^2 is kept, where d = minimum image of x_i - x_j
+ * (d > L/2 -> d - L, d < -L/2 -> d + L) and r2 = (dx*dx + dy*dy) + dz*dz, all in
+ * binary64 without contraction, so the pair set equals the exhaustive one
+ * bit for bit.  The first call sizes the per-atom capacity (synchronises);
+ * later calls regrow it if md_get_status reported an overflow.
+ * Errors: MD_ERR_STATE (no cells), MD_ERR_HIP. */
+int md_build_neighbor_list(md_ctx *ctx, int32_t list_kind, void *stream);
+
+/* Forces at the current cells/list.  forces: [3][N] out, user order.
+ * energy, virial: [n_replicas] out (DEVICE), per replica E and scalar virial
+ * W = sum_{i<j} d_ij . f_ij; either may be NULL.  Sums are taken in a fixed
+ * order (bitwise repeatable for the full list).
+ * Errors: MD_ERR_ARG, MD_ERR_STATE (no list, or rc differs), MD_ERR_HIP. */
+int md_compute_forces(md_ctx *ctx, const md_potential *pot, int32_t precision, double *forces,
+                      double *energy, double *virial, void *stream);
+
+/* n_steps of velocity Verlet (the per-particle integration loop of Sec. II.A):
+ * cells and list are rebuilt from pos, forces F(x0) computed; then per step
+ * v += dt/(2m) F; x += dt v; wrap; if max_i |minimage(x_i - x_i^ref)|^2 >
+ * (skin/2)^2 rebuild cells and list (decided on the device, no host sync);
+ * F <- F(x); v += dt/(2m) F.  pos, vel: [3][N] in/out; forces: [3][N] out
+ * (forces at the final positions).  energy_hist: n_steps x 3 doubles (E_pot,
+ * KE, W) per step, summed over replicas, or NULL.  rebuilds: 1 int32 out
+ * (DEVICE, number of rebuilds after the initial one) or NULL.  Uses the rc and
+ * skin of the last md_build_cells.  If md_get_status then reports
+ * MD_ERR_CAPACITY, the outputs are invalid: the context has grown its
+ * capacity and the caller repeats the call from its saved inputs.
+ * Errors: MD_ERR_ARG (n_steps < 1, dt or mass not finite/positive),
+ * MD_ERR_STATE, MD_ERR_BOX, MD_ERR_HIP. */
+int md_verlet_step(md_ctx *ctx, const md_potential *pot, int32_t precision, int32_t list_kind,
+                   double *pos, double *vel, double *forces, double dt, double mass,
+                   int32_t n_steps, double *energy_hist, int32_t *rebuilds, void *stream);
+
+/* Adjoint (vector-Jacobian product) of (F, E) at positions pos with the
+ * current cells/list (pos must lie within skin/2 of the positions the list was
+ * built from; pos == NULL means exactly those positions).  Inputs: cotangent
+ * u_forces [3][N] on the forces and v_energy [n_replicas] on the energies.
+ * Outputs: g_pos [3][N] = d(sum_r v_r E_r + u.F)/dx = -v F - H u (user order),
+ * g_params = d(...)/d(parameters) summed over replicas: LJ {d/deps, d/dsigma}
+ * (2 doubles); EAM the three tables' shapes back to back, phi then rho then
+ * embed ((n_knots-1) x 4 each).  Either output may be NULL.  Parameter
+ * histograms use binary64 atomics (last-bit order not deterministic).
+ * Errors: MD_ERR_ARG, MD_ERR_STATE, MD_ERR_HIP. */
+int md_force_vjp(md_ctx *ctx, const md_potential *pot, int32_t precision, const double *pos,
+                 const double *u_forces, const double *v_energy, double *g_pos,
+                 double *g_params, void *stream);
+
+/* Device status (synchronises the context's last stream).  device_flags
+ * [host]: bit 0 list overflow, bit 1 non-finite force; cleared after reading.
+ * required_capacity [host]: per-atom list capacity now allocated or required.
+ * Returns MD_ERR_CAPACITY / MD_ERR_NONFINITE if the flag is set, else MD_OK. */
+int md_get_status(md_ctx *ctx, int32_t *device_flags, int64_t *required_capacity);
+
+/* Export the current neighbor list as CSR over user indices (for checking).
+ * start [host]: N+1 int64 out; nbr [host]: capacity ints out (unordered within
+ * an atom); returns the number of entries (which may exceed capacity: then
+ * nothing is written to nbr) or a negative md_status.  Synchronises. */
+int64_t md_get_neighbor_list(md_ctx *ctx, int64_t *start, int32_t *nbr, int64_t capacity);
+
+/* Export the cells (for checking) [host]: cell_start (n_cells_total + 1 int32),
+ * order (N int32: user index of each sorted slot), n_cells_total (1 int64).
+ * Pass NULL arrays to query n_cells_total only.  Synchronises. */
+int md_get_cells(md_ctx *ctx, int32_t *cell_start, int32_t *order, int64_t *n_cells_total);
+
+/* Tuning knobs (used by the autotuner): key 0 = lanes per atom in the
+ * neighbour loops (4, 8, 16 or 32); key 1 = workgroups per CU of the
+ * persistent force grids (1..16); key 2 = fixed per-atom list capacity
+ * (1..4096; reallocates, synchronises the device, and drops the current list --
+ * a small value forces the overflow path).  Returns MD_OK or MD_ERR_ARG. */
+int md_set_tuning(md_ctx *ctx, int32_t key, int32_t value);
+
+/* Human-readable description of the last error on this context (static storage). */
+const char *md_last_error(md_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MD_H */

@@ -1,0 +1,746 @@
+// md_api.hip -- host side of the C ABI declared in include/md.h.
+//
+// The context owns all workspace; every entry point validates its arguments on
+// the host, then enqueues kernels on the caller's stream.  Inside md_verlet_step
+// the rebuild decision is taken on the device (a predicate word per step parity),
+// so a run of n steps is one stream of launches with no host round trip.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "md_internal.h"
+
+namespace {
+
+__global__ void k_set_ctl(DevCtl *ctl, int reset_rebuild, int reset_count)
+{
+    if (threadIdx.x == 0) {
+        if (reset_rebuild) {
+            ctl->rebuild[0] = 0;
+            ctl->rebuild[1] = 0;
+        }
+        if (reset_count) ctl->nrebuild = 0;
+    }
+}
+
+__global__ void k_copy_int(const int32_t *src, int32_t *dst)
+{
+    if (threadIdx.x == 0) *dst = *src;
+}
+
+__global__ void k_pos_from_user(int64_t n, const RepDesc *__restrict__ reps,
+                                const int32_t *__restrict__ rep_of, const int32_t *__restrict__ id,
+                                const double *__restrict__ user, const double4 *__restrict__ xref,
+                                double4 *__restrict__ pos)
+{
+    // positions continued from the build-time reference by the minimum image,
+    // so that the image fixed with each list entry stays valid
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const RepDesc &r = reps[rep_of[i]];
+        const int64_t u = id[i];
+        const double4 x0 = xref[i];
+        double d[3] = {user[u] - x0.x, user[n + u] - x0.y, user[2 * n + u] - x0.z};
+        for (int c = 0; c < 3; c++) {
+            if (d[c] > r.hL[c]) d[c] = d[c] - r.L[c];
+            else if (d[c] < -r.hL[c]) d[c] = d[c] + r.L[c];
+        }
+        pos[i] = make_double4(x0.x + d[0], x0.y + d[1], x0.z + d[2], 0.0);
+    }
+}
+
+template <typename T>
+bool dalloc(T **p, size_t count)
+{
+    if (*p != nullptr) {
+        (void)hipFree(*p);
+        *p = nullptr;
+    }
+    if (count == 0) count = 1;
+    return hipMalloc((void **)p, sizeof(T) * count) == hipSuccess;
+}
+
+template <typename T>
+void dfree(T *&p)
+{
+    if (p != nullptr) (void)hipFree(p);
+    p = nullptr;
+}
+
+} // namespace
+
+struct md_ctx {
+    int device = 0;
+    int64_t n = 0;
+    int32_t R = 0;
+    std::vector<int64_t> off;
+    int n_cu = 256;
+    int wgpc = 8;      // workgroups per CU of the persistent force grids
+    int tpp = 8;       // lanes per atom in the neighbour loops
+    std::string err;
+    hipStream_t last = nullptr;
+
+    // geometry
+    bool have_cells = false;
+    double rc = 0.0, skin = 0.0, rl = 0.0;
+    std::vector<double> boxes;
+    std::vector<RepDesc> reps_h;
+    RepDesc *reps = nullptr;
+    int64_t C = 0, C_alloc = 0;
+    int32_t *rep_of = nullptr;
+
+    // atoms (cell-sorted)
+    double4 *pos[2] = {nullptr, nullptr};
+    double4 *pos_t = nullptr, *xref = nullptr;
+    double *vel = nullptr, *vel_t = nullptr, *force = nullptr;
+    int32_t *id = nullptr, *id_t = nullptr;
+    int32_t *cell_of = nullptr, *slot = nullptr, *perm = nullptr;
+    int32_t *count = nullptr, *start = nullptr;
+    int cur = 0;
+
+    // list
+    bool have_list = false;
+    int list_kind = MD_LIST_FULL;
+    int32_t M = 0;
+    int64_t need_M = 0;
+    uint32_t *nbr = nullptr;
+    int32_t *cnt = nullptr;
+
+    // scratch
+    double *partial = nullptr;      // [maxgrid][4] x 4 sites
+    double *eatom = nullptr, *watom = nullptr;
+    double *rho = nullptr, *fp = nullptr, *fpp = nullptr, *rdot = nullptr;
+    double *u_s = nullptr, *gx_s = nullptr;
+    double *zeros_R = nullptr;
+    double *tab64 = nullptr;
+    float *tab32 = nullptr;
+    int64_t tab_cap = 0;
+    DevCtl *ctl = nullptr;
+    int32_t *one = nullptr;
+
+    int max_grid() const { return n_cu * 16; }
+    int grid_atoms(int64_t per_block) const
+    {
+        int64_t g = (n + per_block - 1) / per_block;
+        int64_t cap = (int64_t)n_cu * 8;
+        return (int)std::max<int64_t>(1, std::min(g, cap));
+    }
+    int grid_force(int apb) const
+    {
+        int64_t g = (n + apb - 1) / apb;
+        int64_t cap = (int64_t)n_cu * wgpc;
+        return (int)std::max<int64_t>(1, std::min(g, cap));
+    }
+    int grid_cells(int cells_per_block, int per_cu) const
+    {
+        int64_t g = (C + cells_per_block - 1) / cells_per_block;
+        int64_t cap = (int64_t)n_cu * per_cu;
+        return (int)std::max<int64_t>(1, std::min(g, cap));
+    }
+};
+
+namespace {
+
+int fail(md_ctx *c, int code, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+int check_hip(md_ctx *c, const char *where)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(c, MD_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+    return MD_OK;
+}
+
+bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+// cell grid of every replica; returns MD_OK, MD_ERR_ARG or MD_ERR_BOX
+int plan_cells(md_ctx *c, const double *boxes, double rc, double skin, hipStream_t s)
+{
+    if (!(isfinite(rc) && rc > 0.0)) return fail(c, MD_ERR_ARG, "rc must be finite and > 0");
+    if (!(isfinite(skin) && skin >= 0.0)) return fail(c, MD_ERR_ARG, "skin must be finite and >= 0");
+    const double rl = rc + skin;
+    for (int32_t r = 0; r < c->R; r++)
+        for (int d = 0; d < 3; d++) {
+            const double L = boxes[3 * r + d];
+            if (!finite_pos(L)) return fail(c, MD_ERR_ARG, "box edges must be finite and > 0");
+            if (!(L >= 2.0 * rl)) return fail(c, MD_ERR_BOX, "box edge shorter than 2 (rc + skin)");
+        }
+    bool same = c->have_cells && c->rc == rc && c->skin == skin &&
+                std::equal(c->boxes.begin(), c->boxes.end(), boxes);
+    if (same) return MD_OK;
+    c->reps_h.assign(c->R, RepDesc{});
+    int64_t cells = 0;
+    for (int32_t r = 0; r < c->R; r++) {
+        RepDesc &d = c->reps_h[r];
+        for (int k = 0; k < 3; k++) {
+            d.L[k] = boxes[3 * r + k];
+            d.hL[k] = 0.5 * d.L[k];
+            d.nc[k] = (int32_t)floor(d.L[k] / rl);
+            if (d.nc[k] < 1) d.nc[k] = 1;
+        }
+        d.cell_off = cells;
+        d.atom_off = c->off[r];
+        d.atom_end = c->off[r + 1];
+        cells += (int64_t)d.nc[0] * d.nc[1] * d.nc[2];
+    }
+    if (cells >= (1ll << 31) - 1) return fail(c, MD_ERR_ARG, "too many cells");
+    if (cells > c->C_alloc) {
+        if (!dalloc(&c->count, cells) || !dalloc(&c->start, cells + 1))
+            return fail(c, MD_ERR_HIP, "cell arrays: out of device memory");
+        if (hipMemsetAsync(c->count, 0, sizeof(int32_t) * cells, s) != hipSuccess)
+            return fail(c, MD_ERR_HIP, "cell arrays: memset");
+        c->C_alloc = cells;
+    }
+    c->C = cells;
+    if (hipMemcpyAsync(c->reps, c->reps_h.data(), sizeof(RepDesc) * c->R, hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(c, MD_ERR_HIP, "replica descriptors: copy");
+    c->rc = rc;
+    c->skin = skin;
+    c->rl = rl;
+    c->boxes.assign(boxes, boxes + 3 * c->R);
+    return MD_OK;
+}
+
+// bin -> scan -> scatter -> per-cell sort of pos[cur] (and vel, id) into the *_t buffers
+void sort_into_tmp(md_ctx *c, const int32_t *pred, bool with_vel, hipStream_t s)
+{
+    const int ga = c->grid_atoms(256);
+    launch_bin(s, ga, pred, c->n, c->R, c->reps, c->rep_of, c->pos[c->cur], c->cell_of, c->slot,
+               c->count);
+    launch_scan(s, pred, c->C, c->count, c->start, c->ctl);
+    launch_scatter(s, ga, pred, c->n, c->cell_of, c->slot, c->start, c->perm);
+    launch_sort_cells(s, c->grid_cells(4, 8), pred, c->C, c->start, c->perm, c->id, c->pos[c->cur],
+                      with_vel ? c->vel : nullptr, c->n, c->pos_t, with_vel ? c->vel_t : nullptr,
+                      c->id_t);
+}
+
+ListArgs list_args(md_ctx *c, const int32_t *pred, const double4 *src, int half)
+{
+    ListArgs a{};
+    a.pred = pred;
+    a.C = c->C;
+    a.R = c->R;
+    a.reps = c->reps;
+    a.start = c->start;
+    a.src = src;
+    a.n = c->n;
+    a.nbr = c->nbr;
+    a.cnt = c->cnt;
+    a.M = c->M;
+    a.rl2 = c->rl * c->rl;
+    a.half = half;
+    a.ctl = c->ctl;
+    return a;
+}
+
+// first build: count pass, then size the rows (1.25 x the largest list + margin)
+int size_list(md_ctx *c, const double4 *src, int half, hipStream_t s)
+{
+    ListArgs a = list_args(c, c->one, src, half);
+    a.M = 0;
+    a.nbr = nullptr;
+    int32_t zero = 0;
+    if (hipMemcpyAsync(&c->ctl->max_cnt, &zero, sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(c, MD_ERR_HIP, "list sizing: reset");
+    launch_build_list(s, c->grid_cells(4, 3), a);
+    int32_t mx = 0;
+    if (hipMemcpyAsync(&mx, &c->ctl->max_cnt, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(c, MD_ERR_HIP, "list sizing: readback");
+    int64_t want = std::max<int64_t>({(int64_t)ceil(1.25 * mx), (int64_t)mx + 16, c->need_M, 16});
+    want = (want + 7) / 8 * 8;
+    if (want * c->n > (1ll << 40)) return fail(c, MD_ERR_ARG, "neighbour list too large");
+    if (!dalloc(&c->nbr, (size_t)(want * c->n))) return fail(c, MD_ERR_HIP, "list: out of device memory");
+    c->M = (int32_t)want;
+    c->need_M = 0;
+    return MD_OK;
+}
+
+int ensure_list_capacity(md_ctx *c, const double4 *src, int half, hipStream_t s)
+{
+    if (c->M == 0 || c->need_M > c->M) return size_list(c, src, half, s);
+    return MD_OK;
+}
+
+ForceArgs force_args(md_ctx *c, const md_potential *p)
+{
+    ForceArgs a{};
+    a.n = c->n;
+    a.R = c->R;
+    a.reps = c->reps;
+    a.rep0 = c->reps_h[0];
+    a.rep_of = c->rep_of;
+    a.pos = c->pos[c->cur];
+    a.pos_next = c->pos[1 - c->cur];
+    a.xref = c->xref;
+    a.vel = c->vel;
+    a.force = c->force;
+    a.nbr = c->nbr;
+    a.cnt = c->cnt;
+    a.M = c->M;
+    a.rc2 = p->rc * p->rc;
+    a.lj = p->lj_params;
+    a.rho = c->rho;
+    a.fp = c->fp;
+    a.partial = c->partial;
+    a.done = &c->ctl->done[0];
+    a.ctl = c->ctl;
+    a.mass = 1.0;
+    if (p->kind == MD_POT_EAM) {
+        const md_spline *sp[3] = {&p->phi, &p->rho, &p->embed};
+        int64_t o = 0;
+        for (int k = 0; k < 3; k++) {
+            a.tab[k] = c->tab64 + o;
+            a.tabf[k] = c->tab32 + o;
+            a.nk[k] = sp[k]->n_knots;
+            a.x0[k] = sp[k]->x0;
+            a.inv_h[k] = 1.0 / sp[k]->h;
+            o += 4 * (int64_t)(sp[k]->n_knots - 1);
+        }
+        a.rphi2 = p->rc_phi * p->rc_phi;
+        a.rrho2 = p->rc_rho * p->rc_rho;
+    }
+    return a;
+}
+
+int check_pot(md_ctx *c, const md_potential *p)
+{
+    if (p == nullptr) return fail(c, MD_ERR_ARG, "potential is null");
+    if (!(isfinite(p->rc) && p->rc > 0.0)) return fail(c, MD_ERR_ARG, "potential rc must be > 0");
+    if (p->rc != c->rc) return fail(c, MD_ERR_STATE, "potential rc differs from the rc of md_build_cells");
+    if (p->kind == MD_POT_LJ) {
+        if (p->lj_params == nullptr) return fail(c, MD_ERR_ARG, "LJ parameters are null");
+        return MD_OK;
+    }
+    if (p->kind != MD_POT_EAM) return fail(c, MD_ERR_ARG, "unknown potential kind");
+    const md_spline *sp[3] = {&p->phi, &p->rho, &p->embed};
+    for (int k = 0; k < 3; k++) {
+        if (sp[k]->coef == nullptr || sp[k]->n_knots < 2 || !finite_pos(sp[k]->h) || !isfinite(sp[k]->x0))
+            return fail(c, MD_ERR_ARG, "EAM table: need coef, n_knots >= 2, finite h > 0");
+    }
+    if (!finite_pos(p->rc_phi) || !finite_pos(p->rc_rho) || std::max(p->rc_phi, p->rc_rho) != p->rc)
+        return fail(c, MD_ERR_ARG, "EAM cutoffs: rc must equal max(rc_phi, rc_rho)");
+    return MD_OK;
+}
+
+// copy (and convert) the EAM tables into aligned context buffers
+int stage_tables(md_ctx *c, const md_potential *p, hipStream_t s)
+{
+    if (p->kind != MD_POT_EAM) return MD_OK;
+    const md_spline *sp[3] = {&p->phi, &p->rho, &p->embed};
+    int64_t total = 0;
+    for (int k = 0; k < 3; k++) total += 4 * (int64_t)(sp[k]->n_knots - 1);
+    if (total > c->tab_cap) {
+        if (!dalloc(&c->tab64, total) || !dalloc(&c->tab32, total))
+            return fail(c, MD_ERR_HIP, "tables: out of device memory");
+        c->tab_cap = total;
+    }
+    int64_t o = 0;
+    for (int k = 0; k < 3; k++) {
+        const int64_t m = 4 * (int64_t)(sp[k]->n_knots - 1);
+        if (hipMemcpyAsync(c->tab64 + o, sp[k]->coef, sizeof(double) * m, hipMemcpyDeviceToDevice, s) !=
+            hipSuccess)
+            return fail(c, MD_ERR_HIP, "tables: copy");
+        o += m;
+    }
+    launch_tables_f32(s, c->tab64, c->tab32, total);
+    return MD_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+int md_create(md_ctx **out, int64_t n, int32_t R, const int64_t *off)
+{
+    if (out == nullptr) return MD_ERR_ARG;
+    *out = nullptr;
+    if (n <= 0 || n > MD_MAX_ATOMS || R <= 0 || off == nullptr) return MD_ERR_ARG;
+    if (off[0] != 0 || off[R] != n) return MD_ERR_ARG;
+    for (int32_t r = 0; r < R; r++)
+        if (off[r + 1] <= off[r]) return MD_ERR_ARG;
+    md_ctx *c = new md_ctx();
+    c->n = n;
+    c->R = R;
+    c->off.assign(off, off + R + 1);
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return MD_ERR_HIP;
+    }
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess &&
+        ncu > 0)
+        c->n_cu = ncu;
+    bool ok = true;
+    ok &= dalloc(&c->pos[0], n) && dalloc(&c->pos[1], n) && dalloc(&c->pos_t, n) && dalloc(&c->xref, n);
+    ok &= dalloc(&c->vel, 3 * n) && dalloc(&c->vel_t, 3 * n) && dalloc(&c->force, 3 * n);
+    ok &= dalloc(&c->id, n) && dalloc(&c->id_t, n) && dalloc(&c->cell_of, n) && dalloc(&c->slot, n) &&
+          dalloc(&c->perm, n) && dalloc(&c->cnt, n) && dalloc(&c->rep_of, n);
+    ok &= dalloc(&c->eatom, n) && dalloc(&c->watom, n) && dalloc(&c->rho, n) && dalloc(&c->fp, n) &&
+          dalloc(&c->fpp, n) && dalloc(&c->rdot, n);
+    ok &= dalloc(&c->u_s, 3 * n) && dalloc(&c->gx_s, 3 * n);
+    ok &= dalloc(&c->partial, (size_t)c->max_grid() * 4 * 4) && dalloc(&c->zeros_R, R);
+    ok &= dalloc(&c->reps, R) && dalloc(&c->ctl, 1) && dalloc(&c->one, 1);
+    if (!ok) {
+        md_destroy(c);
+        return MD_ERR_HIP;
+    }
+    std::vector<int32_t> rep(n);
+    for (int32_t r = 0; r < R; r++)
+        for (int64_t i = off[r]; i < off[r + 1]; i++) rep[i] = r;
+    const int32_t one = 1;
+    DevCtl z{};
+    std::vector<double> zr(R, 0.0);
+    ok = hipMemcpy(c->rep_of, rep.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(c->one, &one, sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(c->ctl, &z, sizeof(DevCtl), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(c->zeros_R, zr.data(), sizeof(double) * R, hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) {
+        md_destroy(c);
+        return MD_ERR_HIP;
+    }
+    *out = c;
+    return MD_OK;
+}
+
+void md_destroy(md_ctx *c)
+{
+    if (c == nullptr) return;
+    (void)hipDeviceSynchronize();
+    dfree(c->pos[0]); dfree(c->pos[1]); dfree(c->pos_t); dfree(c->xref);
+    dfree(c->vel); dfree(c->vel_t); dfree(c->force);
+    dfree(c->id); dfree(c->id_t); dfree(c->cell_of); dfree(c->slot); dfree(c->perm);
+    dfree(c->count); dfree(c->start); dfree(c->nbr); dfree(c->cnt); dfree(c->rep_of);
+    dfree(c->eatom); dfree(c->watom); dfree(c->rho); dfree(c->fp); dfree(c->fpp); dfree(c->rdot);
+    dfree(c->u_s); dfree(c->gx_s); dfree(c->partial); dfree(c->zeros_R);
+    dfree(c->tab64); dfree(c->tab32); dfree(c->reps); dfree(c->ctl); dfree(c->one);
+    delete c;
+}
+
+int md_build_cells(md_ctx *c, const double *pos, const double *boxes, double rc, double skin,
+                   void *stream)
+{
+    if (c == nullptr) return MD_ERR_ARG;
+    if (pos == nullptr || boxes == nullptr) return fail(c, MD_ERR_ARG, "null argument");
+    hipStream_t s = (hipStream_t)stream;
+    c->last = s;
+    int rcode = plan_cells(c, boxes, rc, skin, s);
+    if (rcode != MD_OK) return rcode;
+    launch_load_user(s, c->grid_atoms(256), c->n, pos, nullptr, c->pos[c->cur], c->vel, c->id);
+    sort_into_tmp(c, c->one, false, s);
+    launch_copy_back(s, c->grid_atoms(256), c->one, c->n, c->pos_t, nullptr, c->id_t,
+                     c->pos[c->cur], nullptr, c->id, c->xref);
+    c->have_cells = true;
+    c->have_list = false;
+    return check_hip(c, "md_build_cells");
+}
+
+int md_build_neighbor_list(md_ctx *c, int32_t kind, void *stream)
+{
+    if (c == nullptr) return MD_ERR_ARG;
+    if (kind != MD_LIST_FULL && kind != MD_LIST_HALF) return fail(c, MD_ERR_ARG, "unknown list kind");
+    if (!c->have_cells) return fail(c, MD_ERR_STATE, "md_build_cells first");
+    hipStream_t s = (hipStream_t)stream;
+    c->last = s;
+    const int half = kind == MD_LIST_HALF;
+    int rcode = ensure_list_capacity(c, c->pos[c->cur], half, s);
+    if (rcode != MD_OK) return rcode;
+    launch_build_list(s, c->grid_cells(4, 3), list_args(c, c->one, c->pos[c->cur], half));
+    c->have_list = true;
+    c->list_kind = kind;
+    return check_hip(c, "md_build_neighbor_list");
+}
+
+int md_compute_forces(md_ctx *c, const md_potential *p, int32_t precision, double *forces,
+                      double *energy, double *virial, void *stream)
+{
+    if (c == nullptr) return MD_ERR_ARG;
+    if (forces == nullptr) return fail(c, MD_ERR_ARG, "forces is null");
+    if (precision != MD_FP64 && precision != MD_MIXED) return fail(c, MD_ERR_ARG, "unknown precision");
+    if (!c->have_list) return fail(c, MD_ERR_STATE, "md_build_neighbor_list first");
+    int rcode = check_pot(c, p);
+    if (rcode != MD_OK) return rcode;
+    if (c->list_kind == MD_LIST_HALF && (p->kind != MD_POT_LJ || c->R > 1))
+        return fail(c, MD_ERR_STATE, "the half list serves LJ on one replica; build a full list");
+    hipStream_t s = (hipStream_t)stream;
+    c->last = s;
+    if ((rcode = stage_tables(c, p, s)) != MD_OK) return rcode;
+    const bool mixed = precision == MD_MIXED;
+    ForceArgs a = force_args(c, p);
+    a.mode = 0;
+    if (c->R == 1) {
+        a.outE = energy;
+        a.outW = virial;
+    } else {
+        a.eatom = c->eatom;
+        a.watom = c->watom;
+    }
+    const int gf = c->grid_force(256 / c->tpp);
+    if (p->kind == MD_POT_LJ && c->list_kind == MD_LIST_HALF) {
+        launch_zero(s, c->grid_atoms(256), c->force, 3 * c->n);
+        launch_lj_half(s, gf, c->tpp, mixed, a);
+    } else if (p->kind == MD_POT_LJ) {
+        launch_lj_full(s, gf, c->tpp, mixed, a);
+    } else {
+        launch_eam_density(s, gf, c->tpp, mixed, a);
+        launch_eam_force(s, gf, c->tpp, mixed, a);
+    }
+    if (c->R > 1 && (energy != nullptr || virial != nullptr))
+        launch_replica_sums(s, c->R, c->reps, c->eatom, c->watom, energy, virial);
+    launch_to_user(s, c->grid_atoms(256), c->n, c->id, c->force, forces);
+    return check_hip(c, "md_compute_forces");
+}
+
+int md_verlet_step(md_ctx *c, const md_potential *p, int32_t precision, int32_t kind, double *pos,
+                   double *vel, double *forces, double dt, double mass, int32_t n_steps,
+                   double *hist, int32_t *rebuilds, void *stream)
+{
+    if (c == nullptr) return MD_ERR_ARG;
+    if (pos == nullptr || vel == nullptr || forces == nullptr) return fail(c, MD_ERR_ARG, "null argument");
+    if (n_steps < 1 || !finite_pos(dt) || !finite_pos(mass)) return fail(c, MD_ERR_ARG, "need n_steps >= 1, dt > 0, mass > 0");
+    if (precision != MD_FP64 && precision != MD_MIXED) return fail(c, MD_ERR_ARG, "unknown precision");
+    if (kind != MD_LIST_FULL && kind != MD_LIST_HALF) return fail(c, MD_ERR_ARG, "unknown list kind");
+    if (!c->have_cells) return fail(c, MD_ERR_STATE, "md_build_cells first (sets boxes, rc, skin)");
+    int rcode = check_pot(c, p);
+    if (rcode != MD_OK) return rcode;
+    if (kind == MD_LIST_HALF && p->kind != MD_POT_LJ) return fail(c, MD_ERR_STATE, "the half list serves LJ only");
+    hipStream_t s = (hipStream_t)stream;
+    c->last = s;
+    if ((rcode = stage_tables(c, p, s)) != MD_OK) return rcode;
+    const bool mixed = precision == MD_MIXED;
+    const int half = kind == MD_LIST_HALF;
+    const int ga = c->grid_atoms(256);
+
+    // initial state: user order -> sorted, cells and list from scratch
+    hipLaunchKernelGGL(k_set_ctl, dim3(1), dim3(64), 0, s, c->ctl, 1, 1);
+    launch_load_user(s, ga, c->n, pos, vel, c->pos[c->cur], c->vel, c->id);
+    sort_into_tmp(c, c->one, true, s);
+    if ((rcode = ensure_list_capacity(c, c->pos_t, half, s)) != MD_OK) return rcode;
+    {
+        ListArgs la = list_args(c, c->one, c->pos_t, half);
+        la.vel_src = c->vel_t;
+        la.id_src = c->id_t;
+        la.pos_dst = c->pos[c->cur];
+        la.vel_dst = c->vel;
+        la.id_dst = c->id;
+        la.xref = c->xref;
+        launch_build_list(s, c->grid_cells(4, 3), la);
+    }
+    c->have_list = true;
+    c->list_kind = kind;
+    hipLaunchKernelGGL(k_set_ctl, dim3(1), dim3(64), 0, s, c->ctl, 0, 1);   // count in-run rebuilds only
+
+    const int gf = c->grid_force(256 / c->tpp);
+    auto forces_and_step = [&](int mode, int32_t *clear, int32_t *set, double *h) {
+        ForceArgs a = force_args(c, p);
+        a.mode = mode;
+        a.cdt = 0.5 * dt / mass;
+        a.dt = dt;
+        a.mass = mass;
+        a.thr2 = (0.5 * c->skin) * (0.5 * c->skin);
+        a.flag_clear = clear;
+        a.flag_set = set;
+        if (h != nullptr) {
+            a.outE = h;
+            a.outK = h + 1;
+            a.outW = h + 2;
+        }
+        if (p->kind == MD_POT_LJ && half) {
+            ForceArgs f = a;
+            f.mode = 0;
+            f.force = c->force;
+            f.outK = nullptr;
+            f.flag_clear = nullptr;
+            f.flag_set = nullptr;
+            f.outE = mode >= 2 ? a.outE : nullptr;
+            f.outW = mode >= 2 ? a.outW : nullptr;
+            f.done = &c->ctl->done[1];
+            f.partial = c->partial + (size_t)c->max_grid() * 4;
+            launch_lj_half(s, gf, c->tpp, mixed, f);
+            ForceArgs g = a;
+            g.outE = nullptr;
+            g.outW = nullptr;
+            g.outK = mode >= 2 ? a.outK : nullptr;
+            g.done = &c->ctl->done[2];
+            g.partial = c->partial + (size_t)c->max_grid() * 8;
+            launch_integrate(s, ga, g);
+        } else if (p->kind == MD_POT_LJ) {
+            if (mode == 1) a.outE = a.outK = a.outW = nullptr;
+            launch_lj_full(s, gf, c->tpp, mixed, a);
+        } else {
+            if (mode == 1) a.outE = a.outK = a.outW = nullptr;
+            launch_eam_density(s, gf, c->tpp, mixed, a);
+            launch_eam_force(s, gf, c->tpp, mixed, a);
+        }
+    };
+
+    if (half) launch_zero(s, ga, c->force, 3 * c->n);
+    // F(x0), first half kick and drift; requests a rebuild for step 1 if needed
+    forces_and_step(1, &c->ctl->rebuild[0], &c->ctl->rebuild[1], nullptr);
+    c->cur = 1 - c->cur;
+    for (int32_t st = 1; st <= n_steps; st++) {
+        int32_t *pred = &c->ctl->rebuild[st & 1];
+        sort_into_tmp(c, pred, true, s);
+        ListArgs la = list_args(c, pred, c->pos_t, half);
+        la.vel_src = c->vel_t;
+        la.id_src = c->id_t;
+        la.pos_dst = c->pos[c->cur];
+        la.vel_dst = c->vel;
+        la.id_dst = c->id;
+        la.xref = c->xref;
+        launch_build_list(s, c->grid_cells(4, 3), la);
+        const int mode = st < n_steps ? 2 : 3;
+        forces_and_step(mode, pred, &c->ctl->rebuild[(st + 1) & 1],
+                        hist != nullptr ? hist + 3 * (int64_t)(st - 1) : nullptr);
+        if (mode == 2) c->cur = 1 - c->cur;
+    }
+    launch_pos_to_user(s, ga, c->n, c->R, c->reps, c->rep_of, c->id, c->pos[c->cur], pos);
+    launch_to_user(s, ga, c->n, c->id, c->vel, vel);
+    launch_to_user(s, ga, c->n, c->id, c->force, forces);
+    if (rebuilds != nullptr) hipLaunchKernelGGL(k_copy_int, dim3(1), dim3(64), 0, s, &c->ctl->nrebuild, rebuilds);
+    return check_hip(c, "md_verlet_step");
+}
+
+int md_force_vjp(md_ctx *c, const md_potential *p, int32_t precision, const double *pos,
+                 const double *u, const double *vE, double *g_pos, double *g_params, void *stream)
+{
+    if (c == nullptr) return MD_ERR_ARG;
+    if (u == nullptr) return fail(c, MD_ERR_ARG, "u_forces is null");
+    if (precision != MD_FP64 && precision != MD_MIXED) return fail(c, MD_ERR_ARG, "unknown precision");
+    if (!c->have_list) return fail(c, MD_ERR_STATE, "md_build_neighbor_list first");
+    if (c->list_kind != MD_LIST_FULL) return fail(c, MD_ERR_STATE, "the adjoint needs a full list");
+    int rcode = check_pot(c, p);
+    if (rcode != MD_OK) return rcode;
+    hipStream_t s = (hipStream_t)stream;
+    c->last = s;
+    if ((rcode = stage_tables(c, p, s)) != MD_OK) return rcode;
+    const int ga = c->grid_atoms(256);
+    if (pos != nullptr)
+        hipLaunchKernelGGL(k_pos_from_user, dim3(ga), dim3(256), 0, s, c->n, c->reps, c->rep_of, c->id,
+                           pos, c->xref, c->pos[c->cur]);
+    launch_from_user(s, ga, c->n, c->id, u, c->u_s);
+    VjpArgs v{};
+    v.f = force_args(c, p);
+    v.f.done = &c->ctl->done[3];
+    v.u = c->u_s;
+    v.vE = vE != nullptr ? vE : c->zeros_R;
+    v.gx = c->gx_s;
+    v.gpart = c->partial + (size_t)c->max_grid() * 12;
+    v.rdot = c->rdot;
+    v.fpp = c->fpp;
+    const int gf = c->grid_force(256 / c->tpp);
+    if (p->kind == MD_POT_LJ) {
+        v.gout = g_params;
+        launch_lj_vjp(s, gf, c->tpp, false, v);
+    } else {
+        v.gtab = g_params;
+        if (g_params != nullptr) {
+            int64_t total = 4 * (int64_t)(p->phi.n_knots - 1) + 4 * (int64_t)(p->rho.n_knots - 1) +
+                            4 * (int64_t)(p->embed.n_knots - 1);
+            launch_zero(s, 64, g_params, total);
+        }
+        launch_eam_vjp_a(s, gf, c->tpp, false, v);
+        launch_eam_vjp_b(s, gf, c->tpp, false, v);
+        if (g_params != nullptr) launch_eam_vjp_embed(s, ga, v);
+    }
+    if (g_pos != nullptr) launch_to_user(s, ga, c->n, c->id, c->gx_s, g_pos);
+    return check_hip(c, "md_force_vjp");
+}
+
+int md_get_status(md_ctx *c, int32_t *flags, int64_t *required)
+{
+    if (c == nullptr) return MD_ERR_ARG;
+    if (hipStreamSynchronize(c->last) != hipSuccess) return fail(c, MD_ERR_HIP, "synchronise");
+    DevCtl h{};
+    if (hipMemcpy(&h, c->ctl, sizeof(DevCtl), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(c, MD_ERR_HIP, "status readback");
+    if (h.err & MD_FLAG_OVERFLOW) c->need_M = std::max<int64_t>(c->need_M, (int64_t)ceil(1.25 * h.max_cnt));
+    if (flags) *flags = h.err;
+    if (required) *required = std::max<int64_t>(c->M, c->need_M);
+    if (h.err != 0) {
+        int32_t zero = 0;
+        if (hipMemcpy(&c->ctl->err, &zero, sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
+            return fail(c, MD_ERR_HIP, "status clear");
+    }
+    if (h.err & MD_FLAG_OVERFLOW) return fail(c, MD_ERR_CAPACITY, "neighbour list overflow");
+    if (h.err & MD_FLAG_NONFINITE) return fail(c, MD_ERR_NONFINITE, "non-finite force");
+    return MD_OK;
+}
+
+int64_t md_get_neighbor_list(md_ctx *c, int64_t *start, int32_t *nbr, int64_t capacity)
+{
+    if (c == nullptr || start == nullptr) return MD_ERR_ARG;
+    if (!c->have_list) return fail(c, MD_ERR_STATE, "no list");
+    if (hipStreamSynchronize(c->last) != hipSuccess) return fail(c, MD_ERR_HIP, "synchronise");
+    const int64_t n = c->n;
+    std::vector<int32_t> cnt(n), id(n);
+    std::vector<uint32_t> rows((size_t)(n * c->M));
+    if (hipMemcpy(cnt.data(), c->cnt, sizeof(int32_t) * n, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(id.data(), c->id, sizeof(int32_t) * n, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(rows.data(), c->nbr, sizeof(uint32_t) * rows.size(), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(c, MD_ERR_HIP, "list readback");
+    std::vector<int64_t> len(n, 0);
+    for (int64_t i = 0; i < n; i++) len[id[i]] = std::min(cnt[i], c->M);
+    start[0] = 0;
+    for (int64_t u = 0; u < n; u++) start[u + 1] = start[u] + len[u];
+    const int64_t total = start[n];
+    if (nbr == nullptr || total > capacity) return total;
+    for (int64_t i = 0; i < n; i++) {
+        const int64_t u = id[i];
+        for (int64_t k = 0; k < len[u]; k++)
+            nbr[start[u] + k] = id[rows[(size_t)(i * c->M + k)] & MD_IDX_MASK];
+    }
+    return total;
+}
+
+int md_get_cells(md_ctx *c, int32_t *cell_start, int32_t *order, int64_t *ncells)
+{
+    if (c == nullptr) return MD_ERR_ARG;
+    if (!c->have_cells) return fail(c, MD_ERR_STATE, "no cells");
+    if (ncells) *ncells = c->C;
+    if (hipStreamSynchronize(c->last) != hipSuccess) return fail(c, MD_ERR_HIP, "synchronise");
+    if (cell_start && hipMemcpy(cell_start, c->start, sizeof(int32_t) * (c->C + 1), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(c, MD_ERR_HIP, "cells readback");
+    if (order && hipMemcpy(order, c->id, sizeof(int32_t) * c->n, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(c, MD_ERR_HIP, "order readback");
+    return MD_OK;
+}
+
+int md_set_tuning(md_ctx *c, int32_t key, int32_t value)
+{
+    if (c == nullptr) return MD_ERR_ARG;
+    if (key == 0 && (value == 4 || value == 8 || value == 16 || value == 32)) {
+        c->tpp = value;
+        return MD_OK;
+    }
+    if (key == 1 && value >= 1 && value <= 16) {
+        c->wgpc = value;
+        return MD_OK;
+    }
+    if (key == 2 && value >= 1 && value <= 4096) {
+        // fixed per-atom list capacity (tests of the overflow path force a small one)
+        if (hipDeviceSynchronize() != hipSuccess) return fail(c, MD_ERR_HIP, "synchronise");
+        if (!dalloc(&c->nbr, (size_t)value * (size_t)c->n)) return fail(c, MD_ERR_HIP, "list: out of device memory");
+        c->M = value;
+        c->need_M = 0;
+        c->have_list = false;
+        return MD_OK;
+    }
+    return fail(c, MD_ERR_ARG, "tuning: key 0 in {4, 8, 16, 32}, key 1 in 1..16, key 2 in 1..4096");
+}
+
+const char *md_last_error(md_ctx *c)
+{
+    return c == nullptr ? "null context" : c->err.c_str();
+}
+
+} // extern "C"

@@ -1,0 +1,642 @@
+// md_force.hip -- LJ and FS-EAM forces over Verlet lists, fused with velocity Verlet.
+//
+// Work decomposition: TPP consecutive lanes own one atom i of the cell-sorted
+// order and stride through its list row; their partial sums are combined by a
+// butterfly inside the group.  With the full list every pair appears in both
+// rows and each atom's force is written only by its own lane group, so no
+// particle is updated by two workers at once -- the invariant the cell-task
+// schedule of Sec. II.A/II.B exists to guarantee, here obtained by ownership
+// instead of by a dependent schedule.  The half-list kernel is the Newton-3
+// alternative (Sec. II.D.3) with binary64 atomics on the partner atom.
+//
+// Precision (MIXED = false: all binary64):
+//   displacement, image shift, r2 and the r2 < rc^2 test are always binary64
+//   (the pair set of a force call equals the exhaustive one); with MIXED the
+//   pair scalar (LJ 24 eps (2 q12 - q6)/r2 and V; EAM table polynomials) is
+//   evaluated in binary32, then projected and accumulated in binary64.
+//
+// Integration (mode): after the group's forces are known, lane 0 of the group
+// applies the velocity-Verlet pieces of this atom (the per-particle loop of
+// Sec. II.A) -- the closing half kick of the current step, the kinetic energy,
+// the opening half kick and drift of the next -- and flags a rebuild when the
+// displacement since the last build exceeds skin/2.  Drifted positions go to a
+// second buffer because other groups still gather the current ones.
+#include <math.h>
+
+#include "md_internal.h"
+#include "md_reduce.h"
+
+namespace {
+
+__device__ __forceinline__ void apply_image(uint32_t e, double Lx, double Ly, double Lz,
+                                            double &dx, double &dy, double &dz)
+{
+    const uint32_t c = e >> MD_IDX_BITS;
+    if (c & 1u) dx = dx + Lx;
+    if (c & 2u) dx = dx - Lx;
+    if (c & 4u) dy = dy + Ly;
+    if (c & 8u) dy = dy - Ly;
+    if (c & 16u) dz = dz + Lz;
+    if (c & 32u) dz = dz - Lz;
+}
+
+__device__ __forceinline__ void atom_box(const ForceArgs &a, int64_t i, double &Lx, double &Ly,
+                                         double &Lz)
+{
+    if (a.R > 1) {
+        const RepDesc &r = a.reps[a.rep_of[i]];
+        Lx = r.L[0]; Ly = r.L[1]; Lz = r.L[2];
+    } else {
+        Lx = a.rep0.L[0]; Ly = a.rep0.L[1]; Lz = a.rep0.L[2];
+    }
+}
+
+template <int TPP>
+__device__ __forceinline__ double group_sum(double v)
+{
+    for (int o = TPP / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ int seg(double u, int nk)
+{
+    int k = (int)floor(u);
+    k = k > nk - 2 ? nk - 2 : k;
+    return k < 0 ? 0 : k;
+}
+
+// value and d/du of a binary64 table row at u = (x - x0)/h
+__device__ __forceinline__ void spl64(const double *tab, double u, int nk, double &f, double &fu)
+{
+    const int k = seg(u, nk);
+    const double t = u - (double)k;
+    const double4 c = reinterpret_cast<const double4 *>(tab)[k];
+    f = c.x + t * (c.y + t * (c.z + t * c.w));
+    fu = c.y + t * (2.0 * c.z + 3.0 * t * c.w);
+}
+
+__device__ __forceinline__ void spl32(const float *tab, double u, int nk, float &f, float &fu)
+{
+    const int k = seg(u, nk);
+    const float t = (float)(u - (double)k);
+    const float4 c = reinterpret_cast<const float4 *>(tab)[k];
+    f = c.x + t * (c.y + t * (c.z + t * c.w));
+    fu = c.y + t * (2.0f * c.z + 3.0f * t * c.w);
+}
+
+// embedding function F(rho), F'(rho), binary64, linear beyond the last knot
+__device__ __forceinline__ void embed64(const ForceArgs &a, double rho, double &F, double &Fp)
+{
+    const int nk = a.nk[2];
+    const double u = (rho - a.x0[2]) * a.inv_h[2];
+    const double4 *rows = reinterpret_cast<const double4 *>(a.tab[2]);
+    if (u > (double)(nk - 1)) {
+        const double4 c = rows[nk - 2];
+        const double fend = ((c.x + c.y) + c.z) + c.w;
+        const double sl = (c.y + 2.0 * c.z) + 3.0 * c.w;
+        F = fend + sl * (u - (double)(nk - 1));
+        Fp = sl * a.inv_h[2];
+        return;
+    }
+    double fu;
+    spl64(a.tab[2], u, nk, F, fu);
+    Fp = fu * a.inv_h[2];
+}
+
+// Per-atom epilogue run by lane 0 of the group.
+__device__ __forceinline__ void finish_atom(const ForceArgs &a, int64_t i, const double4 &xi,
+                                            double fx, double fy, double fz, double e, double w,
+                                            double &accE, double &accW, double &accK,
+                                            bool write_f = true)
+{
+    const int64_t n = a.n;
+    if (!(isfinite(fx) && isfinite(fy) && isfinite(fz))) atomicOr(&a.ctl->err, MD_FLAG_NONFINITE);
+    if (a.mode == 0) {
+        if (write_f && a.force != nullptr) {
+            a.force[i] = fx;
+            a.force[n + i] = fy;
+            a.force[2 * n + i] = fz;
+        }
+        if (a.eatom != nullptr) {
+            a.eatom[i] = e;
+            a.watom[i] = w;
+        }
+        accE += e;
+        accW += w;
+        return;
+    }
+    const double c = a.cdt;
+    double vx = a.vel[i], vy = a.vel[n + i], vz = a.vel[2 * n + i];
+    if (a.mode >= 2) {
+        vx = vx + c * fx;
+        vy = vy + c * fy;
+        vz = vz + c * fz;
+        accK += (vx * vx + vy * vy) + vz * vz;
+        accE += e;
+        accW += w;
+    }
+    if (a.mode <= 2) {
+        vx = vx + c * fx;
+        vy = vy + c * fy;
+        vz = vz + c * fz;
+        const double4 xn = make_double4(xi.x + a.dt * vx, xi.y + a.dt * vy, xi.z + a.dt * vz, 0.0);
+        a.pos_next[i] = xn;
+        const double4 xr = a.xref[i];
+        const double dx = xn.x - xr.x, dy = xn.y - xr.y, dz = xn.z - xr.z;
+        if ((dx * dx + dy * dy) + dz * dz > a.thr2) *a.flag_set = 1;
+    }
+    a.vel[i] = vx;
+    a.vel[n + i] = vy;
+    a.vel[2 * n + i] = vz;
+    if (a.mode == 3 && write_f && a.force != nullptr) {
+        a.force[i] = fx;
+        a.force[n + i] = fy;
+        a.force[2 * n + i] = fz;
+    }
+}
+
+__device__ __forceinline__ void finish_block(const ForceArgs &a, double accE, double accW,
+                                             double accK, double *lds)
+{
+    if (a.outE == nullptr && a.outK == nullptr && a.outW == nullptr) return;
+    double v[4] = {accE, accW, accK, 0.0};
+    if (mdred::last_block_sum4(v, a.partial, a.done, lds) && threadIdx.x == 0) {
+        if (a.outE) *a.outE = v[0];
+        if (a.outW) *a.outW = v[1];
+        if (a.outK) *a.outK = 0.5 * a.mass * v[2];
+    }
+}
+
+// ---------------------------------------------------------------- LJ, full list
+template <int TPP, bool MIXED>
+__global__ __launch_bounds__(256) void k_lj_full(ForceArgs a)
+{
+    __shared__ double lds[16];
+    constexpr int APB = 256 / TPP;
+    const int sub = threadIdx.x % TPP, grp = threadIdx.x / TPP;
+    if (a.flag_clear != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *a.flag_clear = 0;
+    const double eps = a.lj[0], sig = a.lj[1];
+    const double s2 = sig * sig, e4 = 4.0 * eps, e24 = 24.0 * eps;
+    const float s2f = (float)s2, e4f = (float)e4, e24f = (float)e24;
+    double accE = 0.0, accW = 0.0, accK = 0.0;
+    const int64_t ntiles = (a.n + APB - 1) / APB;
+    const ItemRange it = xcd_items(ntiles, 1, 0);
+    for (int64_t t = it.first; t < it.end; t += it.stride) {
+        const int64_t i = t * APB + grp;
+        const bool valid = i < a.n;
+        double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0, w = 0.0;
+        double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (valid) {
+            xi = a.pos[i];
+            double Lx, Ly, Lz;
+            atom_box(a, i, Lx, Ly, Lz);
+            const int32_t m = a.cnt[i] < a.M ? a.cnt[i] : a.M;
+            const uint32_t *row = a.nbr + i * (int64_t)a.M;
+            for (int32_t k = sub; k < m; k += TPP) {
+                const uint32_t en = row[k];
+                const double4 xj = a.pos[en & MD_IDX_MASK];
+                double dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+                if (en >> MD_IDX_BITS) apply_image(en, Lx, Ly, Lz, dx, dy, dz);
+                const double r2 = (dx * dx + dy * dy) + dz * dz;
+                if (r2 < a.rc2) {
+                    if (MIXED) {
+                        const float ir2 = __builtin_amdgcn_rcpf((float)r2);
+                        const float q2 = s2f * ir2;
+                        const float q6 = q2 * q2 * q2;
+                        const float q12 = q6 * q6;
+                        const float fs = e24f * (2.0f * q12 - q6) * ir2;
+                        const double fsd = (double)fs;
+                        fx = fma(fsd, dx, fx);
+                        fy = fma(fsd, dy, fy);
+                        fz = fma(fsd, dz, fz);
+                        e += (double)(e4f * (q12 - q6));
+                        w += fsd * r2;
+                    } else {
+                        const double ir2 = 1.0 / r2;
+                        const double q2 = s2 * ir2;
+                        const double q6 = q2 * q2 * q2;
+                        const double q12 = q6 * q6;
+                        const double fs = e24 * (2.0 * q12 - q6) * ir2;
+                        fx = fma(fs, dx, fx);
+                        fy = fma(fs, dy, fy);
+                        fz = fma(fs, dz, fz);
+                        e += e4 * (q12 - q6);
+                        w += fs * r2;
+                    }
+                }
+            }
+        }
+        fx = group_sum<TPP>(fx);
+        fy = group_sum<TPP>(fy);
+        fz = group_sum<TPP>(fz);
+        e = group_sum<TPP>(e);
+        w = group_sum<TPP>(w);
+        if (valid && sub == 0) finish_atom(a, i, xi, fx, fy, fz, 0.5 * e, 0.5 * w, accE, accW, accK);
+    }
+    finish_block(a, accE, accW, accK, lds);
+}
+
+// ---------------------------------------------------------------- LJ, half list + atomics
+template <int TPP, bool MIXED>
+__global__ __launch_bounds__(256) void k_lj_half(ForceArgs a)
+{
+    __shared__ double lds[16];
+    constexpr int APB = 256 / TPP;
+    const int sub = threadIdx.x % TPP, grp = threadIdx.x / TPP;
+    const double eps = a.lj[0], sig = a.lj[1];
+    const double s2 = sig * sig, e4 = 4.0 * eps, e24 = 24.0 * eps;
+    const float s2f = (float)s2, e4f = (float)e4, e24f = (float)e24;
+    const int64_t n = a.n;
+    double accE = 0.0, accW = 0.0;
+    const int64_t ntiles = (n + APB - 1) / APB;
+    const ItemRange it = xcd_items(ntiles, 1, 0);
+    for (int64_t t = it.first; t < it.end; t += it.stride) {
+        const int64_t i = t * APB + grp;
+        const bool valid = i < n;
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        if (valid) {
+            const double4 xi = a.pos[i];
+            double Lx, Ly, Lz;
+            atom_box(a, i, Lx, Ly, Lz);
+            const int32_t m = a.cnt[i] < a.M ? a.cnt[i] : a.M;
+            const uint32_t *row = a.nbr + i * (int64_t)a.M;
+            for (int32_t k = sub; k < m; k += TPP) {
+                const uint32_t en = row[k];
+                const int64_t j = en & MD_IDX_MASK;
+                const double4 xj = a.pos[j];
+                double dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+                if (en >> MD_IDX_BITS) apply_image(en, Lx, Ly, Lz, dx, dy, dz);
+                const double r2 = (dx * dx + dy * dy) + dz * dz;
+                if (r2 < a.rc2) {
+                    double fs, V;
+                    if (MIXED) {
+                        const float ir2 = __builtin_amdgcn_rcpf((float)r2);
+                        const float q2 = s2f * ir2;
+                        const float q6 = q2 * q2 * q2;
+                        const float q12 = q6 * q6;
+                        fs = (double)(e24f * (2.0f * q12 - q6) * ir2);
+                        V = (double)(e4f * (q12 - q6));
+                    } else {
+                        const double ir2 = 1.0 / r2;
+                        const double q2 = s2 * ir2;
+                        const double q6 = q2 * q2 * q2;
+                        const double q12 = q6 * q6;
+                        fs = e24 * (2.0 * q12 - q6) * ir2;
+                        V = e4 * (q12 - q6);
+                    }
+                    const double px = fs * dx, py = fs * dy, pz = fs * dz;
+                    fx += px;
+                    fy += py;
+                    fz += pz;
+                    atomicAdd(&a.force[j], -px);
+                    atomicAdd(&a.force[n + j], -py);
+                    atomicAdd(&a.force[2 * n + j], -pz);
+                    accE += V;
+                    accW += fs * r2;
+                }
+            }
+        }
+        fx = group_sum<TPP>(fx);
+        fy = group_sum<TPP>(fy);
+        fz = group_sum<TPP>(fz);
+        if (valid && sub == 0) {
+            atomicAdd(&a.force[i], fx);
+            atomicAdd(&a.force[n + i], fy);
+            atomicAdd(&a.force[2 * n + i], fz);
+        }
+    }
+    double v[4] = {accE, accW, 0.0, 0.0};
+    if (a.outE == nullptr && a.outW == nullptr) return;
+    if (mdred::last_block_sum4(v, a.partial, a.done, lds) && threadIdx.x == 0) {
+        if (a.outE) *a.outE = v[0];
+        if (a.outW) *a.outW = v[1];
+    }
+}
+
+// velocity-Verlet pieces for forces already in a.force (half-list path); the
+// consumed forces are cleared for the next atomic accumulation
+__global__ __launch_bounds__(256) void k_integrate(ForceArgs a)
+{
+    __shared__ double lds[16];
+    if (a.flag_clear != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *a.flag_clear = 0;
+    const int64_t n = a.n;
+    double accE = 0.0, accW = 0.0, accK = 0.0;
+    const int64_t ntiles = (n + 255) / 256;
+    const ItemRange it = xcd_items(ntiles, 1, 0);
+    for (int64_t t = it.first; t < it.end; t += it.stride) {
+        const int64_t i = t * 256 + threadIdx.x;
+        if (i >= n) continue;
+        const double fx = a.force[i], fy = a.force[n + i], fz = a.force[2 * n + i];
+        const double4 xi = a.pos[i];
+        finish_atom(a, i, xi, fx, fy, fz, 0.0, 0.0, accE, accW, accK, false);
+        if (a.mode != 3) {
+            a.force[i] = 0.0;
+            a.force[n + i] = 0.0;
+            a.force[2 * n + i] = 0.0;
+        }
+    }
+    double v[4] = {0.0, 0.0, accK, 0.0};
+    if (a.outK == nullptr) return;
+    if (mdred::last_block_sum4(v, a.partial, a.done, lds) && threadIdx.x == 0)
+        *a.outK = 0.5 * a.mass * v[2];
+}
+
+// ---------------------------------------------------------------- EAM pass 1: density
+template <int TPP, bool MIXED>
+__global__ __launch_bounds__(256) void k_eam_density(ForceArgs a)
+{
+    constexpr int APB = 256 / TPP;
+    const int sub = threadIdx.x % TPP, grp = threadIdx.x / TPP;
+    const int nk = a.nk[1];
+    const double x0 = a.x0[1], ih = a.inv_h[1];
+    const int64_t ntiles = (a.n + APB - 1) / APB;
+    const ItemRange it = xcd_items(ntiles, 1, 0);
+    for (int64_t t = it.first; t < it.end; t += it.stride) {
+        const int64_t i = t * APB + grp;
+        const bool valid = i < a.n;
+        double rho = 0.0;
+        if (valid) {
+            const double4 xi = a.pos[i];
+            double Lx, Ly, Lz;
+            atom_box(a, i, Lx, Ly, Lz);
+            const int32_t m = a.cnt[i] < a.M ? a.cnt[i] : a.M;
+            const uint32_t *row = a.nbr + i * (int64_t)a.M;
+            for (int32_t k = sub; k < m; k += TPP) {
+                const uint32_t en = row[k];
+                const double4 xj = a.pos[en & MD_IDX_MASK];
+                double dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+                if (en >> MD_IDX_BITS) apply_image(en, Lx, Ly, Lz, dx, dy, dz);
+                const double r2 = (dx * dx + dy * dy) + dz * dz;
+                if (r2 < a.rrho2) {
+                    const double u = (sqrt(r2) - x0) * ih;
+                    if (MIXED) {
+                        float f, fu;
+                        spl32(a.tabf[1], u, nk, f, fu);
+                        rho += (double)f;
+                    } else {
+                        double f, fu;
+                        spl64(a.tab[1], u, nk, f, fu);
+                        rho += f;
+                    }
+                }
+            }
+        }
+        rho = group_sum<TPP>(rho);
+        if (valid && sub == 0) {
+            double F, Fp;
+            embed64(a, rho, F, Fp);
+            a.rho[i] = rho;
+            a.fp[i] = Fp;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- EAM pass 2: forces
+template <int TPP, bool MIXED>
+__global__ __launch_bounds__(256) void k_eam_force(ForceArgs a)
+{
+    __shared__ double lds[16];
+    constexpr int APB = 256 / TPP;
+    const int sub = threadIdx.x % TPP, grp = threadIdx.x / TPP;
+    if (a.flag_clear != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *a.flag_clear = 0;
+    const int nkp = a.nk[0], nkr = a.nk[1];
+    const double x0p = a.x0[0], ihp = a.inv_h[0], x0r = a.x0[1], ihr = a.inv_h[1];
+    double accE = 0.0, accW = 0.0, accK = 0.0;
+    const int64_t ntiles = (a.n + APB - 1) / APB;
+    const ItemRange it = xcd_items(ntiles, 1, 0);
+    for (int64_t t = it.first; t < it.end; t += it.stride) {
+        const int64_t i = t * APB + grp;
+        const bool valid = i < a.n;
+        double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0, w = 0.0;
+        double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (valid) {
+            xi = a.pos[i];
+            const double fpi = a.fp[i];
+            double Lx, Ly, Lz;
+            atom_box(a, i, Lx, Ly, Lz);
+            const int32_t m = a.cnt[i] < a.M ? a.cnt[i] : a.M;
+            const uint32_t *row = a.nbr + i * (int64_t)a.M;
+            for (int32_t k = sub; k < m; k += TPP) {
+                const uint32_t en = row[k];
+                const int64_t j = en & MD_IDX_MASK;
+                const double4 xj = a.pos[j];
+                double dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+                if (en >> MD_IDX_BITS) apply_image(en, Lx, Ly, Lz, dx, dy, dz);
+                const double r2 = (dx * dx + dy * dy) + dz * dz;
+                const bool in_phi = r2 < a.rphi2, in_rho = r2 < a.rrho2;
+                if (in_phi || in_rho) {
+                    const double r = sqrt(r2);
+                    const double ir = 1.0 / r;
+                    double g, ep;
+                    if (MIXED) {
+                        float gf = 0.0f, epf = 0.0f;
+                        if (in_phi) {
+                            float f, fu;
+                            spl32(a.tabf[0], (r - x0p) * ihp, nkp, f, fu);
+                            gf += fu * (float)ihp;
+                            epf += f;
+                        }
+                        if (in_rho) {
+                            float f, fu;
+                            spl32(a.tabf[1], (r - x0r) * ihr, nkr, f, fu);
+                            gf += (float)(fpi + a.fp[j]) * fu * (float)ihr;
+                        }
+                        g = (double)gf;
+                        ep = (double)epf;
+                    } else {
+                        g = 0.0;
+                        ep = 0.0;
+                        if (in_phi) {
+                            double f, fu;
+                            spl64(a.tab[0], (r - x0p) * ihp, nkp, f, fu);
+                            g += fu * ihp;
+                            ep += f;
+                        }
+                        if (in_rho) {
+                            double f, fu;
+                            spl64(a.tab[1], (r - x0r) * ihr, nkr, f, fu);
+                            g += (fpi + a.fp[j]) * (fu * ihr);
+                        }
+                    }
+                    const double gr = g * ir;
+                    fx = fma(-gr, dx, fx);
+                    fy = fma(-gr, dy, fy);
+                    fz = fma(-gr, dz, fz);
+                    e += ep;
+                    w -= g * r;
+                }
+            }
+        }
+        fx = group_sum<TPP>(fx);
+        fy = group_sum<TPP>(fy);
+        fz = group_sum<TPP>(fz);
+        e = group_sum<TPP>(e);
+        w = group_sum<TPP>(w);
+        if (valid && sub == 0) {
+            double F, Fp;
+            embed64(a, a.rho[i], F, Fp);
+            finish_atom(a, i, xi, fx, fy, fz, F + 0.5 * e, 0.5 * w, accE, accW, accK);
+        }
+    }
+    finish_block(a, accE, accW, accK, lds);
+}
+
+// ---------------------------------------------------------------- small kernels
+__global__ void k_zero(double *p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+__global__ void k_to_user(int64_t n, const int32_t *__restrict__ id, const double *__restrict__ src,
+                          double *__restrict__ dst)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t u = id[i];
+        dst[u] = src[i];
+        dst[n + u] = src[n + i];
+        dst[2 * n + u] = src[2 * n + i];
+    }
+}
+
+__global__ void k_from_user(int64_t n, const int32_t *__restrict__ id, const double *__restrict__ src,
+                            double *__restrict__ dst)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t u = id[i];
+        dst[i] = src[u];
+        dst[n + i] = src[n + u];
+        dst[2 * n + i] = src[2 * n + u];
+    }
+}
+
+__device__ __forceinline__ double wrap1(double x, double L)
+{
+    double w = x - L * floor(x / L);
+    if (w >= L) w = w - L;
+    if (w < 0.0) w = 0.0;
+    return w;
+}
+
+__global__ void k_pos_to_user(int64_t n, const RepDesc *__restrict__ reps,
+                              const int32_t *__restrict__ rep_of, const int32_t *__restrict__ id,
+                              const double4 *__restrict__ pos, double *__restrict__ dst)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const RepDesc &r = reps[rep_of[i]];
+        const double4 p = pos[i];
+        const int64_t u = id[i];
+        dst[u] = wrap1(p.x, r.L[0]);
+        dst[n + u] = wrap1(p.y, r.L[1]);
+        dst[2 * n + u] = wrap1(p.z, r.L[2]);
+    }
+}
+
+__global__ void k_tables_f32(const double *__restrict__ src, float *__restrict__ dst, int64_t m)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = (float)src[i];
+}
+
+// per-replica energy and virial in a fixed order: one workgroup per replica
+__global__ __launch_bounds__(256) void k_replica_sums(const RepDesc *__restrict__ reps,
+                                                      const double *__restrict__ eatom,
+                                                      const double *__restrict__ watom,
+                                                      double *energy, double *virial)
+{
+    __shared__ double lds[16];
+    const RepDesc &r = reps[blockIdx.x];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = r.atom_off + threadIdx.x; i < r.atom_end; i += blockDim.x) {
+        v[0] += eatom[i];
+        v[1] += watom[i];
+    }
+    mdred::block_sum4(v, lds);
+    if (threadIdx.x == 0) {
+        if (energy) energy[blockIdx.x] = v[0];
+        if (virial) virial[blockIdx.x] = v[1];
+    }
+}
+
+#define MD_TPP_SWITCH(KERNEL, MIXED_, ...)                                                   \
+    switch (tpp) {                                                                           \
+    case 4: hipLaunchKernelGGL((KERNEL<4, MIXED_>), __VA_ARGS__); break;                      \
+    case 8: hipLaunchKernelGGL((KERNEL<8, MIXED_>), __VA_ARGS__); break;                      \
+    case 16: hipLaunchKernelGGL((KERNEL<16, MIXED_>), __VA_ARGS__); break;                    \
+    default: hipLaunchKernelGGL((KERNEL<32, MIXED_>), __VA_ARGS__); break;                    \
+    }
+
+#define MD_LAUNCH_TPP(KERNEL)                                                                \
+    if (mixed) {                                                                             \
+        MD_TPP_SWITCH(KERNEL, true, dim3(grid), dim3(256), 0, s, a)                          \
+    } else {                                                                                 \
+        MD_TPP_SWITCH(KERNEL, false, dim3(grid), dim3(256), 0, s, a)                         \
+    }
+
+} // namespace
+
+void launch_lj_full(hipStream_t s, int grid, int tpp, bool mixed, const ForceArgs &a)
+{
+    MD_LAUNCH_TPP(k_lj_full)
+}
+
+void launch_lj_half(hipStream_t s, int grid, int tpp, bool mixed, const ForceArgs &a)
+{
+    MD_LAUNCH_TPP(k_lj_half)
+}
+
+void launch_eam_density(hipStream_t s, int grid, int tpp, bool mixed, const ForceArgs &a)
+{
+    MD_LAUNCH_TPP(k_eam_density)
+}
+
+void launch_eam_force(hipStream_t s, int grid, int tpp, bool mixed, const ForceArgs &a)
+{
+    MD_LAUNCH_TPP(k_eam_force)
+}
+
+void launch_integrate(hipStream_t s, int grid, const ForceArgs &a)
+{
+    hipLaunchKernelGGL(k_integrate, dim3(grid), dim3(256), 0, s, a);
+}
+
+void launch_zero(hipStream_t s, int grid, double *p, int64_t n)
+{
+    hipLaunchKernelGGL(k_zero, dim3(grid), dim3(256), 0, s, p, n);
+}
+
+void launch_replica_sums(hipStream_t s, int32_t R, const RepDesc *reps, const double *eatom,
+                         const double *watom, double *energy, double *virial)
+{
+    hipLaunchKernelGGL(k_replica_sums, dim3(R), dim3(256), 0, s, reps, eatom, watom, energy, virial);
+}
+
+void launch_to_user(hipStream_t s, int grid, int64_t n, const int32_t *id, const double *src3,
+                    double *dst_user)
+{
+    hipLaunchKernelGGL(k_to_user, dim3(grid), dim3(256), 0, s, n, id, src3, dst_user);
+}
+
+void launch_from_user(hipStream_t s, int grid, int64_t n, const int32_t *id,
+                      const double *src_user, double *dst3)
+{
+    hipLaunchKernelGGL(k_from_user, dim3(grid), dim3(256), 0, s, n, id, src_user, dst3);
+}
+
+void launch_pos_to_user(hipStream_t s, int grid, int64_t n, int32_t R, const RepDesc *reps,
+                        const int32_t *rep_of, const int32_t *id, const double4 *pos,
+                        double *dst_user)
+{
+    (void)R;
+    hipLaunchKernelGGL(k_pos_to_user, dim3(grid), dim3(256), 0, s, n, reps, rep_of, id, pos, dst_user);
+}
+
+void launch_tables_f32(hipStream_t s, const double *src, float *dst, int64_t m)
+{
+    hipLaunchKernelGGL(k_tables_f32, dim3(64), dim3(256), 0, s, src, dst, m);
+}

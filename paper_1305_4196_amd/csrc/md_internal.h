@@ -1,0 +1,215 @@
+// md_internal.h -- device-side layout and kernel launchers of the MD hot path.
+//
+// Layout in HBM (all arrays in cell-sorted order unless named *_user):
+//   pos      double4[N]  x, y, z, (unused)   -- gathered by neighbour loops
+//   vel      double[3][N]                     -- streamed once per step
+//   force    double[3][N]
+//   xref     double4[N]  positions at the last list build
+//   id       int32[N]    user index of each sorted slot
+//   nbr      uint32[N][M] per-atom rows of the Verlet list (capacity M), entry =
+//            sorted index j (low 26 bits) | image code (high 6 bits, 2 per axis:
+//            01 = add L, 10 = subtract L) fixed when the list is built
+//   cnt      int32[N]    list length of each atom
+// Positions are wrapped into [0, L) when the cells are built; between builds they
+// move freely and each pair uses the image fixed at build time (exact as long as
+// no atom moves more than skin/2, which the rebuild trigger guarantees).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/md.h"
+
+#define MD_WAVE 64
+#define MD_IDX_BITS 26
+#define MD_IDX_MASK ((1u << MD_IDX_BITS) - 1u)
+#define MD_MAX_ATOMS (1ll << MD_IDX_BITS)
+
+// error bits of the sticky device word
+#define MD_FLAG_OVERFLOW 1
+#define MD_FLAG_NONFINITE 2
+
+struct RepDesc {
+    double L[3];
+    double hL[3];
+    int32_t nc[3];
+    int32_t pad;
+    int64_t cell_off;   // first global cell of this replica
+    int64_t atom_off;   // first atom (user and sorted order agree on replica ranges)
+    int64_t atom_end;
+};
+
+// Device-resident control words.
+struct DevCtl {
+    int32_t rebuild[2];   // rebuild request, indexed by step parity
+    int32_t err;          // sticky MD_FLAG_* bits
+    int32_t max_cnt;      // largest per-atom list length of the last build
+    int32_t max_cell;     // largest cell occupancy of the last build
+    int32_t nrebuild;     // rebuilds performed inside md_verlet_step
+    uint32_t done[4];     // last-block counters (one per reduction site)
+};
+
+// ---------------------------------------------------------------- launchers
+// cells
+void launch_load_user(hipStream_t s, int grid, int64_t n, const double *pos_user,
+                      const double *vel_user, double4 *pos, double *vel, int32_t *id);
+void launch_bin(hipStream_t s, int grid, const int32_t *pred, int64_t n, int32_t R,
+                const RepDesc *reps, const int32_t *rep_of, double4 *pos, int32_t *cell_of,
+                int32_t *slot, int32_t *count);
+void launch_scan(hipStream_t s, const int32_t *pred, int64_t C, int32_t *count,
+                 int32_t *start, DevCtl *ctl);
+void launch_scatter(hipStream_t s, int grid, const int32_t *pred, int64_t n,
+                    const int32_t *cell_of, const int32_t *slot, const int32_t *start,
+                    int32_t *perm);
+void launch_sort_cells(hipStream_t s, int grid, const int32_t *pred, int64_t C,
+                       const int32_t *start, const int32_t *perm, const int32_t *id,
+                       const double4 *pos, const double *vel, int64_t n, double4 *pos_out,
+                       double *vel_out, int32_t *id_out);
+void launch_copy_back(hipStream_t s, int grid, const int32_t *pred, int64_t n,
+                      const double4 *pos_t, const double *vel_t, const int32_t *id_t,
+                      double4 *pos, double *vel, int32_t *id, double4 *xref);
+
+// neighbour list
+struct ListArgs {
+    const int32_t *pred;      // predicate word (build only if non-zero), may point at a constant 1
+    int64_t C;                // total cells
+    int32_t R;
+    const RepDesc *reps;
+    const int32_t *start;     // cell_start[C+1]
+    const double4 *src;       // sorted positions the list is built from
+    int64_t n;
+    uint32_t *nbr;
+    int32_t *cnt;
+    int32_t M;
+    double rl2;
+    int half;
+    // optional copy of the freshly sorted state into the working buffers
+    const double *vel_src;
+    const int32_t *id_src;
+    double4 *pos_dst;
+    double *vel_dst;
+    int32_t *id_dst;
+    double4 *xref;
+    DevCtl *ctl;
+};
+void launch_build_list(hipStream_t s, int grid, const ListArgs &a);
+
+// forces
+struct ForceArgs {
+    int64_t n;
+    int32_t R;
+    const RepDesc *reps;      // R entries (device)
+    RepDesc rep0;             // replica 0 by value (single-replica fast path)
+    const int32_t *rep_of;    // replica of each sorted atom
+    const double4 *pos;
+    double4 *pos_next;        // drift output
+    const double4 *xref;
+    double *vel;              // [3][n]
+    double *force;            // [3][n] sorted out (may be null)
+    const uint32_t *nbr;
+    const int32_t *cnt;
+    int32_t M;
+    double rc2;
+    const double *lj;         // device {eps, sigma}
+    // EAM
+    const double *tab[3];     // phi, rho, embed coefficient tables (binary64)
+    const float *tabf[3];     // binary32 copies (mixed precision)
+    int32_t nk[3];
+    double x0[3], inv_h[3];
+    double rphi2, rrho2;
+    double *rho;              // [n] density, sorted
+    double *fp;               // [n] F'(rho), sorted
+    // integration
+    int mode;                 // 0 forces only, 1 first (kick+drift), 2 middle, 3 last
+    double cdt;               // dt / (2m)
+    double dt;
+    double mass;
+    double thr2;              // (skin/2)^2
+    int32_t *flag_set;        // rebuild request for the next step (may be null)
+    int32_t *flag_clear;      // this step's request, cleared by block 0 (may be null)
+    // reductions
+    double *partial;          // [grid][4]
+    uint32_t *done;
+    double *outE;             // final sums of this launch (each may be null):
+    double *outK;             //   potential energy, kinetic energy,
+    double *outW;             //   scalar virial
+    double *eatom;            // per-atom energy (multi-replica outputs), or null
+    double *watom;            // per-atom virial, or null
+    DevCtl *ctl;
+};
+void launch_lj_full(hipStream_t s, int grid, int tpp, bool mixed, const ForceArgs &a);
+void launch_lj_half(hipStream_t s, int grid, int tpp, bool mixed, const ForceArgs &a);
+void launch_eam_density(hipStream_t s, int grid, int tpp, bool mixed, const ForceArgs &a);
+void launch_eam_force(hipStream_t s, int grid, int tpp, bool mixed, const ForceArgs &a);
+void launch_integrate(hipStream_t s, int grid, const ForceArgs &a);
+void launch_zero(hipStream_t s, int grid, double *p, int64_t n);
+void launch_replica_sums(hipStream_t s, int32_t R, const RepDesc *reps, const double *eatom,
+                         const double *watom, double *energy, double *virial);
+void launch_to_user(hipStream_t s, int grid, int64_t n, const int32_t *id, const double *src3,
+                    double *dst_user);
+void launch_pos_to_user(hipStream_t s, int grid, int64_t n, int32_t R, const RepDesc *reps,
+                        const int32_t *rep_of, const int32_t *id, const double4 *pos,
+                        double *dst_user);
+void launch_from_user(hipStream_t s, int grid, int64_t n, const int32_t *id,
+                      const double *src_user, double *dst3);
+void launch_tables_f32(hipStream_t s, const double *src, float *dst, int64_t m);
+
+// adjoint
+struct VjpArgs {
+    ForceArgs f;
+    const double *u;          // [3][n] sorted cotangent
+    const double *vE;         // [R]
+    double *gx;               // [3][n] sorted out
+    double *gpart;            // LJ: [grid][4] parameter partials
+    double *gtab;             // EAM: [3][(nk-1)*4] parameter gradient (atomics)
+    double *rdot;             // EAM pass A output
+    double *fpp;              // EAM F''
+    double *gout;             // LJ: 2 doubles out (final)
+};
+void launch_lj_vjp(hipStream_t s, int grid, int tpp, bool mixed, const VjpArgs &a);
+void launch_eam_vjp_a(hipStream_t s, int grid, int tpp, bool mixed, const VjpArgs &a);
+void launch_eam_vjp_b(hipStream_t s, int grid, int tpp, bool mixed, const VjpArgs &a);
+void launch_eam_vjp_embed(hipStream_t s, int grid, const VjpArgs &a);
+
+// ---------------------------------------------------------------- device helpers
+#ifdef __HIPCC__
+// Work item sequence of one unit (a wave or a whole block) of a persistent grid.
+// The items are split into eight contiguous ranges and workgroup b serves range
+// b % 8: workgroups are dispatched round-robin over the eight XCDs, so each XCD's
+// L2 sees one compact region of the cell-sorted data.
+struct ItemRange {
+    int64_t first, end, stride;
+};
+__device__ __forceinline__ ItemRange xcd_items(int64_t nitems, int units_per_block, int unit)
+{
+    ItemRange r;
+    const int G = gridDim.x;
+    if (G % 8 != 0) {
+        r.first = (int64_t)blockIdx.x * units_per_block + unit;
+        r.stride = (int64_t)G * units_per_block;
+        r.end = nitems;
+        return r;
+    }
+    const int x = blockIdx.x & 7, slot = blockIdx.x >> 3, G8 = G >> 3;
+    const int64_t per = (nitems + 7) / 8;
+    const int64_t lo = (int64_t)x * per;
+    r.end = lo + per < nitems ? lo + per : nitems;
+    r.first = lo + (int64_t)slot * units_per_block + unit;
+    r.stride = (int64_t)G8 * units_per_block;
+    return r;
+}
+
+// make LDS stores of this wavefront visible to its other lanes
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+#endif

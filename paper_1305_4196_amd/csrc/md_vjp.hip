@@ -1,0 +1,379 @@
+// md_vjp.hip -- hand-written adjoints of forces and energy.
+//
+// For cotangents u (on F) and v (on E, one per replica) the kernels return
+//   g_x = d(v E + u.F)/dx = -v F - H u      and the parameter gradient.
+// Derivation (d = x_i - x_j, r = |d|, e = d/r, u_ij = u_i - u_j, s = e.u_ij):
+//   LJ:  H u |_i = sum_j [B u_ij + C (d.u_ij) d],  B = -24 eps (2 q12 - q6)/r^2,
+//        C = 96 eps (7 q12 - 2 q6)/r^4,  q6 = (sigma/r)^6, q12 = q6^2;
+//        dV/deps = 4 (q12 - q6), dV/dsigma = 24 eps (2 q12 - q6)/sigma,
+//        d(u_ij.f_ij)/deps = (d.u_ij) 24 (2 q12 - q6)/r^2,
+//        d(u_ij.f_ij)/dsigma = (d.u_ij) 144 eps (4 q12 - q6)/(sigma r^2).
+//   EAM: pass A gives rho_i, F'_i, F''_i and rho-dot_i = sum_j rho'(r) s;
+//        H u |_i = sum_j { [phi'' + (F'_i+F'_j) rho''] s e + (g/r)(u_ij - s e)
+//                          + (F''_i rho-dot_i + F''_j rho-dot_j) rho' e },
+//        g = phi' + (F'_i + F'_j) rho';  table coefficient (k, p) gradients are
+//        histograms over pairs (phi, rho) and atoms (embedding) of t^p and
+//        p t^(p-1)/h weights.
+// The full list visits every pair from both atoms, so position terms need no
+// atomics; pair parameter terms are taken once per pair (j after i).  The
+// adjoint always evaluates in binary64.
+#include <math.h>
+
+#include "md_internal.h"
+#include "md_reduce.h"
+
+namespace {
+
+__device__ __forceinline__ void apply_image(uint32_t e, double Lx, double Ly, double Lz,
+                                            double &dx, double &dy, double &dz)
+{
+    const uint32_t c = e >> MD_IDX_BITS;
+    if (c & 1u) dx = dx + Lx;
+    if (c & 2u) dx = dx - Lx;
+    if (c & 4u) dy = dy + Ly;
+    if (c & 8u) dy = dy - Ly;
+    if (c & 16u) dz = dz + Lz;
+    if (c & 32u) dz = dz - Lz;
+}
+
+__device__ __forceinline__ void atom_box(const ForceArgs &a, int64_t i, double &Lx, double &Ly,
+                                         double &Lz)
+{
+    if (a.R > 1) {
+        const RepDesc &r = a.reps[a.rep_of[i]];
+        Lx = r.L[0]; Ly = r.L[1]; Lz = r.L[2];
+    } else {
+        Lx = a.rep0.L[0]; Ly = a.rep0.L[1]; Lz = a.rep0.L[2];
+    }
+}
+
+template <int TPP>
+__device__ __forceinline__ double group_sum(double v)
+{
+    for (int o = TPP / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// row k, t and value / d/du / d2/du2 of a binary64 table at u
+__device__ __forceinline__ void spl_full(const double *tab, double u, int nk, int &k, double &t,
+                                         double &f, double &fu, double &fuu)
+{
+    k = (int)floor(u);
+    k = k > nk - 2 ? nk - 2 : k;
+    k = k < 0 ? 0 : k;
+    t = u - (double)k;
+    const double4 c = reinterpret_cast<const double4 *>(tab)[k];
+    f = c.x + t * (c.y + t * (c.z + t * c.w));
+    fu = c.y + t * (2.0 * c.z + 3.0 * t * c.w);
+    fuu = 2.0 * c.z + 6.0 * t * c.w;
+}
+
+// embedding with linear continuation: F, F', F'', row k, t (t = u - (nk-1) when lin)
+__device__ __forceinline__ void embed_full(const ForceArgs &a, double rho, double &F, double &Fp,
+                                           double &Fpp, int &k, double &t, bool &lin)
+{
+    const int nk = a.nk[2];
+    const double ih = a.inv_h[2];
+    const double u = (rho - a.x0[2]) * ih;
+    if (u > (double)(nk - 1)) {
+        const double4 c = reinterpret_cast<const double4 *>(a.tab[2])[nk - 2];
+        const double fend = ((c.x + c.y) + c.z) + c.w;
+        const double sl = (c.y + 2.0 * c.z) + 3.0 * c.w;
+        t = u - (double)(nk - 1);
+        F = fend + sl * t;
+        Fp = sl * ih;
+        Fpp = 0.0;
+        k = nk - 2;
+        lin = true;
+        return;
+    }
+    double fu, fuu;
+    spl_full(a.tab[2], u, nk, k, t, F, fu, fuu);
+    Fp = fu * ih;
+    Fpp = fuu * (ih * ih);
+    lin = false;
+}
+
+// ---------------------------------------------------------------- LJ
+template <int TPP>
+__global__ __launch_bounds__(256) void k_lj_vjp(VjpArgs v)
+{
+    __shared__ double lds[16];
+    const ForceArgs &a = v.f;
+    constexpr int APB = 256 / TPP;
+    const int sub = threadIdx.x % TPP, grp = threadIdx.x / TPP;
+    const int64_t n = a.n;
+    const double eps = a.lj[0], sig = a.lj[1];
+    const double s2 = sig * sig;
+    double acc_e = 0.0, acc_s = 0.0;
+    const int64_t ntiles = (n + APB - 1) / APB;
+    const ItemRange it = xcd_items(ntiles, 1, 0);
+    for (int64_t t = it.first; t < it.end; t += it.stride) {
+        const int64_t i = t * APB + grp;
+        const bool valid = i < n;
+        double F[3] = {0.0, 0.0, 0.0}, Hu[3] = {0.0, 0.0, 0.0};
+        double vE = 0.0;
+        if (valid) {
+            const double4 xi = a.pos[i];
+            const double ui[3] = {v.u[i], v.u[n + i], v.u[2 * n + i]};
+            vE = v.vE[a.R > 1 ? a.rep_of[i] : 0];
+            double Lx, Ly, Lz;
+            atom_box(a, i, Lx, Ly, Lz);
+            const int32_t m = a.cnt[i] < a.M ? a.cnt[i] : a.M;
+            const uint32_t *row = a.nbr + i * (int64_t)a.M;
+            for (int32_t k = sub; k < m; k += TPP) {
+                const uint32_t en = row[k];
+                const int64_t j = en & MD_IDX_MASK;
+                const double4 xj = a.pos[j];
+                double d[3] = {xi.x - xj.x, xi.y - xj.y, xi.z - xj.z};
+                if (en >> MD_IDX_BITS) apply_image(en, Lx, Ly, Lz, d[0], d[1], d[2]);
+                const double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+                if (!(r2 < a.rc2)) continue;
+                const double ir2 = 1.0 / r2;
+                const double q2 = s2 * ir2;
+                const double q6 = q2 * q2 * q2;
+                const double q12 = q6 * q6;
+                const double fs = 24.0 * eps * (2.0 * q12 - q6) * ir2;
+                const double B = -fs;
+                const double C = 96.0 * eps * (7.0 * q12 - 2.0 * q6) * (ir2 * ir2);
+                const double uij[3] = {ui[0] - v.u[j], ui[1] - v.u[n + j], ui[2] - v.u[2 * n + j]};
+                const double du = (d[0] * uij[0] + d[1] * uij[1]) + d[2] * uij[2];
+                for (int c = 0; c < 3; c++) {
+                    F[c] = fma(fs, d[c], F[c]);
+                    Hu[c] += B * uij[c] + C * du * d[c];
+                }
+                // each unordered pair is visited twice: half weight
+                const double dVde = 4.0 * (q12 - q6);
+                const double dVds = 24.0 * eps * (2.0 * q12 - q6) / sig;
+                const double dufe = du * 24.0 * (2.0 * q12 - q6) * ir2;
+                const double dufs = du * 144.0 * eps * (4.0 * q12 - q6) * ir2 / sig;
+                acc_e += 0.5 * (vE * dVde + dufe);
+                acc_s += 0.5 * (vE * dVds + dufs);
+            }
+        }
+        for (int c = 0; c < 3; c++) {
+            F[c] = group_sum<TPP>(F[c]);
+            Hu[c] = group_sum<TPP>(Hu[c]);
+        }
+        if (valid && sub == 0)
+            for (int c = 0; c < 3; c++) v.gx[c * n + i] = -vE * F[c] - Hu[c];
+    }
+    double s[4] = {acc_e, acc_s, 0.0, 0.0};
+    if (mdred::last_block_sum4(s, v.gpart, a.done, lds) && threadIdx.x == 0 && v.gout != nullptr) {
+        v.gout[0] = s[0];
+        v.gout[1] = s[1];
+    }
+}
+
+// ---------------------------------------------------------------- EAM pass A
+template <int TPP>
+__global__ __launch_bounds__(256) void k_eam_vjp_a(VjpArgs v)
+{
+    const ForceArgs &a = v.f;
+    constexpr int APB = 256 / TPP;
+    const int sub = threadIdx.x % TPP, grp = threadIdx.x / TPP;
+    const int64_t n = a.n;
+    const int nkr = a.nk[1];
+    const double x0r = a.x0[1], ihr = a.inv_h[1];
+    const int64_t ntiles = (n + APB - 1) / APB;
+    const ItemRange it = xcd_items(ntiles, 1, 0);
+    for (int64_t t = it.first; t < it.end; t += it.stride) {
+        const int64_t i = t * APB + grp;
+        const bool valid = i < n;
+        double rho = 0.0, rdot = 0.0;
+        if (valid) {
+            const double4 xi = a.pos[i];
+            const double ui[3] = {v.u[i], v.u[n + i], v.u[2 * n + i]};
+            double Lx, Ly, Lz;
+            atom_box(a, i, Lx, Ly, Lz);
+            const int32_t m = a.cnt[i] < a.M ? a.cnt[i] : a.M;
+            const uint32_t *row = a.nbr + i * (int64_t)a.M;
+            for (int32_t k = sub; k < m; k += TPP) {
+                const uint32_t en = row[k];
+                const int64_t j = en & MD_IDX_MASK;
+                const double4 xj = a.pos[j];
+                double d[3] = {xi.x - xj.x, xi.y - xj.y, xi.z - xj.z};
+                if (en >> MD_IDX_BITS) apply_image(en, Lx, Ly, Lz, d[0], d[1], d[2]);
+                const double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+                if (!(r2 < a.rrho2)) continue;
+                const double r = sqrt(r2);
+                int kk;
+                double tt, f, fu, fuu;
+                spl_full(a.tab[1], (r - x0r) * ihr, nkr, kk, tt, f, fu, fuu);
+                const double uij[3] = {ui[0] - v.u[j], ui[1] - v.u[n + j], ui[2] - v.u[2 * n + j]};
+                const double s = ((d[0] * uij[0] + d[1] * uij[1]) + d[2] * uij[2]) / r;
+                rho += f;
+                rdot += (fu * ihr) * s;
+            }
+        }
+        rho = group_sum<TPP>(rho);
+        rdot = group_sum<TPP>(rdot);
+        if (valid && sub == 0) {
+            double F, Fp, Fpp, tt;
+            int kk;
+            bool lin;
+            embed_full(a, rho, F, Fp, Fpp, kk, tt, lin);
+            a.rho[i] = rho;
+            a.fp[i] = Fp;
+            v.fpp[i] = Fpp;
+            v.rdot[i] = rdot;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- EAM pass B
+template <int TPP>
+__global__ __launch_bounds__(256) void k_eam_vjp_b(VjpArgs v)
+{
+    const ForceArgs &a = v.f;
+    constexpr int APB = 256 / TPP;
+    const int sub = threadIdx.x % TPP, grp = threadIdx.x / TPP;
+    const int64_t n = a.n;
+    const int nkp = a.nk[0], nkr = a.nk[1];
+    const double x0p = a.x0[0], ihp = a.inv_h[0], x0r = a.x0[1], ihr = a.inv_h[1];
+    double *gphi = v.gtab;
+    double *grho = v.gtab + 4 * (int64_t)(nkp - 1);
+    const int64_t ntiles = (n + APB - 1) / APB;
+    const ItemRange it = xcd_items(ntiles, 1, 0);
+    for (int64_t t = it.first; t < it.end; t += it.stride) {
+        const int64_t i = t * APB + grp;
+        const bool valid = i < n;
+        double F[3] = {0.0, 0.0, 0.0}, Hu[3] = {0.0, 0.0, 0.0};
+        double vE = 0.0;
+        if (valid) {
+            const double4 xi = a.pos[i];
+            const double ui[3] = {v.u[i], v.u[n + i], v.u[2 * n + i]};
+            const double fpi = a.fp[i], qi = v.fpp[i] * v.rdot[i];
+            vE = v.vE[a.R > 1 ? a.rep_of[i] : 0];
+            double Lx, Ly, Lz;
+            atom_box(a, i, Lx, Ly, Lz);
+            const int32_t m = a.cnt[i] < a.M ? a.cnt[i] : a.M;
+            const uint32_t *row = a.nbr + i * (int64_t)a.M;
+            for (int32_t k = sub; k < m; k += TPP) {
+                const uint32_t en = row[k];
+                const int64_t j = en & MD_IDX_MASK;
+                const double4 xj = a.pos[j];
+                double d[3] = {xi.x - xj.x, xi.y - xj.y, xi.z - xj.z};
+                if (en >> MD_IDX_BITS) apply_image(en, Lx, Ly, Lz, d[0], d[1], d[2]);
+                const double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+                const bool in_phi = r2 < a.rphi2, in_rho = r2 < a.rrho2;
+                if (!in_phi && !in_rho) continue;
+                const double r = sqrt(r2);
+                const double e[3] = {d[0] / r, d[1] / r, d[2] / r};
+                const double uij[3] = {ui[0] - v.u[j], ui[1] - v.u[n + j], ui[2] - v.u[2 * n + j]};
+                const double s = (e[0] * uij[0] + e[1] * uij[1]) + e[2] * uij[2];
+                double ph = 0.0, php = 0.0, phpp = 0.0, rh = 0.0, rhp = 0.0, rhpp = 0.0;
+                double tp = 0.0, tr = 0.0;
+                int kp = 0, kr = 0;
+                if (in_phi) {
+                    double fu, fuu;
+                    spl_full(a.tab[0], (r - x0p) * ihp, nkp, kp, tp, ph, fu, fuu);
+                    php = fu * ihp;
+                    phpp = fuu * (ihp * ihp);
+                }
+                if (in_rho) {
+                    double fu, fuu;
+                    spl_full(a.tab[1], (r - x0r) * ihr, nkr, kr, tr, rh, fu, fuu);
+                    rhp = fu * ihr;
+                    rhpp = fuu * (ihr * ihr);
+                }
+                const double Fs = fpi + a.fp[j];
+                const double g = php + Fs * rhp;
+                const double gg = phpp + Fs * rhpp;
+                const double q = qi + v.fpp[j] * v.rdot[j];
+                for (int c = 0; c < 3; c++) {
+                    F[c] -= g * e[c];
+                    Hu[c] += gg * s * e[c] + (g / r) * (uij[c] - s * e[c]) + q * rhp * e[c];
+                }
+                if (v.gtab != nullptr && j > i) {
+                    if (in_phi) {
+                        const double t2 = tp * tp;
+                        const double pw[4] = {1.0, tp, t2, t2 * tp};
+                        const double dp[4] = {0.0, 1.0, 2.0 * tp, 3.0 * t2};
+                        for (int p = 0; p < 4; p++)
+                            atomicAdd(&gphi[4 * (int64_t)kp + p], vE * pw[p] - s * dp[p] * ihp);
+                    }
+                    if (in_rho) {
+                        const double t2 = tr * tr;
+                        const double pw[4] = {1.0, tr, t2, t2 * tr};
+                        const double dp[4] = {0.0, 1.0, 2.0 * tr, 3.0 * t2};
+                        for (int p = 0; p < 4; p++)
+                            atomicAdd(&grho[4 * (int64_t)kr + p],
+                                      vE * Fs * pw[p] - (s * Fs * dp[p] * ihr + q * pw[p]));
+                    }
+                }
+            }
+        }
+        for (int c = 0; c < 3; c++) {
+            F[c] = group_sum<TPP>(F[c]);
+            Hu[c] = group_sum<TPP>(Hu[c]);
+        }
+        if (valid && sub == 0)
+            for (int c = 0; c < 3; c++) v.gx[c * n + i] = -vE * F[c] - Hu[c];
+    }
+}
+
+// embedding-table gradient: one entry per atom
+__global__ __launch_bounds__(256) void k_eam_vjp_embed(VjpArgs v)
+{
+    const ForceArgs &a = v.f;
+    const int64_t n = a.n;
+    const int nkp = a.nk[0], nkr = a.nk[1];
+    double *gemb = v.gtab + 4 * (int64_t)(nkp - 1) + 4 * (int64_t)(nkr - 1);
+    const double ih = a.inv_h[2];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double F, Fp, Fpp, t;
+        int k;
+        bool lin;
+        embed_full(a, a.rho[i], F, Fp, Fpp, k, t, lin);
+        const double vE = v.vE[a.R > 1 ? a.rep_of[i] : 0];
+        const double rd = v.rdot[i];
+        for (int p = 0; p < 4; p++) {
+            double dF, dFp;
+            if (lin) {
+                dF = 1.0 + (double)p * t;
+                dFp = (double)p * ih;
+            } else {
+                const double tp = p == 0 ? 1.0 : (p == 1 ? t : (p == 2 ? t * t : t * t * t));
+                const double dtp = p == 0 ? 0.0 : (p == 1 ? 1.0 : (p == 2 ? 2.0 * t : 3.0 * t * t));
+                dF = tp;
+                dFp = dtp * ih;
+            }
+            atomicAdd(&gemb[4 * (int64_t)k + p], vE * dF - rd * dFp);
+        }
+    }
+}
+
+#define MD_VJP_SWITCH(KERNEL)                                                                \
+    switch (tpp) {                                                                           \
+    case 4: hipLaunchKernelGGL((KERNEL<4>), dim3(grid), dim3(256), 0, s, a); break;           \
+    case 8: hipLaunchKernelGGL((KERNEL<8>), dim3(grid), dim3(256), 0, s, a); break;           \
+    case 16: hipLaunchKernelGGL((KERNEL<16>), dim3(grid), dim3(256), 0, s, a); break;         \
+    default: hipLaunchKernelGGL((KERNEL<32>), dim3(grid), dim3(256), 0, s, a); break;         \
+    }
+
+} // namespace
+
+void launch_lj_vjp(hipStream_t s, int grid, int tpp, bool mixed, const VjpArgs &a)
+{
+    (void)mixed;
+    MD_VJP_SWITCH(k_lj_vjp)
+}
+
+void launch_eam_vjp_a(hipStream_t s, int grid, int tpp, bool mixed, const VjpArgs &a)
+{
+    (void)mixed;
+    MD_VJP_SWITCH(k_eam_vjp_a)
+}
+
+void launch_eam_vjp_b(hipStream_t s, int grid, int tpp, bool mixed, const VjpArgs &a)
+{
+    (void)mixed;
+    MD_VJP_SWITCH(k_eam_vjp_b)
+}
+
+void launch_eam_vjp_embed(hipStream_t s, int grid, const VjpArgs &a)
+{
+    hipLaunchKernelGGL(k_eam_vjp_embed, dim3(grid), dim3(256), 0, s, a);
+}

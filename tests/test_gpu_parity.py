@@ -1,0 +1,358 @@
+"""GPU path (through the C ABI) against the CPU oracle, element by element.
+
+Integer results (cells, sorted order, neighbour pair sets) must match exactly.
+Floating point: the FP64 path within 1e-12 relative (norm-wise over all 3N
+force components; the two sides only sum in different orders), the FP32-pair
+path within the 1e-5 relative force error it is specified for.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1305_4196_amd import binding as B
+from paper_1305_4196_amd import workloads as W
+from paper_1305_4196_amd.system import MDSystem
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+MIXED_TOL = 1e-5
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def thermal(w, sd, seed):
+    g = np.random.default_rng(seed)
+    parts = []
+    for r in range(w.n_replicas):
+        lo, hi = int(w.offsets[r]), int(w.offsets[r + 1])
+        parts.append(oracle.wrap(w.pos[:, lo:hi] + g.normal(0, sd, size=(3, hi - lo)), w.boxes[r]))
+    return np.ascontiguousarray(np.concatenate(parts, axis=1))
+
+
+def ragged_fcc(cells, drop, seed):
+    """fcc block with `drop` random atoms removed: a ragged tail in every tile."""
+    w = W.lj_fcc(cells)
+    g = np.random.default_rng(seed)
+    keep = np.ones(w.n, dtype=bool)
+    keep[g.choice(w.n, size=drop, replace=False)] = False
+    w.pos = np.ascontiguousarray(w.pos[:, keep])
+    w.vel = np.ascontiguousarray(w.vel[:, keep])
+    w.offsets = np.array([0, w.pos.shape[1]], dtype=np.int64)
+    return w
+
+
+def random_box(L, n, seed):
+    g = np.random.default_rng(seed)
+    L = np.asarray(L, dtype=np.float64)
+    w = W.lj_fcc(2)
+    w.pos = np.ascontiguousarray(g.uniform(0, 1, size=(3, n)) * L[:, None])
+    w.vel = np.zeros_like(w.pos)
+    w.boxes = L[None, :]
+    w.offsets = np.array([0, n], dtype=np.int64)
+    return w
+
+
+def lj_cases():
+    return {
+        "fcc256": W.lj_small(),                                 # 2 cells per axis
+        "box_2x3x5": random_box((6.0, 8.9, 14.5), 300, 1),        # aliased stencils
+        "fcc2048_thermal": (W.lj_fcc(8), 0.08, 2),               # 4 cells per axis
+        "ragged_6859": ragged_fcc(12, 53, 3),                   # 7 cells, ragged tail
+    }
+
+
+def materialise(case):
+    if isinstance(case, tuple):
+        w, sd, seed = case
+        w.pos = thermal(w, sd, seed)
+        return w
+    return case
+
+
+CASES = lj_cases()
+
+
+def user_pairs(start, nbr):
+    n = start.size - 1
+    return {(i, int(j)) for i in range(n) for j in nbr[start[i]:start[i + 1]]}
+
+
+# ---------------------------------------------------------------- cells and lists
+@pytest.mark.parametrize("name", list(CASES))
+def test_cells_and_order_exact(name):
+    w = materialise(lj_cases()[name])
+    s = MDSystem.from_workload(w)
+    s.build()
+    cs, order = s.cells()
+    L = w.boxes[0]
+    c = oracle.bin_cells(oracle.wrap(w.pos, L), L, w.pot.rc + w.skin)
+    assert np.array_equal(cs, c["cell_start"])
+    assert np.array_equal(order, c["order"])
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_full_list_bit_exact(name):
+    w = materialise(lj_cases()[name])
+    s = MDSystem.from_workload(w)
+    s.build(B.MD_LIST_FULL)
+    start, nbr = s.neighbor_list()
+    L = w.boxes[0]
+    x = oracle.wrap(w.pos, L)
+    os_, on = oracle.neighbor_list(x, L, w.pot.rc + w.skin, full=True)
+    assert np.array_equal(start, os_), "per-atom neighbour counts differ"
+    assert user_pairs(start, nbr) == user_pairs(os_, on)
+    if w.n <= 400:
+        pi, pj = oracle.pairs_brute(x, L, w.pot.rc + w.skin, full=True)
+        assert user_pairs(start, nbr) == set(zip(pi.tolist(), pj.tolist()))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_half_list_bit_exact(name):
+    w = materialise(lj_cases()[name])
+    s = MDSystem.from_workload(w)
+    s.build(B.MD_LIST_HALF)
+    start, nbr = s.neighbor_list()
+    L = w.boxes[0]
+    x = oracle.wrap(w.pos, L)
+    hs, hn = oracle.neighbor_list(x, L, w.pot.rc + w.skin, full=False)
+    got = user_pairs(start, nbr)
+    assert got == user_pairs(hs, hn)
+    _, order = s.cells()
+    rank = np.empty(w.n, dtype=np.int64)
+    rank[order] = np.arange(w.n)
+    assert all(rank[j] > rank[i] for i, j in got)
+
+
+# ---------------------------------------------------------------- LJ forces
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("kind", [B.MD_LIST_FULL, B.MD_LIST_HALF])
+def test_lj_forces_fp64(name, kind):
+    w = materialise(lj_cases()[name])
+    s = MDSystem.from_workload(w)
+    F, E, Wv = s.forces(B.MD_FP64, kind)
+    L = w.boxes[0]
+    Fo, Eo, Wo = oracle.forces(oracle.wrap(w.pos, L), L, w.pot, skin=w.skin)
+    Fg = F.cpu().numpy()
+    scale = max(np.linalg.norm(Fo), 1e-300)
+    assert np.linalg.norm(Fg - Fo) <= FP64_TOL * scale + 1e-13 * np.sqrt(w.n)
+    assert E.item() == pytest.approx(Eo, rel=FP64_TOL, abs=1e-12)
+    assert Wv.item() == pytest.approx(Wo, rel=FP64_TOL, abs=1e-12)
+
+
+@pytest.mark.parametrize("name", ["fcc2048_thermal", "ragged_6859"])
+def test_lj_forces_mixed_within_1e5(name):
+    w = materialise(lj_cases()[name])
+    if name == "ragged_6859":
+        w.pos = thermal(w, 0.07, 11)
+    s = MDSystem.from_workload(w)
+    F, E, Wv = s.forces(B.MD_MIXED)
+    L = w.boxes[0]
+    Fo, Eo, Wo = oracle.forces(oracle.wrap(w.pos, L), L, w.pot, skin=w.skin)
+    err = rel(F.cpu().numpy(), Fo)
+    print(f"{name}: mixed relative force error {err:.3e}")
+    assert err <= MIXED_TOL
+    assert E.item() == pytest.approx(Eo, rel=1e-6)
+
+
+def test_full_list_forces_are_bitwise_repeatable():
+    w = materialise(lj_cases()["ragged_6859"])
+    w.pos = thermal(w, 0.06, 12)
+    s = MDSystem.from_workload(w)
+    F1, E1, _ = s.forces(B.MD_FP64)
+    F2, E2, _ = s.forces(B.MD_FP64)
+    assert torch.equal(F1, F2) and torch.equal(E1, E2)
+
+
+# ---------------------------------------------------------------- EAM forces
+def eam_case(cells, seed, vac=0.05, sd=0.05):
+    return W.fs_eam(cells=cells, vacancy_frac=vac, sigma_d=sd, workload_id=50 + seed)
+
+
+@pytest.mark.parametrize("cells,seed", [(3, 0), (5, 1), (9, 2)])
+def test_eam_forces_fp64(cells, seed):
+    w = eam_case(cells, seed)
+    s = MDSystem.from_workload(w)
+    F, E, Wv = s.forces(B.MD_FP64)
+    L = w.boxes[0]
+    Fo, Eo, Wo = oracle.forces(oracle.wrap(w.pos, L), L, w.pot, skin=w.skin)
+    assert rel(F.cpu().numpy(), Fo) <= 1e-11
+    assert E.item() == pytest.approx(Eo, rel=1e-12)
+    assert Wv.item() == pytest.approx(Wo, rel=1e-10, abs=1e-10)
+
+
+@pytest.mark.parametrize("cells,seed", [(5, 3), (9, 4)])
+def test_eam_forces_mixed_within_1e5(cells, seed):
+    w = eam_case(cells, seed)
+    s = MDSystem.from_workload(w)
+    F, E, Wv = s.forces(B.MD_MIXED)
+    L = w.boxes[0]
+    Fo, Eo, Wo = oracle.forces(oracle.wrap(w.pos, L), L, w.pot, skin=w.skin)
+    err = rel(F.cpu().numpy(), Fo)
+    print(f"EAM {cells}^3 mixed relative force error {err:.3e}")
+    assert err <= MIXED_TOL
+    assert E.item() == pytest.approx(Eo, rel=1e-7)
+
+
+# ---------------------------------------------------------------- velocity Verlet
+@pytest.mark.parametrize("kind", [B.MD_LIST_FULL, B.MD_LIST_HALF])
+def test_verlet_small_lj_fp64(kind):
+    w = W.lj_small()
+    L = w.boxes[0]
+    s = MDSystem.from_workload(w)
+    F, hist, nreb = s.run(100, w.dt, w.mass, B.MD_FP64, kind)
+    xo, vo, Fo, ho, nrebo = oracle.verlet(w.pos, w.vel, L, w.pot, w.dt, w.mass, 100, w.skin)
+    h = hist.cpu().numpy()
+    assert np.allclose(h, ho, rtol=1e-9, atol=1e-9)
+    d = s.pos.cpu().numpy() - xo
+    d -= L[:, None] * np.round(d / L[:, None])
+    assert np.max(np.abs(d)) < 1e-8
+    assert np.max(np.abs(s.vel.cpu().numpy() - vo)) < 1e-8
+    assert rel(F.cpu().numpy(), Fo) < 1e-8
+    assert np.all(s.pos.cpu().numpy() >= 0) and np.all(s.pos.cpu().numpy() < L[:, None])
+    assert nreb == nrebo
+
+
+def test_verlet_mixed_tracks_fp64():
+    w = W.lj_small()
+    L = w.boxes[0]
+    s = MDSystem.from_workload(w)
+    F, hist, nreb = s.run(100, w.dt, w.mass, B.MD_MIXED)
+    _, _, _, ho, _ = oracle.verlet(w.pos, w.vel, L, w.pot, w.dt, w.mass, 100, w.skin)
+    h = hist.cpu().numpy()
+    e, eo = h[:, 0] + h[:, 1], ho[:, 0] + ho[:, 1]
+    assert np.max(np.abs(e - eo)) / abs(eo[0]) < 1e-5
+
+
+def test_verlet_eam_fp64():
+    w = eam_case(5, 6, sd=0.08)
+    L = w.boxes[0]
+    s = MDSystem.from_workload(w)
+    F, hist, nreb = s.run(40, w.dt, w.mass, B.MD_FP64)
+    xo, vo, Fo, ho, nrebo = oracle.verlet(w.pos, w.vel, L, w.pot, w.dt, w.mass, 40, w.skin)
+    assert np.allclose(hist.cpu().numpy(), ho, rtol=1e-9, atol=1e-9)
+    d = s.pos.cpu().numpy() - xo
+    d -= L[:, None] * np.round(d / L[:, None])
+    assert np.max(np.abs(d)) < 1e-9
+    assert nreb == nrebo
+
+
+def test_overflow_is_reported_and_recovered():
+    w = materialise(lj_cases()["fcc2048_thermal"])
+    s = MDSystem.from_workload(w)
+    B.md_set_tuning(s.ctx, 2, 40)            # rows of 40 < the ~78 neighbours
+    B.md_build_cells(s.ctx, s.pos, s.boxes, w.pot.rc, w.skin)
+    B.md_build_neighbor_list(s.ctx, B.MD_LIST_FULL)
+    code, flags, cap = s.status()
+    assert code == B.MD_ERR_CAPACITY and flags & B.FLAG_OVERFLOW and cap >= 78
+    F, E, _ = s.forces(B.MD_FP64)             # rebuild regrows the rows
+    assert s.status()[0] == B.MD_OK
+    L = w.boxes[0]
+    Fo, Eo, _ = oracle.forces(oracle.wrap(w.pos, L), L, w.pot, skin=w.skin)
+    assert rel(F.cpu().numpy(), Fo) <= FP64_TOL
+
+
+def test_verlet_overflow_retry():
+    w = W.lj_small()
+    L = w.boxes[0]
+    s = MDSystem.from_workload(w)
+    B.md_set_tuning(s.ctx, 2, 60)
+    F, hist, nreb = s.run(50, w.dt, w.mass, B.MD_FP64)
+    _, _, _, ho, _ = oracle.verlet(w.pos, w.vel, L, w.pot, w.dt, w.mass, 50, w.skin)
+    assert np.allclose(hist.cpu().numpy(), ho, rtol=1e-9, atol=1e-9)
+
+
+def test_bad_box_is_rejected():
+    w = W.lj_small()
+    s = MDSystem.from_workload(w)
+    with pytest.raises(B.MDError) as e:
+        B.md_build_cells(s.ctx, s.pos, np.array([[5.5, 7.0, 7.0]]), 2.5, 0.3)
+    assert e.value.code == B.MD_ERR_BOX
+    with pytest.raises(B.MDError) as e:
+        B.md_build_cells(s.ctx, s.pos, np.array([[np.nan, 7.0, 7.0]]), 2.5, 0.3)
+    assert e.value.code == B.MD_ERR_ARG
+
+
+def test_nonfinite_force_is_flagged():
+    w = W.lj_small()
+    pos = w.pos.copy()
+    pos[:, 1] = pos[:, 0]                    # two atoms on top of each other: r = 0
+    s = MDSystem(pos, w.boxes, w.offsets, w.pot, w.skin)
+    s.forces(B.MD_FP64)
+    code, flags, _ = s.status()
+    assert code == B.MD_ERR_NONFINITE and flags & B.FLAG_NONFINITE
+    assert s.status()[0] == B.MD_OK          # flags are cleared after reading
+
+
+# ---------------------------------------------------------------- batched replicas
+@pytest.mark.parametrize("kind", ["lj", "eam"])
+def test_replica_batch_forces(kind):
+    w = W.replica_batch(kind, n_replicas=12)
+    w.pos = thermal(w, 0.03, 13)
+    s = MDSystem.from_workload(w)
+    F, E, Wv = s.forces(B.MD_FP64)
+    Fg = F.cpu().numpy()
+    for r in range(w.n_replicas):
+        lo, hi = int(w.offsets[r]), int(w.offsets[r + 1])
+        L = w.boxes[r]
+        Fo, Eo, Wo = oracle.forces(oracle.wrap(w.pos[:, lo:hi], L), L, w.pot, skin=w.skin)
+        assert rel(Fg[:, lo:hi], Fo) <= 1e-11
+        assert E[r].item() == pytest.approx(Eo, rel=1e-12)
+        assert Wv[r].item() == pytest.approx(Wo, rel=1e-10, abs=1e-10)
+
+
+# ---------------------------------------------------------------- adjoints
+def test_lj_vjp_matches_oracle():
+    w = materialise(lj_cases()["fcc2048_thermal"])
+    L = w.boxes[0]
+    s = MDSystem.from_workload(w)
+    g = np.random.default_rng(20)
+    u = g.normal(size=w.pos.shape)
+    vE = 0.7
+    gx, gp = s.vjp(u, np.array([vE]))
+    x = oracle.wrap(w.pos, L)
+    pi, pj = oracle.half_pairs(x, L, w.pot.rc + w.skin)
+    gxo, gpo = oracle.lj_vjp(x, L, pi, pj, u, vE)
+    assert rel(gx.cpu().numpy(), gxo) <= 1e-12
+    assert np.allclose(gp.cpu().numpy(), gpo, rtol=1e-11)
+
+
+def test_eam_vjp_matches_oracle():
+    w = eam_case(5, 7, sd=0.08)
+    L = w.boxes[0]
+    s = MDSystem.from_workload(w)
+    g = np.random.default_rng(21)
+    u = g.normal(size=w.pos.shape)
+    vE = -0.4
+    gx, gp = s.vjp(u, np.array([vE]))
+    x = oracle.wrap(w.pos, L)
+    pi, pj = oracle.half_pairs(x, L, w.pot.rc + w.skin)
+    gxo, gphi, grho, gemb = oracle.eam_vjp(x, L, pi, pj, w.pot, u, vE)
+    assert rel(gx.cpu().numpy(), gxo) <= 1e-11
+    gpo = np.concatenate([gphi.ravel(), grho.ravel(), gemb.ravel()])
+    gpg = gp.cpu().numpy()
+    assert np.linalg.norm(gpg - gpo) <= 1e-10 * np.linalg.norm(gpo)
+
+
+def test_autograd_function_gradients():
+    from paper_1305_4196_amd.system import MDForces
+    w = materialise(lj_cases()["fcc2048_thermal"])
+    s = MDSystem.from_workload(w)
+    pos = s.pos.clone().requires_grad_(True)
+    params = torch.tensor([1.05, 0.98], dtype=torch.float64, device="cuda", requires_grad=True)
+    F, E = MDForces.apply(pos, params, s, B.MD_FP64)
+    target = torch.zeros_like(F)
+    loss = ((F - target) ** 2).sum() / F.numel() + 0.01 * E.sum()
+    loss.backward()
+    u = (2 * F.detach() / F.numel()).cpu().numpy()
+    L = w.boxes[0]
+    x = oracle.wrap(w.pos, L)
+    pi, pj = oracle.half_pairs(x, L, w.pot.rc + w.skin)
+    gxo, gpo = oracle.lj_vjp(x, L, pi, pj, u, 0.01, eps=1.05, sigma=0.98)
+    assert rel(pos.grad.cpu().numpy(), gxo) <= 1e-11
+    assert np.allclose(params.grad.cpu().numpy(), gpo, rtol=1e-10)
