@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Throughput of the MD hot path on one MI355X: atom-steps/s of velocity Verlet
+(forces + device-decided neighbour rebuilds + integration + energy sums) on the
+1,048,576-atom Lennard-Jones fcc crystal (64^3 unit cells, density 0.8442,
+rc 2.5, skin 0.3, T 0.72, dt 0.005), FP32-pair/FP64-accumulate path versus the
+plain FP64 path, with the mixed path's force error against the FP64 reference.
+
+Prints ONE JSON line.  `value` is the mixed path's atom-steps/s with inputs
+resident in HBM; the FP64 path's figure, the force error, energy drift, the
+event-timed roofline of the dominant kernel and the CPU reference timed on the
+host's cores ride along in the same line.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1]
+  python bench.py --copy-probe      # plain 1 GiB device copy (counter calibration)
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, datasheet
+FP64_VECTOR_TFLOPS = 78.6        # MI355X, datasheet
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # non-packed vector lane-ops/s (256 CU x 64 lanes x 2.4 GHz)
+FORCE_SOURCES = ["paper_1305_4196_amd/csrc/md_force.hip", "paper_1305_4196_amd/csrc/md_internal.h",
+                 "paper_1305_4196_amd/csrc/md_reduce.h"]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def source_hash(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def copy_probe():
+    import torch
+    n = (1 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": a.numel() * 8, "copy_probe_bytes_written": b.numel() * 8,
+                      "launches": 5}))
+
+
+def cpu_baseline(w, steps: int):
+    """The CPU reference (single-threaded C, binary64) on the first `steps` steps
+    of the same run, including its initial list build."""
+    import oracle
+    t0 = time.perf_counter()
+    oracle.verlet(w.pos, w.vel, w.boxes[0], w.pot, w.dt, w.mass, steps, w.skin)
+    dt = time.perf_counter() - t0
+    return {"value": w.n * steps / dt, "unit": "atom-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} steps of the same {w.n:,}-atom run from its initial state, "
+                      f"including the reference's initial neighbour-list build ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--cap", type=int, default=0, help="LDS candidates per cell task")
+    ap.add_argument("--wgpc", type=int, default=0)
+    ap.add_argument("--only", choices=["mixed", "fp64"], default=None,
+                    help="time one path only (for profiler runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU decomposition is design-only)", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
+
+    import numpy as np
+    import torch
+    from paper_1305_4196_amd import binding as B
+    from paper_1305_4196_amd import workloads as W
+    from paper_1305_4196_amd.system import MDSystem
+
+    torch.cuda.set_device(0)
+    w = W.lj_bulk()
+    n = w.n
+    log(f"workload {w.name}: N={n}, L={w.boxes[0, 0]:.4f}, steps={args.steps}, warmup={args.warmup}")
+    sysm = MDSystem.from_workload(w)
+    if args.cap:
+        B.md_set_tuning(sysm.ctx, 0, args.cap)
+    if args.wgpc:
+        B.md_set_tuning(sysm.ctx, 1, args.wgpc)
+    pos0 = torch.tensor(w.pos, dtype=torch.float64, device="cuda")
+    vel0 = torch.tensor(w.vel, dtype=torch.float64, device="cuda")
+    F = torch.empty_like(pos0)
+    hist = torch.zeros((args.steps, 3), dtype=torch.float64, device="cuda")
+    nreb = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    results = {}
+    paths = [("mixed", B.MD_MIXED), ("fp64", B.MD_FP64)]
+    if args.only:
+        paths = [p for p in paths if p[0] == args.only]
+    for name, prec in paths:
+        sysm.pos.copy_(pos0)
+        sysm.vel.copy_(vel0)
+        B.md_build_cells(sysm.ctx, sysm.pos, sysm.boxes, w.pot.rc, w.skin)
+        if args.warmup > 0:
+            B.md_verlet_step(sysm.ctx, sysm.dpot, prec, B.MD_LIST_FULL, sysm.pos, sysm.vel, F,
+                             w.dt, w.mass, args.warmup, None, None)
+        code = B.md_get_status(sysm.ctx)[0]
+        if code != B.MD_OK:
+            raise RuntimeError(f"warm-up ended with status {code}")
+        torch.cuda.synchronize()
+        B.md_profile(sysm.ctx, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.md_verlet_step(sysm.ctx, sysm.dpot, prec, B.MD_LIST_FULL, sysm.pos, sysm.vel, F,
+                         w.dt, w.mass, args.steps, hist, nreb)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        fms, fn, lms, ln = B.md_profile(sysm.ctx, False)
+        code, flags, cap = B.md_get_status(sysm.ctx)
+        if code != B.MD_OK:
+            raise RuntimeError(f"{name} run ended with status {code} (flags {flags})")
+        h = hist.cpu().numpy()
+        etot = h[:, 0] + h[:, 1]
+        start, _ = B.md_get_neighbor_list(sysm.ctx)
+        nbar = float(start[-1]) / n
+        results[name] = dict(
+            seconds=t1 - t0, atom_steps=n * args.steps / (t1 - t0), rebuilds=int(nreb.item()),
+            force_ms_avg=fms / max(fn, 1), force_launches=fn, list_ms_total=lms, list_launches=ln,
+            nbar=nbar, drift=float(np.max(np.abs(etot - etot[0])) / abs(etot[0])),
+            T_end=float(2 * h[-1, 1] / (3 * n - 3)), capacity=cap)
+        log(f"{name}: {results[name]['atom_steps'] / 1e9:.3f} G atom-steps/s, "
+            f"{1e3 * (t1 - t0) / args.steps:.3f} ms/step, force kernel {results[name]['force_ms_avg'] * 1e3:.1f} us, "
+            f"rebuilds {results[name]['rebuilds']}, nbar {nbar:.2f}, drift {results[name]['drift']:.2e}")
+
+    # force error of the mixed path against the binary64 reference on a thermal snapshot
+    import oracle
+    snap = W.thermal_snapshot(w, 0.05)
+    s2 = MDSystem(snap, w.boxes, w.offsets, w.pot, w.skin)
+    Fm = s2.forces(B.MD_MIXED)[0].cpu().numpy()
+    Fd = s2.forces(B.MD_FP64)[0].cpu().numpy()
+    sample = np.random.default_rng(7).choice(n, size=512, replace=False).astype(np.int32)
+    Fo, _ = oracle.lj_atoms(snap, w.boxes[0], sample, w.pot.eps, w.pot.sigma, w.pot.rc)
+    err_mixed = float(np.linalg.norm(Fm[:, sample] - Fo) / np.linalg.norm(Fo))
+    err_fp64 = float(np.linalg.norm(Fd[:, sample] - Fo) / np.linalg.norm(Fo))
+    log(f"force error vs reference (512 sampled atoms): mixed {err_mixed:.2e}, fp64 {err_fp64:.2e}")
+
+    main_name = "mixed" if "mixed" in results else "fp64"
+    r = results[main_name]
+    # algorithmic bytes per atom-step of the fused LJ force kernel: list 4 nbar
+    # + x read 24 + v read/write 48 + x' write 24 + x_ref read 24
+    bytes_per_atom = 4.0 * r["nbar"] + 120.0
+    achieved = n * bytes_per_atom / (r["force_ms_avg"] * 1e-3) / 1e9
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", "traffic_lj_force.json")
+    if os.path.exists(tf):
+        with open(tf) as f:
+            t = json.load(f)
+        if t.get("source_hash") == source_hash(FORCE_SOURCES) and t.get("path") == main_name:
+            traffic = t.get("hbm_bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_lj_full (cell-task LJ forces + velocity Verlet, fused)",
+                "kernel_avg_us": round(r["force_ms_avg"] * 1e3, 2),
+                "bytes_per_atom_step": round(bytes_per_atom, 1)}
+
+    line = {
+        "metric": "atom-steps/s (forces+neighbor rebuild), FP32-mixed vs FP64 path at stated error",
+        "value": round(r["atom_steps"], 1),
+        "unit": "atom-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * r["seconds"] / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32-pair/f64-accumulate" if main_name == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "lj_fcc_1048576", "atoms": n, "cells": "64^3 fcc", "density": 0.8442,
+                   "rc": 2.5, "skin": 0.3, "T": 0.72, "dt": 0.005, "list": "full",
+                   "parallelism": "single GPU"},
+        "fp64_path": ({"value": round(results["fp64"]["atom_steps"], 1),
+                       "ms_per_step": round(1e3 * results["fp64"]["seconds"] / args.steps, 4),
+                       "force_kernel_us": round(results["fp64"]["force_ms_avg"] * 1e3, 2),
+                       "energy_drift": results["fp64"]["drift"], "rebuilds": results["fp64"]["rebuilds"]}
+                      if "fp64" in results else None),
+        "mixed_force_rel_err": err_mixed,
+        "fp64_force_rel_err": err_fp64,
+        "energy_drift": r["drift"],
+        "rebuilds": r["rebuilds"],
+        "mean_neighbors": round(r["nbar"], 3),
+        "list_ms_total": round(r["list_ms_total"], 3),
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU reference ...")
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -178,12 +178,24 @@ int64_t md_get_neighbor_list(md_ctx *ctx, int64_t *start, int32_t *nbr, int64_t 
  * Pass NULL arrays to query n_cells_total only.  Synchronises. */
 int md_get_cells(md_ctx *ctx, int32_t *cell_start, int32_t *order, int64_t *n_cells_total);
 
-/* Tuning knobs (used by the autotuner): key 0 = lanes per atom in the
- * neighbour loops (4, 8, 16 or 32); key 1 = workgroups per CU of the
- * persistent force grids (1..16); key 2 = fixed per-atom list capacity
- * (1..4096; reallocates, synchronises the device, and drops the current list --
- * a small value forces the overflow path).  Returns MD_OK or MD_ERR_ARG. */
+/* Tuning knobs (used by the autotuner): key 0 = candidates staged in LDS per
+ * cell task (64..2048, a multiple of 64; the first list build picks one from
+ * the largest neighbourhood, and candidates beyond it are read from global
+ * memory); key 1 = most workgroups per CU in the cell-task grids (1..8);
+ * key 2 = fixed per-atom list capacity (1..4096, rounded up to a multiple of 8;
+ * reallocates, synchronises the device and drops the current list -- a small
+ * value forces the overflow path).  Returns MD_OK or MD_ERR_ARG. */
 int md_set_tuning(md_ctx *ctx, int32_t key, int32_t value);
+
+/* Kernel timing with HIP events on the stream of the timed calls.
+ * enable = 1: clear the counters and, from the next call on, record an event
+ * pair around every force launch (LJ kernel, or EAM density + force pair, or
+ * half-list kernel + integration) and every neighbour-list launch.
+ * enable = 0: stop, synchronise, and return [host] the summed durations and
+ * launch counts (any pointer may be NULL).  List launches include those that
+ * exit at once because no rebuild was due. */
+int md_profile(md_ctx *ctx, int32_t enable, double *force_ms, int64_t *force_launches,
+               double *list_ms, int64_t *list_launches);
 
 /* Human-readable description of the last error on this context (static storage). */
 const char *md_last_error(md_ctx *ctx);

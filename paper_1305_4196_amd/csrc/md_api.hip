@@ -12,7 +12,7 @@
 #include <string>
 #include <vector>
 
-#include "md_internal.h"
+#include "md_nbhd.h"
 
 namespace {
 
@@ -79,8 +79,9 @@ struct md_ctx {
     int32_t R = 0;
     std::vector<int64_t> off;
     int n_cu = 256;
-    int wgpc = 8;      // workgroups per CU of the persistent force grids
-    int tpp = 8;       // lanes per atom in the neighbour loops
+    int lds_max = 65536;   // LDS bytes a workgroup may use
+    int wgpc = 8;      // most cell-task workgroups per CU
+    int tpp = 0;       // unused: lanes per atom follow each cell's occupancy
     std::string err;
     hipStream_t last = nullptr;
 
@@ -105,6 +106,7 @@ struct md_ctx {
     // list
     bool have_list = false;
     int list_kind = MD_LIST_FULL;
+    int32_t cap = 256;       // candidates staged in LDS per cell task
     int32_t M = 0;
     int64_t need_M = 0;
     uint32_t *nbr = nullptr;
@@ -122,6 +124,21 @@ struct md_ctx {
     DevCtl *ctl = nullptr;
     int32_t *one = nullptr;
 
+    // event timing (md_profile)
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_force, ev_list;
+    hipEvent_t next_event()
+    {
+        if (ev_used == ev_pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            ev_pool.push_back(e);
+        }
+        return ev_pool[ev_used++];
+    }
+
     int max_grid() const { return n_cu * 16; }
     int grid_atoms(int64_t per_block) const
     {
@@ -129,17 +146,19 @@ struct md_ctx {
         int64_t cap = (int64_t)n_cu * 8;
         return (int)std::max<int64_t>(1, std::min(g, cap));
     }
-    int grid_force(int apb) const
-    {
-        int64_t g = (n + apb - 1) / apb;
-        int64_t cap = (int64_t)n_cu * wgpc;
-        return (int)std::max<int64_t>(1, std::min(g, cap));
-    }
     int grid_cells(int cells_per_block, int per_cu) const
     {
         int64_t g = (C + cells_per_block - 1) / cells_per_block;
-        int64_t cap = (int64_t)n_cu * per_cu;
-        return (int)std::max<int64_t>(1, std::min(g, cap));
+        int64_t capg = (int64_t)n_cu * per_cu;
+        return (int)std::max<int64_t>(1, std::min(g, capg));
+    }
+    // persistent grid of cell tasks (one 256-thread workgroup per cell): as
+    // many workgroups per CU as the LDS allows (160 KiB per CU), at most wgpc
+    int grid_tasks(int extra) const
+    {
+        const size_t per_block = nbhd_lds_bytes(cap, extra) + 2048 + 512;
+        int per_cu = (int)std::min<size_t>((size_t)wgpc, std::max<size_t>(1, (160 * 1024) / per_block));
+        return grid_cells(1, per_cu);
     }
 };
 
@@ -238,8 +257,17 @@ ListArgs list_args(md_ctx *c, const int32_t *pred, const double4 *src, int half)
     a.M = c->M;
     a.rl2 = c->rl * c->rl;
     a.half = half;
+    a.cap = c->cap;
     a.ctl = c->ctl;
     return a;
+}
+
+// largest LDS slice (candidates, a multiple of 64) a cell task may stage with
+// one extra binary64 array per candidate within the per-workgroup LDS limit
+int64_t cap_limit(const md_ctx *c)
+{
+    const int64_t room = c->lds_max - 4096 - (int64_t)sizeof(NbhdLds);
+    return std::max<int64_t>(64, room / (int64_t)(3 * sizeof(double) + sizeof(int32_t) + sizeof(double)) / 64 * 64);
 }
 
 // first build: count pass, then size the rows (1.25 x the largest list + margin)
@@ -248,14 +276,21 @@ int size_list(md_ctx *c, const double4 *src, int half, hipStream_t s)
     ListArgs a = list_args(c, c->one, src, half);
     a.M = 0;
     a.nbr = nullptr;
-    int32_t zero = 0;
-    if (hipMemcpyAsync(&c->ctl->max_cnt, &zero, sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess)
+    const int32_t zero2[2] = {0, 0};
+    if (hipMemcpyAsync(&c->ctl->max_cnt, &zero2[0], sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(&c->ctl->max_nbhd, &zero2[1], sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess)
         return fail(c, MD_ERR_HIP, "list sizing: reset");
-    launch_build_list(s, c->grid_cells(4, 3), a);
-    int32_t mx = 0;
+    launch_build_list(s, c->grid_tasks(0), a);
+    int32_t mx = 0, nbhd = 0;
     if (hipMemcpyAsync(&mx, &c->ctl->max_cnt, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&nbhd, &c->ctl->max_nbhd, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return fail(c, MD_ERR_HIP, "list sizing: readback");
+    // LDS slice: the largest neighbourhood seen plus 12 %, in multiples of 64,
+    // at most 1536 candidates (larger neighbourhoods read their overflow
+    // candidates from global memory)
+    c->cap = (int32_t)std::min<int64_t>(std::min<int64_t>(1536, cap_limit(c)),
+                                        std::max<int64_t>(64, ((int64_t)(1.12 * nbhd) + 63) / 64 * 64));
     int64_t want = std::max<int64_t>({(int64_t)ceil(1.25 * mx), (int64_t)mx + 16, c->need_M, 16});
     want = (want + 7) / 8 * 8;
     if (want * c->n > (1ll << 40)) return fail(c, MD_ERR_ARG, "neighbour list too large");
@@ -287,6 +322,9 @@ ForceArgs force_args(md_ctx *c, const md_potential *p)
     a.nbr = c->nbr;
     a.cnt = c->cnt;
     a.M = c->M;
+    a.C = c->C;
+    a.start = c->start;
+    a.cap = c->cap;
     a.rc2 = p->rc * p->rc;
     a.lj = p->lj_params;
     a.rho = c->rho;
@@ -356,6 +394,23 @@ int stage_tables(md_ctx *c, const md_potential *p, hipStream_t s)
     return MD_OK;
 }
 
+// records an event pair around launch() when profiling is on
+template <typename F>
+void timed(md_ctx *c, hipStream_t s, std::vector<std::pair<hipEvent_t, hipEvent_t>> &log, F launch)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    if (c->prof) {
+        a = c->next_event();
+        b = c->next_event();
+        if (a && b) (void)hipEventRecord(a, s);
+    }
+    launch();
+    if (c->prof && a && b) {
+        (void)hipEventRecord(b, s);
+        log.emplace_back(a, b);
+    }
+}
+
 } // namespace
 
 extern "C" {
@@ -380,6 +435,10 @@ int md_create(md_ctx **out, int64_t n, int32_t R, const int64_t *off)
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess &&
         ncu > 0)
         c->n_cu = ncu;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) == hipSuccess &&
+        lds > 0)
+        c->lds_max = lds;
     bool ok = true;
     ok &= dalloc(&c->pos[0], n) && dalloc(&c->pos[1], n) && dalloc(&c->pos_t, n) && dalloc(&c->xref, n);
     ok &= dalloc(&c->vel, 3 * n) && dalloc(&c->vel_t, 3 * n) && dalloc(&c->force, 3 * n);
@@ -423,6 +482,7 @@ void md_destroy(md_ctx *c)
     dfree(c->eatom); dfree(c->watom); dfree(c->rho); dfree(c->fp); dfree(c->fpp); dfree(c->rdot);
     dfree(c->u_s); dfree(c->gx_s); dfree(c->partial); dfree(c->zeros_R);
     dfree(c->tab64); dfree(c->tab32); dfree(c->reps); dfree(c->ctl); dfree(c->one);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -454,7 +514,7 @@ int md_build_neighbor_list(md_ctx *c, int32_t kind, void *stream)
     const int half = kind == MD_LIST_HALF;
     int rcode = ensure_list_capacity(c, c->pos[c->cur], half, s);
     if (rcode != MD_OK) return rcode;
-    launch_build_list(s, c->grid_cells(4, 3), list_args(c, c->one, c->pos[c->cur], half));
+    launch_build_list(s, c->grid_tasks(0), list_args(c, c->one, c->pos[c->cur], half));
     c->have_list = true;
     c->list_kind = kind;
     return check_hip(c, "md_build_neighbor_list");
@@ -484,7 +544,7 @@ int md_compute_forces(md_ctx *c, const md_potential *p, int32_t precision, doubl
         a.eatom = c->eatom;
         a.watom = c->watom;
     }
-    const int gf = c->grid_force(256 / c->tpp);
+    const int gf = c->grid_tasks(0), gf1 = c->grid_tasks(1);
     if (p->kind == MD_POT_LJ && c->list_kind == MD_LIST_HALF) {
         launch_zero(s, c->grid_atoms(256), c->force, 3 * c->n);
         launch_lj_half(s, gf, c->tpp, mixed, a);
@@ -492,7 +552,7 @@ int md_compute_forces(md_ctx *c, const md_potential *p, int32_t precision, doubl
         launch_lj_full(s, gf, c->tpp, mixed, a);
     } else {
         launch_eam_density(s, gf, c->tpp, mixed, a);
-        launch_eam_force(s, gf, c->tpp, mixed, a);
+        launch_eam_force(s, gf1, c->tpp, mixed, a);
     }
     if (c->R > 1 && (energy != nullptr || virial != nullptr))
         launch_replica_sums(s, c->R, c->reps, c->eatom, c->watom, energy, virial);
@@ -533,13 +593,13 @@ int md_verlet_step(md_ctx *c, const md_potential *p, int32_t precision, int32_t 
         la.vel_dst = c->vel;
         la.id_dst = c->id;
         la.xref = c->xref;
-        launch_build_list(s, c->grid_cells(4, 3), la);
+        launch_build_list(s, c->grid_tasks(0), la);
     }
     c->have_list = true;
     c->list_kind = kind;
     hipLaunchKernelGGL(k_set_ctl, dim3(1), dim3(64), 0, s, c->ctl, 0, 1);   // count in-run rebuilds only
 
-    const int gf = c->grid_force(256 / c->tpp);
+    const int gf = c->grid_tasks(0), gf1 = c->grid_tasks(1);
     auto forces_and_step = [&](int mode, int32_t *clear, int32_t *set, double *h) {
         ForceArgs a = force_args(c, p);
         a.mode = mode;
@@ -565,21 +625,25 @@ int md_verlet_step(md_ctx *c, const md_potential *p, int32_t precision, int32_t 
             f.outW = mode >= 2 ? a.outW : nullptr;
             f.done = &c->ctl->done[1];
             f.partial = c->partial + (size_t)c->max_grid() * 4;
-            launch_lj_half(s, gf, c->tpp, mixed, f);
             ForceArgs g = a;
             g.outE = nullptr;
             g.outW = nullptr;
             g.outK = mode >= 2 ? a.outK : nullptr;
             g.done = &c->ctl->done[2];
             g.partial = c->partial + (size_t)c->max_grid() * 8;
-            launch_integrate(s, ga, g);
+            timed(c, s, c->ev_force, [&] {
+                launch_lj_half(s, gf, c->tpp, mixed, f);
+                launch_integrate(s, ga, g);
+            });
         } else if (p->kind == MD_POT_LJ) {
             if (mode == 1) a.outE = a.outK = a.outW = nullptr;
-            launch_lj_full(s, gf, c->tpp, mixed, a);
+            timed(c, s, c->ev_force, [&] { launch_lj_full(s, gf, c->tpp, mixed, a); });
         } else {
             if (mode == 1) a.outE = a.outK = a.outW = nullptr;
-            launch_eam_density(s, gf, c->tpp, mixed, a);
-            launch_eam_force(s, gf, c->tpp, mixed, a);
+            timed(c, s, c->ev_force, [&] {
+                launch_eam_density(s, gf, c->tpp, mixed, a);
+                launch_eam_force(s, gf1, c->tpp, mixed, a);
+            });
         }
     };
 
@@ -597,7 +661,7 @@ int md_verlet_step(md_ctx *c, const md_potential *p, int32_t precision, int32_t 
         la.vel_dst = c->vel;
         la.id_dst = c->id;
         la.xref = c->xref;
-        launch_build_list(s, c->grid_cells(4, 3), la);
+        timed(c, s, c->ev_list, [&] { launch_build_list(s, c->grid_tasks(0), la); });
         const int mode = st < n_steps ? 2 : 3;
         forces_and_step(mode, pred, &c->ctl->rebuild[(st + 1) & 1],
                         hist != nullptr ? hist + 3 * (int64_t)(st - 1) : nullptr);
@@ -637,7 +701,7 @@ int md_force_vjp(md_ctx *c, const md_potential *p, int32_t precision, const doub
     v.gpart = c->partial + (size_t)c->max_grid() * 12;
     v.rdot = c->rdot;
     v.fpp = c->fpp;
-    const int gf = c->grid_force(256 / c->tpp);
+    const int gf = c->grid_tasks(0);
     if (p->kind == MD_POT_LJ) {
         v.gout = g_params;
         launch_lj_vjp(s, gf, c->tpp, false, v);
@@ -682,22 +746,63 @@ int64_t md_get_neighbor_list(md_ctx *c, int64_t *start, int32_t *nbr, int64_t ca
     if (!c->have_list) return fail(c, MD_ERR_STATE, "no list");
     if (hipStreamSynchronize(c->last) != hipSuccess) return fail(c, MD_ERR_HIP, "synchronise");
     const int64_t n = c->n;
-    std::vector<int32_t> cnt(n), id(n);
+    std::vector<int32_t> cnt(n), id(n), cs(c->C + 1);
     std::vector<uint32_t> rows((size_t)(n * c->M));
     if (hipMemcpy(cnt.data(), c->cnt, sizeof(int32_t) * n, hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(id.data(), c->id, sizeof(int32_t) * n, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(cs.data(), c->start, sizeof(int32_t) * (c->C + 1), hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(rows.data(), c->nbr, sizeof(uint32_t) * rows.size(), hipMemcpyDeviceToHost) != hipSuccess)
         return fail(c, MD_ERR_HIP, "list readback");
-    std::vector<int64_t> len(n, 0);
-    for (int64_t i = 0; i < n; i++) len[id[i]] = std::min(cnt[i], c->M);
+    // walk the cells exactly as the cell tasks do: neighbourhood order, one row
+    // of capacity M per sorted atom
+    std::vector<int64_t> len(n, 0), row0(n, 0);
+    std::vector<int32_t> soff_all((size_t)c->C * 28), sbeg_all((size_t)c->C * 28);
+    for (int32_t r = 0; r < c->R; r++) {
+        const RepDesc &d = c->reps_h[r];
+        const int64_t ncell = (int64_t)d.nc[0] * d.nc[1] * d.nc[2];
+        for (int64_t lc = 0; lc < ncell; lc++) {
+            const int64_t cell = d.cell_off + lc;
+            const int32_t cx = (int32_t)(lc % d.nc[0]), cy = (int32_t)((lc / d.nc[0]) % d.nc[1]);
+            const int32_t cz = (int32_t)(lc / ((int64_t)d.nc[0] * d.nc[1]));
+            int64_t nb[27];
+            int32_t run = 0;
+            int32_t *soff = &soff_all[(size_t)cell * 28], *sbeg = &sbeg_all[(size_t)cell * 28];
+            for (int s = 0; s < 27; s++) {
+                const int32_t x = (cx + s % 3 - 1 + d.nc[0]) % d.nc[0];
+                const int32_t y = (cy + (s / 3) % 3 - 1 + d.nc[1]) % d.nc[1];
+                const int32_t z = (cz + s / 9 - 1 + d.nc[2]) % d.nc[2];
+                nb[s] = d.cell_off + x + (int64_t)d.nc[0] * (y + (int64_t)d.nc[1] * z);
+                bool dup = false;
+                for (int k = 0; k < s; k++) dup |= nb[k] == nb[s];
+                soff[s] = run;
+                sbeg[s] = dup ? 0 : cs[nb[s]];
+                if (!dup) run += cs[nb[s] + 1] - cs[nb[s]];
+            }
+            soff[27] = run;
+            for (int32_t i = cs[cell]; i < cs[cell + 1]; i++) {
+                len[id[i]] = std::min<int64_t>(cnt[i], c->M);
+                row0[i] = (int64_t)i * c->M;
+            }
+        }
+    }
     start[0] = 0;
     for (int64_t u = 0; u < n; u++) start[u + 1] = start[u] + len[u];
     const int64_t total = start[n];
     if (nbr == nullptr || total > capacity) return total;
+    // cell of each sorted atom, to find its neighbourhood
+    std::vector<int64_t> cell_of_atom(n);
+    for (int64_t cell = 0; cell < c->C; cell++)
+        for (int32_t i = cs[cell]; i < cs[cell + 1]; i++) cell_of_atom[i] = cell;
     for (int64_t i = 0; i < n; i++) {
         const int64_t u = id[i];
-        for (int64_t k = 0; k < len[u]; k++)
-            nbr[start[u] + k] = id[rows[(size_t)(i * c->M + k)] & MD_IDX_MASK];
+        const int32_t *soff = &soff_all[(size_t)cell_of_atom[i] * 28];
+        const int32_t *sbeg = &sbeg_all[(size_t)cell_of_atom[i] * 28];
+        for (int64_t k = 0; k < len[u]; k++) {
+            const int32_t g = (int32_t)(rows[(size_t)(row0[i] + k)] & MD_IDX_MASK);
+            int s = 26;
+            while (s > 0 && soff[s] > g) s--;
+            nbr[start[u] + k] = id[sbeg[s] + (g - soff[s])];
+        }
     }
     return total;
 }
@@ -718,24 +823,61 @@ int md_get_cells(md_ctx *c, int32_t *cell_start, int32_t *order, int64_t *ncells
 int md_set_tuning(md_ctx *c, int32_t key, int32_t value)
 {
     if (c == nullptr) return MD_ERR_ARG;
-    if (key == 0 && (value == 4 || value == 8 || value == 16 || value == 32)) {
-        c->tpp = value;
+    if (key == 0 && value >= 64 && value <= 2048 && value % 64 == 0 && value <= cap_limit(c)) {
+        c->cap = value;
         return MD_OK;
     }
-    if (key == 1 && value >= 1 && value <= 16) {
+    if (key == 1 && value >= 1 && value <= 8) {
         c->wgpc = value;
         return MD_OK;
     }
     if (key == 2 && value >= 1 && value <= 4096) {
         // fixed per-atom list capacity (tests of the overflow path force a small one)
         if (hipDeviceSynchronize() != hipSuccess) return fail(c, MD_ERR_HIP, "synchronise");
-        if (!dalloc(&c->nbr, (size_t)value * (size_t)c->n)) return fail(c, MD_ERR_HIP, "list: out of device memory");
-        c->M = value;
+        const int32_t m = (value + 7) / 8 * 8;
+        if (!dalloc(&c->nbr, (size_t)m * (size_t)c->n)) return fail(c, MD_ERR_HIP, "list: out of device memory");
+        c->M = m;
         c->need_M = 0;
         c->have_list = false;
         return MD_OK;
     }
-    return fail(c, MD_ERR_ARG, "tuning: key 0 in {4, 8, 16, 32}, key 1 in 1..16, key 2 in 1..4096");
+    return fail(c, MD_ERR_ARG, "tuning: key 0 in 64..2048 (multiple of 64), key 1 in 1..8, key 2 in 1..4096");
+}
+
+int md_profile(md_ctx *c, int32_t enable, double *force_ms, int64_t *force_n, double *list_ms,
+               int64_t *list_n)
+{
+    if (c == nullptr) return MD_ERR_ARG;
+    if (enable) {
+        if (c->last != nullptr && hipStreamSynchronize(c->last) != hipSuccess)
+            return fail(c, MD_ERR_HIP, "synchronise");
+        c->ev_force.clear();
+        c->ev_list.clear();
+        c->ev_used = 0;
+        c->prof = true;
+        return MD_OK;
+    }
+    c->prof = false;
+    if (c->last != nullptr && hipStreamSynchronize(c->last) != hipSuccess) return fail(c, MD_ERR_HIP, "synchronise");
+    auto total = [](const std::vector<std::pair<hipEvent_t, hipEvent_t>> &v, double &ms) {
+        ms = 0.0;
+        for (auto &p : v) {
+            float t = 0.0f;
+            if (hipEventElapsedTime(&t, p.first, p.second) != hipSuccess) return false;
+            ms += (double)t;
+        }
+        return true;
+    };
+    double fm = 0.0, lm = 0.0;
+    if (!total(c->ev_force, fm) || !total(c->ev_list, lm)) return fail(c, MD_ERR_HIP, "event timing");
+    if (force_ms) *force_ms = fm;
+    if (force_n) *force_n = (int64_t)c->ev_force.size();
+    if (list_ms) *list_ms = lm;
+    if (list_n) *list_n = (int64_t)c->ev_list.size();
+    c->ev_force.clear();
+    c->ev_list.clear();
+    c->ev_used = 0;
+    return MD_OK;
 }
 
 const char *md_last_error(md_ctx *c)

@@ -23,40 +23,10 @@
 // second buffer because other groups still gather the current ones.
 #include <math.h>
 
-#include "md_internal.h"
+#include "md_nbhd.h"
 #include "md_reduce.h"
 
 namespace {
-
-__device__ __forceinline__ void apply_image(uint32_t e, double Lx, double Ly, double Lz,
-                                            double &dx, double &dy, double &dz)
-{
-    const uint32_t c = e >> MD_IDX_BITS;
-    if (c & 1u) dx = dx + Lx;
-    if (c & 2u) dx = dx - Lx;
-    if (c & 4u) dy = dy + Ly;
-    if (c & 8u) dy = dy - Ly;
-    if (c & 16u) dz = dz + Lz;
-    if (c & 32u) dz = dz - Lz;
-}
-
-__device__ __forceinline__ void atom_box(const ForceArgs &a, int64_t i, double &Lx, double &Ly,
-                                         double &Lz)
-{
-    if (a.R > 1) {
-        const RepDesc &r = a.reps[a.rep_of[i]];
-        Lx = r.L[0]; Ly = r.L[1]; Lz = r.L[2];
-    } else {
-        Lx = a.rep0.L[0]; Ly = a.rep0.L[1]; Lz = a.rep0.L[2];
-    }
-}
-
-template <int TPP>
-__device__ __forceinline__ double group_sum(double v)
-{
-    for (int o = TPP / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
 
 __device__ __forceinline__ int seg(double u, int nk)
 {
@@ -168,143 +138,150 @@ __device__ __forceinline__ void finish_block(const ForceArgs &a, double accE, do
 }
 
 // ---------------------------------------------------------------- LJ, full list
-template <int TPP, bool MIXED>
+template <bool MIXED>
 __global__ __launch_bounds__(256) void k_lj_full(ForceArgs a)
 {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ double red[TASK_THREADS];
     __shared__ double lds[16];
-    constexpr int APB = 256 / TPP;
-    const int sub = threadIdx.x % TPP, grp = threadIdx.x / TPP;
+    const Stage st = stage_slice(lds_raw, 0, a.cap, 0);
     if (a.flag_clear != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *a.flag_clear = 0;
     const double eps = a.lj[0], sig = a.lj[1];
     const double s2 = sig * sig, e4 = 4.0 * eps, e24 = 24.0 * eps;
     const float s2f = (float)s2, e4f = (float)e4, e24f = (float)e24;
     double accE = 0.0, accW = 0.0, accK = 0.0;
-    const int64_t ntiles = (a.n + APB - 1) / APB;
-    const ItemRange it = xcd_items(ntiles, 1, 0);
-    for (int64_t t = it.first; t < it.end; t += it.stride) {
-        const int64_t i = t * APB + grp;
-        const bool valid = i < a.n;
+    CELL_TASK_BEGIN(nullptr)
         double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0, w = 0.0;
         double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
-        if (valid) {
-            xi = a.pos[i];
-            double Lx, Ly, Lz;
-            atom_box(a, i, Lx, Ly, Lz);
-            const int32_t m = a.cnt[i] < a.M ? a.cnt[i] : a.M;
-            const uint32_t *row = a.nbr + i * (int64_t)a.M;
-            for (int32_t k = sub; k < m; k += TPP) {
-                const uint32_t en = row[k];
-                const double4 xj = a.pos[en & MD_IDX_MASK];
-                double dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
-                if (en >> MD_IDX_BITS) apply_image(en, Lx, Ly, Lz, dx, dy, dz);
-                const double r2 = (dx * dx + dy * dy) + dz * dz;
-                if (r2 < a.rc2) {
-                    if (MIXED) {
-                        const float ir2 = __builtin_amdgcn_rcpf((float)r2);
-                        const float q2 = s2f * ir2;
-                        const float q6 = q2 * q2 * q2;
-                        const float q12 = q6 * q6;
-                        const float fs = e24f * (2.0f * q12 - q6) * ir2;
-                        const double fsd = (double)fs;
-                        fx = fma(fsd, dx, fx);
-                        fy = fma(fsd, dy, fy);
-                        fz = fma(fsd, dz, fz);
-                        e += (double)(e4f * (q12 - q6));
-                        w += fsd * r2;
-                    } else {
-                        const double ir2 = 1.0 / r2;
-                        const double q2 = s2 * ir2;
-                        const double q6 = q2 * q2 * q2;
-                        const double q12 = q6 * q6;
-                        const double fs = e24 * (2.0 * q12 - q6) * ir2;
-                        fx = fma(fs, dx, fx);
-                        fy = fma(fs, dy, fy);
-                        fz = fma(fs, dz, fz);
-                        e += e4 * (q12 - q6);
-                        w += fs * r2;
+        if (valid) xi = a.pos[i];
+        STAGED_SPLIT(all_staged,
+        for (int32_t q = sub; q < nq; q += tpa) {
+            const uint4 ev = row4[q];
+            const uint32_t es[4] = {ev.x, ev.y, ev.z, ev.w};
+_Pragma("unroll")
+            for (int u = 0; u < 4; u++) {
+                if (4 * q + u < mm) {
+                    const uint32_t en = es[u];
+                    double xj, yj, zj;
+                    candidate_pos<STAGED>(st, (int32_t)(en & MD_IDX_MASK), a.pos, xj, yj, zj);
+                    double dx = xi.x - xj, dy = xi.y - yj, dz = xi.z - zj;
+                    if (en >> MD_IDX_BITS) apply_image_code(en, Lx, Ly, Lz, dx, dy, dz);
+                    const double r2 = (dx * dx + dy * dy) + dz * dz;
+                    if (r2 < a.rc2) {
+                        if (MIXED) {
+                            const float ir2 = __builtin_amdgcn_rcpf((float)r2);
+                            const float q2 = s2f * ir2;
+                            const float q6 = q2 * q2 * q2;
+                            const float q12 = q6 * q6;
+                            const float fs = e24f * (2.0f * q12 - q6) * ir2;
+                            const double fsd = (double)fs;
+                            fx = fma(fsd, dx, fx);
+                            fy = fma(fsd, dy, fy);
+                            fz = fma(fsd, dz, fz);
+                            e += (double)(e4f * (q12 - q6));
+                            w += fsd * r2;
+                        } else {
+                            const double ir2 = rcp64(r2);
+                            const double q2 = s2 * ir2;
+                            const double q6 = q2 * q2 * q2;
+                            const double q12 = q6 * q6;
+                            const double fs = e24 * (2.0 * q12 - q6) * ir2;
+                            fx = fma(fs, dx, fx);
+                            fy = fma(fs, dy, fy);
+                            fz = fma(fs, dz, fz);
+                            e += e4 * (q12 - q6);
+                            w += fs * r2;
+                        }
                     }
                 }
             }
         }
-        fx = group_sum<TPP>(fx);
-        fy = group_sum<TPP>(fy);
-        fz = group_sum<TPP>(fz);
-        e = group_sum<TPP>(e);
-        w = group_sum<TPP>(w);
+        )
+        double gv[5] = {fx, fy, fz, e, w};
+        task_group_sum(gv, tpa, am, red);
+        fx = gv[0];
+        fy = gv[1];
+        fz = gv[2];
+        e = gv[3];
+        w = gv[4];
         if (valid && sub == 0) finish_atom(a, i, xi, fx, fy, fz, 0.5 * e, 0.5 * w, accE, accW, accK);
-    }
+    CELL_TASK_END
     finish_block(a, accE, accW, accK, lds);
 }
 
 // ---------------------------------------------------------------- LJ, half list + atomics
-template <int TPP, bool MIXED>
+template <bool MIXED>
 __global__ __launch_bounds__(256) void k_lj_half(ForceArgs a)
 {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ double red[TASK_THREADS];
     __shared__ double lds[16];
-    constexpr int APB = 256 / TPP;
-    const int sub = threadIdx.x % TPP, grp = threadIdx.x / TPP;
+    const Stage st = stage_slice(lds_raw, 0, a.cap, 0);
     const double eps = a.lj[0], sig = a.lj[1];
     const double s2 = sig * sig, e4 = 4.0 * eps, e24 = 24.0 * eps;
     const float s2f = (float)s2, e4f = (float)e4, e24f = (float)e24;
     const int64_t n = a.n;
     double accE = 0.0, accW = 0.0;
-    const int64_t ntiles = (n + APB - 1) / APB;
-    const ItemRange it = xcd_items(ntiles, 1, 0);
-    for (int64_t t = it.first; t < it.end; t += it.stride) {
-        const int64_t i = t * APB + grp;
-        const bool valid = i < n;
+    CELL_TASK_BEGIN(nullptr)
         double fx = 0.0, fy = 0.0, fz = 0.0;
-        if (valid) {
-            const double4 xi = a.pos[i];
-            double Lx, Ly, Lz;
-            atom_box(a, i, Lx, Ly, Lz);
-            const int32_t m = a.cnt[i] < a.M ? a.cnt[i] : a.M;
-            const uint32_t *row = a.nbr + i * (int64_t)a.M;
-            for (int32_t k = sub; k < m; k += TPP) {
-                const uint32_t en = row[k];
-                const int64_t j = en & MD_IDX_MASK;
-                const double4 xj = a.pos[j];
-                double dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
-                if (en >> MD_IDX_BITS) apply_image(en, Lx, Ly, Lz, dx, dy, dz);
-                const double r2 = (dx * dx + dy * dy) + dz * dz;
-                if (r2 < a.rc2) {
-                    double fs, V;
-                    if (MIXED) {
-                        const float ir2 = __builtin_amdgcn_rcpf((float)r2);
-                        const float q2 = s2f * ir2;
-                        const float q6 = q2 * q2 * q2;
-                        const float q12 = q6 * q6;
-                        fs = (double)(e24f * (2.0f * q12 - q6) * ir2);
-                        V = (double)(e4f * (q12 - q6));
-                    } else {
-                        const double ir2 = 1.0 / r2;
-                        const double q2 = s2 * ir2;
-                        const double q6 = q2 * q2 * q2;
-                        const double q12 = q6 * q6;
-                        fs = e24 * (2.0 * q12 - q6) * ir2;
-                        V = e4 * (q12 - q6);
+        double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (valid) xi = a.pos[i];
+        STAGED_SPLIT(all_staged,
+        for (int32_t q = sub; q < nq; q += tpa) {
+            const uint4 ev = row4[q];
+            const uint32_t es[4] = {ev.x, ev.y, ev.z, ev.w};
+_Pragma("unroll")
+            for (int u = 0; u < 4; u++) {
+                if (4 * q + u < mm) {
+                    const uint32_t en = es[u];
+                    double xj, yj, zj;
+                    int32_t j;
+                    candidate<STAGED>(st, (int32_t)(en & MD_IDX_MASK), a.pos, xj, yj, zj, j);
+                    double dx = xi.x - xj, dy = xi.y - yj, dz = xi.z - zj;
+                    if (en >> MD_IDX_BITS) apply_image_code(en, Lx, Ly, Lz, dx, dy, dz);
+                    const double r2 = (dx * dx + dy * dy) + dz * dz;
+                    if (r2 < a.rc2) {
+                        double fs, V;
+                        if (MIXED) {
+                            const float ir2 = __builtin_amdgcn_rcpf((float)r2);
+                            const float q2 = s2f * ir2;
+                            const float q6 = q2 * q2 * q2;
+                            const float q12 = q6 * q6;
+                            fs = (double)(e24f * (2.0f * q12 - q6) * ir2);
+                            V = (double)(e4f * (q12 - q6));
+                        } else {
+                            const double ir2 = rcp64(r2);
+                            const double q2 = s2 * ir2;
+                            const double q6 = q2 * q2 * q2;
+                            const double q12 = q6 * q6;
+                            fs = e24 * (2.0 * q12 - q6) * ir2;
+                            V = e4 * (q12 - q6);
+                        }
+                        const double px = fs * dx, py = fs * dy, pz = fs * dz;
+                        fx += px;
+                        fy += py;
+                        fz += pz;
+                        atomicAdd(&a.force[j], -px);
+                        atomicAdd(&a.force[n + j], -py);
+                        atomicAdd(&a.force[2 * n + j], -pz);
+                        accE += V;
+                        accW += fs * r2;
                     }
-                    const double px = fs * dx, py = fs * dy, pz = fs * dz;
-                    fx += px;
-                    fy += py;
-                    fz += pz;
-                    atomicAdd(&a.force[j], -px);
-                    atomicAdd(&a.force[n + j], -py);
-                    atomicAdd(&a.force[2 * n + j], -pz);
-                    accE += V;
-                    accW += fs * r2;
                 }
             }
         }
-        fx = group_sum<TPP>(fx);
-        fy = group_sum<TPP>(fy);
-        fz = group_sum<TPP>(fz);
+        )
+        double gv[3] = {fx, fy, fz};
+        task_group_sum(gv, tpa, am, red);
+        fx = gv[0];
+        fy = gv[1];
+        fz = gv[2];
         if (valid && sub == 0) {
             atomicAdd(&a.force[i], fx);
             atomicAdd(&a.force[n + i], fy);
             atomicAdd(&a.force[2 * n + i], fz);
         }
-    }
+    CELL_TASK_END
     double v[4] = {accE, accW, 0.0, 0.0};
     if (a.outE == nullptr && a.outW == nullptr) return;
     if (mdred::last_block_sum4(v, a.partial, a.done, lds) && threadIdx.x == 0) {
@@ -342,142 +319,164 @@ __global__ __launch_bounds__(256) void k_integrate(ForceArgs a)
 }
 
 // ---------------------------------------------------------------- EAM pass 1: density
-template <int TPP, bool MIXED>
+template <bool MIXED>
 __global__ __launch_bounds__(256) void k_eam_density(ForceArgs a)
 {
-    constexpr int APB = 256 / TPP;
-    const int sub = threadIdx.x % TPP, grp = threadIdx.x / TPP;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ double red[TASK_THREADS];
+    const Stage st = stage_slice(lds_raw, 0, a.cap, 0);
     const int nk = a.nk[1];
     const double x0 = a.x0[1], ih = a.inv_h[1];
-    const int64_t ntiles = (a.n + APB - 1) / APB;
-    const ItemRange it = xcd_items(ntiles, 1, 0);
-    for (int64_t t = it.first; t < it.end; t += it.stride) {
-        const int64_t i = t * APB + grp;
-        const bool valid = i < a.n;
+    CELL_TASK_BEGIN(nullptr)
         double rho = 0.0;
-        if (valid) {
-            const double4 xi = a.pos[i];
-            double Lx, Ly, Lz;
-            atom_box(a, i, Lx, Ly, Lz);
-            const int32_t m = a.cnt[i] < a.M ? a.cnt[i] : a.M;
-            const uint32_t *row = a.nbr + i * (int64_t)a.M;
-            for (int32_t k = sub; k < m; k += TPP) {
-                const uint32_t en = row[k];
-                const double4 xj = a.pos[en & MD_IDX_MASK];
-                double dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
-                if (en >> MD_IDX_BITS) apply_image(en, Lx, Ly, Lz, dx, dy, dz);
-                const double r2 = (dx * dx + dy * dy) + dz * dz;
-                if (r2 < a.rrho2) {
-                    const double u = (sqrt(r2) - x0) * ih;
-                    if (MIXED) {
-                        float f, fu;
-                        spl32(a.tabf[1], u, nk, f, fu);
-                        rho += (double)f;
-                    } else {
-                        double f, fu;
-                        spl64(a.tab[1], u, nk, f, fu);
-                        rho += f;
+        double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (valid) xi = a.pos[i];
+        STAGED_SPLIT(all_staged,
+        for (int32_t q = sub; q < nq; q += tpa) {
+            const uint4 ev = row4[q];
+            const uint32_t es[4] = {ev.x, ev.y, ev.z, ev.w};
+_Pragma("unroll")
+            for (int u = 0; u < 4; u++) {
+                if (4 * q + u < mm) {
+                    const uint32_t en = es[u];
+                    double xj, yj, zj;
+                    candidate_pos<STAGED>(st, (int32_t)(en & MD_IDX_MASK), a.pos, xj, yj, zj);
+                    double dx = xi.x - xj, dy = xi.y - yj, dz = xi.z - zj;
+                    if (en >> MD_IDX_BITS) apply_image_code(en, Lx, Ly, Lz, dx, dy, dz);
+                    const double r2 = (dx * dx + dy * dy) + dz * dz;
+                    if (r2 < a.rrho2) {
+                        const double uu = (sqrt(r2) - x0) * ih;
+                        if (MIXED) {
+                            float f, fu;
+                            spl32(a.tabf[1], uu, nk, f, fu);
+                            rho += (double)f;
+                        } else {
+                            double f, fu;
+                            spl64(a.tab[1], uu, nk, f, fu);
+                            rho += f;
+                        }
                     }
                 }
             }
         }
-        rho = group_sum<TPP>(rho);
+        )
+        double gv[1] = {rho};
+        task_group_sum(gv, tpa, am, red);
+        rho = gv[0];
         if (valid && sub == 0) {
             double F, Fp;
             embed64(a, rho, F, Fp);
             a.rho[i] = rho;
             a.fp[i] = Fp;
         }
-    }
+    CELL_TASK_END
 }
 
 // ---------------------------------------------------------------- EAM pass 2: forces
-template <int TPP, bool MIXED>
+template <bool MIXED>
 __global__ __launch_bounds__(256) void k_eam_force(ForceArgs a)
 {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ double red[TASK_THREADS];
     __shared__ double lds[16];
-    constexpr int APB = 256 / TPP;
-    const int sub = threadIdx.x % TPP, grp = threadIdx.x / TPP;
+    const Stage st = stage_slice(lds_raw, 0, a.cap, 1);
     if (a.flag_clear != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *a.flag_clear = 0;
     const int nkp = a.nk[0], nkr = a.nk[1];
     const double x0p = a.x0[0], ihp = a.inv_h[0], x0r = a.x0[1], ihr = a.inv_h[1];
     double accE = 0.0, accW = 0.0, accK = 0.0;
-    const int64_t ntiles = (a.n + APB - 1) / APB;
-    const ItemRange it = xcd_items(ntiles, 1, 0);
-    for (int64_t t = it.first; t < it.end; t += it.stride) {
-        const int64_t i = t * APB + grp;
-        const bool valid = i < a.n;
+    CELL_TASK_BEGIN(a.fp)
         double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0, w = 0.0;
         double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
+        double fpi = 0.0;
         if (valid) {
             xi = a.pos[i];
-            const double fpi = a.fp[i];
-            double Lx, Ly, Lz;
-            atom_box(a, i, Lx, Ly, Lz);
-            const int32_t m = a.cnt[i] < a.M ? a.cnt[i] : a.M;
-            const uint32_t *row = a.nbr + i * (int64_t)a.M;
-            for (int32_t k = sub; k < m; k += TPP) {
-                const uint32_t en = row[k];
-                const int64_t j = en & MD_IDX_MASK;
-                const double4 xj = a.pos[j];
-                double dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
-                if (en >> MD_IDX_BITS) apply_image(en, Lx, Ly, Lz, dx, dy, dz);
-                const double r2 = (dx * dx + dy * dy) + dz * dz;
-                const bool in_phi = r2 < a.rphi2, in_rho = r2 < a.rrho2;
-                if (in_phi || in_rho) {
-                    const double r = sqrt(r2);
-                    const double ir = 1.0 / r;
-                    double g, ep;
-                    if (MIXED) {
-                        float gf = 0.0f, epf = 0.0f;
-                        if (in_phi) {
-                            float f, fu;
-                            spl32(a.tabf[0], (r - x0p) * ihp, nkp, f, fu);
-                            gf += fu * (float)ihp;
-                            epf += f;
-                        }
-                        if (in_rho) {
-                            float f, fu;
-                            spl32(a.tabf[1], (r - x0r) * ihr, nkr, f, fu);
-                            gf += (float)(fpi + a.fp[j]) * fu * (float)ihr;
-                        }
-                        g = (double)gf;
-                        ep = (double)epf;
+            fpi = a.fp[i];
+        }
+        STAGED_SPLIT(all_staged,
+        for (int32_t q = sub; q < nq; q += tpa) {
+            const uint4 ev = row4[q];
+            const uint32_t es[4] = {ev.x, ev.y, ev.z, ev.w};
+_Pragma("unroll")
+            for (int u = 0; u < 4; u++) {
+                if (4 * q + u < mm) {
+                    const uint32_t en = es[u];
+                    const int32_t gg = (int32_t)(en & MD_IDX_MASK);
+                    double xj, yj, zj, fpj;
+                    if (STAGED || gg < st.cap) {
+                        xj = st.x[gg];
+                        yj = st.y[gg];
+                        zj = st.z[gg];
+                        fpj = st.ex[gg];
                     } else {
-                        g = 0.0;
-                        ep = 0.0;
-                        if (in_phi) {
-                            double f, fu;
-                            spl64(a.tab[0], (r - x0p) * ihp, nkp, f, fu);
-                            g += fu * ihp;
-                            ep += f;
-                        }
-                        if (in_rho) {
-                            double f, fu;
-                            spl64(a.tab[1], (r - x0r) * ihr, nkr, f, fu);
-                            g += (fpi + a.fp[j]) * (fu * ihr);
-                        }
+                        const int32_t j = nbhd_index(*st.L, gg);
+                        const double4 p = a.pos[j];
+                        xj = p.x;
+                        yj = p.y;
+                        zj = p.z;
+                        fpj = a.fp[j];
                     }
-                    const double gr = g * ir;
-                    fx = fma(-gr, dx, fx);
-                    fy = fma(-gr, dy, fy);
-                    fz = fma(-gr, dz, fz);
-                    e += ep;
-                    w -= g * r;
+                    double dx = xi.x - xj, dy = xi.y - yj, dz = xi.z - zj;
+                    if (en >> MD_IDX_BITS) apply_image_code(en, Lx, Ly, Lz, dx, dy, dz);
+                    const double r2 = (dx * dx + dy * dy) + dz * dz;
+                    const bool in_phi = r2 < a.rphi2, in_rho = r2 < a.rrho2;
+                    if (in_phi || in_rho) {
+                        const double r = sqrt(r2);
+                        const double ir = rcp64(r);
+                        double gsc, ep;
+                        if (MIXED) {
+                            float gf = 0.0f, epf = 0.0f;
+                            if (in_phi) {
+                                float f, fu;
+                                spl32(a.tabf[0], (r - x0p) * ihp, nkp, f, fu);
+                                gf += fu * (float)ihp;
+                                epf += f;
+                            }
+                            if (in_rho) {
+                                float f, fu;
+                                spl32(a.tabf[1], (r - x0r) * ihr, nkr, f, fu);
+                                gf += (float)(fpi + fpj) * fu * (float)ihr;
+                            }
+                            gsc = (double)gf;
+                            ep = (double)epf;
+                        } else {
+                            gsc = 0.0;
+                            ep = 0.0;
+                            if (in_phi) {
+                                double f, fu;
+                                spl64(a.tab[0], (r - x0p) * ihp, nkp, f, fu);
+                                gsc += fu * ihp;
+                                ep += f;
+                            }
+                            if (in_rho) {
+                                double f, fu;
+                                spl64(a.tab[1], (r - x0r) * ihr, nkr, f, fu);
+                                gsc += (fpi + fpj) * (fu * ihr);
+                            }
+                        }
+                        const double gr = gsc * ir;
+                        fx = fma(-gr, dx, fx);
+                        fy = fma(-gr, dy, fy);
+                        fz = fma(-gr, dz, fz);
+                        e += ep;
+                        w -= gsc * r;
+                    }
                 }
             }
         }
-        fx = group_sum<TPP>(fx);
-        fy = group_sum<TPP>(fy);
-        fz = group_sum<TPP>(fz);
-        e = group_sum<TPP>(e);
-        w = group_sum<TPP>(w);
+        )
+        double gv[5] = {fx, fy, fz, e, w};
+        task_group_sum(gv, tpa, am, red);
+        fx = gv[0];
+        fy = gv[1];
+        fz = gv[2];
+        e = gv[3];
+        w = gv[4];
         if (valid && sub == 0) {
             double F, Fp;
             embed64(a, a.rho[i], F, Fp);
             finish_atom(a, i, xi, fx, fy, fz, F + 0.5 * e, 0.5 * w, accE, accW, accK);
         }
-    }
+    CELL_TASK_END
     finish_block(a, accE, accW, accK, lds);
 }
 
@@ -563,41 +562,40 @@ __global__ __launch_bounds__(256) void k_replica_sums(const RepDesc *__restrict_
     }
 }
 
-#define MD_TPP_SWITCH(KERNEL, MIXED_, ...)                                                   \
-    switch (tpp) {                                                                           \
-    case 4: hipLaunchKernelGGL((KERNEL<4, MIXED_>), __VA_ARGS__); break;                      \
-    case 8: hipLaunchKernelGGL((KERNEL<8, MIXED_>), __VA_ARGS__); break;                      \
-    case 16: hipLaunchKernelGGL((KERNEL<16, MIXED_>), __VA_ARGS__); break;                    \
-    default: hipLaunchKernelGGL((KERNEL<32, MIXED_>), __VA_ARGS__); break;                    \
-    }
-
-#define MD_LAUNCH_TPP(KERNEL)                                                                \
-    if (mixed) {                                                                             \
-        MD_TPP_SWITCH(KERNEL, true, dim3(grid), dim3(256), 0, s, a)                          \
-    } else {                                                                                 \
-        MD_TPP_SWITCH(KERNEL, false, dim3(grid), dim3(256), 0, s, a)                         \
+#define MD_LAUNCH_CELLS(KERNEL, EXTRA)                                                     \
+    const size_t lds = nbhd_lds_bytes(a.cap, EXTRA);                                \
+    if (mixed) {                                                                            \
+        allow_lds(KERNEL<true>, lds);                                                       \
+        hipLaunchKernelGGL((KERNEL<true>), dim3(grid), dim3(256), lds, s, a);               \
+    } else {                                                                                \
+        allow_lds(KERNEL<false>, lds);                                                      \
+        hipLaunchKernelGGL((KERNEL<false>), dim3(grid), dim3(256), lds, s, a);              \
     }
 
 } // namespace
 
 void launch_lj_full(hipStream_t s, int grid, int tpp, bool mixed, const ForceArgs &a)
 {
-    MD_LAUNCH_TPP(k_lj_full)
+    (void)tpp;
+    MD_LAUNCH_CELLS(k_lj_full, 0)
 }
 
 void launch_lj_half(hipStream_t s, int grid, int tpp, bool mixed, const ForceArgs &a)
 {
-    MD_LAUNCH_TPP(k_lj_half)
+    (void)tpp;
+    MD_LAUNCH_CELLS(k_lj_half, 0)
 }
 
 void launch_eam_density(hipStream_t s, int grid, int tpp, bool mixed, const ForceArgs &a)
 {
-    MD_LAUNCH_TPP(k_eam_density)
+    (void)tpp;
+    MD_LAUNCH_CELLS(k_eam_density, 0)
 }
 
 void launch_eam_force(hipStream_t s, int grid, int tpp, bool mixed, const ForceArgs &a)
 {
-    MD_LAUNCH_TPP(k_eam_force)
+    (void)tpp;
+    MD_LAUNCH_CELLS(k_eam_force, 1)
 }
 
 void launch_integrate(hipStream_t s, int grid, const ForceArgs &a)

@@ -6,9 +6,11 @@
 //   force    double[3][N]
 //   xref     double4[N]  positions at the last list build
 //   id       int32[N]    user index of each sorted slot
-//   nbr      uint32[N][M] per-atom rows of the Verlet list (capacity M), entry =
-//            sorted index j (low 26 bits) | image code (high 6 bits, 2 per axis:
-//            01 = add L, 10 = subtract L) fixed when the list is built
+//   nbr      uint32[N*M] Verlet list, one contiguous segment per cell (rows of
+//            the cell's atoms back to back, each padded to 4 entries); entry =
+//            candidate index in the cell's neighbourhood (low 26 bits) | image
+//            code (high 6 bits, 2 per axis: 01 = add L, 10 = subtract L) fixed
+//            when the list is built
 //   cnt      int32[N]    list length of each atom
 // Positions are wrapped into [0, L) when the cells are built; between builds they
 // move freely and each pair uses the image fixed at build time (exact as long as
@@ -46,6 +48,8 @@ struct DevCtl {
     int32_t max_cnt;      // largest per-atom list length of the last build
     int32_t max_cell;     // largest cell occupancy of the last build
     int32_t nrebuild;     // rebuilds performed inside md_verlet_step
+    int32_t max_nbhd;     // largest cell-task neighbourhood (candidates) seen
+    int32_t pad;
     uint32_t done[4];     // last-block counters (one per reduction site)
 };
 
@@ -83,6 +87,7 @@ struct ListArgs {
     int32_t M;
     double rl2;
     int half;
+    int32_t cap;              // candidates staged in LDS per cell task
     // optional copy of the freshly sorted state into the working buffers
     const double *vel_src;
     const int32_t *id_src;
@@ -109,6 +114,9 @@ struct ForceArgs {
     const uint32_t *nbr;
     const int32_t *cnt;
     int32_t M;
+    int64_t C;                // cells
+    const int32_t *start;     // cell_start[C+1]
+    int32_t cap;              // candidates staged in LDS per cell task
     double rc2;
     const double *lj;         // device {eps, sigma}
     // EAM

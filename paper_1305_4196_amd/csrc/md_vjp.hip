@@ -14,45 +14,16 @@
 //        g = phi' + (F'_i + F'_j) rho';  table coefficient (k, p) gradients are
 //        histograms over pairs (phi, rho) and atoms (embedding) of t^p and
 //        p t^(p-1)/h weights.
-// The full list visits every pair from both atoms, so position terms need no
-// atomics; pair parameter terms are taken once per pair (j after i).  The
-// adjoint always evaluates in binary64.
+// The kernels are cell tasks like the force kernels (md_nbhd.h).  The full list
+// visits every pair from both atoms, so position terms need no atomics; pair
+// parameter terms are taken once per pair (j after i).  The adjoint always
+// evaluates in binary64.
 #include <math.h>
 
-#include "md_internal.h"
+#include "md_nbhd.h"
 #include "md_reduce.h"
 
 namespace {
-
-__device__ __forceinline__ void apply_image(uint32_t e, double Lx, double Ly, double Lz,
-                                            double &dx, double &dy, double &dz)
-{
-    const uint32_t c = e >> MD_IDX_BITS;
-    if (c & 1u) dx = dx + Lx;
-    if (c & 2u) dx = dx - Lx;
-    if (c & 4u) dy = dy + Ly;
-    if (c & 8u) dy = dy - Ly;
-    if (c & 16u) dz = dz + Lz;
-    if (c & 32u) dz = dz - Lz;
-}
-
-__device__ __forceinline__ void atom_box(const ForceArgs &a, int64_t i, double &Lx, double &Ly,
-                                         double &Lz)
-{
-    if (a.R > 1) {
-        const RepDesc &r = a.reps[a.rep_of[i]];
-        Lx = r.L[0]; Ly = r.L[1]; Lz = r.L[2];
-    } else {
-        Lx = a.rep0.L[0]; Ly = a.rep0.L[1]; Lz = a.rep0.L[2];
-    }
-}
-
-template <int TPP>
-__device__ __forceinline__ double group_sum(double v)
-{
-    for (int o = TPP / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
 
 // row k, t and value / d/du / d2/du2 of a binary64 table at u
 __device__ __forceinline__ void spl_full(const double *tab, double u, int nk, int &k, double &t,
@@ -95,41 +66,44 @@ __device__ __forceinline__ void embed_full(const ForceArgs &a, double rho, doubl
 }
 
 // ---------------------------------------------------------------- LJ
-template <int TPP>
 __global__ __launch_bounds__(256) void k_lj_vjp(VjpArgs v)
 {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ double red[TASK_THREADS];
     __shared__ double lds[16];
     const ForceArgs &a = v.f;
-    constexpr int APB = 256 / TPP;
-    const int sub = threadIdx.x % TPP, grp = threadIdx.x / TPP;
+    const Stage st = stage_slice(lds_raw, 0, a.cap, 0);
     const int64_t n = a.n;
     const double eps = a.lj[0], sig = a.lj[1];
     const double s2 = sig * sig;
     double acc_e = 0.0, acc_s = 0.0;
-    const int64_t ntiles = (n + APB - 1) / APB;
-    const ItemRange it = xcd_items(ntiles, 1, 0);
-    for (int64_t t = it.first; t < it.end; t += it.stride) {
-        const int64_t i = t * APB + grp;
-        const bool valid = i < n;
+    CELL_TASK_BEGIN(nullptr)
         double F[3] = {0.0, 0.0, 0.0}, Hu[3] = {0.0, 0.0, 0.0};
         double vE = 0.0;
+        double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
+        double ui[3] = {0.0, 0.0, 0.0};
         if (valid) {
-            const double4 xi = a.pos[i];
-            const double ui[3] = {v.u[i], v.u[n + i], v.u[2 * n + i]};
-            vE = v.vE[a.R > 1 ? a.rep_of[i] : 0];
-            double Lx, Ly, Lz;
-            atom_box(a, i, Lx, Ly, Lz);
-            const int32_t m = a.cnt[i] < a.M ? a.cnt[i] : a.M;
-            const uint32_t *row = a.nbr + i * (int64_t)a.M;
-            for (int32_t k = sub; k < m; k += TPP) {
-                const uint32_t en = row[k];
-                const int64_t j = en & MD_IDX_MASK;
-                const double4 xj = a.pos[j];
-                double d[3] = {xi.x - xj.x, xi.y - xj.y, xi.z - xj.z};
-                if (en >> MD_IDX_BITS) apply_image(en, Lx, Ly, Lz, d[0], d[1], d[2]);
+            xi = a.pos[i];
+            ui[0] = v.u[i];
+            ui[1] = v.u[n + i];
+            ui[2] = v.u[2 * n + i];
+            vE = v.vE[g_.r];
+        }
+        STAGED_SPLIT(all_staged,
+        for (int32_t q = sub; q < nq; q += tpa) {
+            const uint4 ev = row4[q];
+            const uint32_t es[4] = {ev.x, ev.y, ev.z, ev.w};
+            for (int uu = 0; uu < 4; uu++) {
+                if (4 * q + uu >= mm) break;
+                const uint32_t en = es[uu];
+                double xj, yj, zj;
+                int32_t j;
+                candidate<STAGED>(st, (int32_t)(en & MD_IDX_MASK), a.pos, xj, yj, zj, j);
+                double d[3] = {xi.x - xj, xi.y - yj, xi.z - zj};
+                if (en >> MD_IDX_BITS) apply_image_code(en, Lx, Ly, Lz, d[0], d[1], d[2]);
                 const double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
                 if (!(r2 < a.rc2)) continue;
-                const double ir2 = 1.0 / r2;
+                const double ir2 = rcp64(r2);
                 const double q2 = s2 * ir2;
                 const double q6 = q2 * q2 * q2;
                 const double q12 = q6 * q6;
@@ -138,9 +112,9 @@ __global__ __launch_bounds__(256) void k_lj_vjp(VjpArgs v)
                 const double C = 96.0 * eps * (7.0 * q12 - 2.0 * q6) * (ir2 * ir2);
                 const double uij[3] = {ui[0] - v.u[j], ui[1] - v.u[n + j], ui[2] - v.u[2 * n + j]};
                 const double du = (d[0] * uij[0] + d[1] * uij[1]) + d[2] * uij[2];
-                for (int c = 0; c < 3; c++) {
-                    F[c] = fma(fs, d[c], F[c]);
-                    Hu[c] += B * uij[c] + C * du * d[c];
+                for (int k = 0; k < 3; k++) {
+                    F[k] = fma(fs, d[k], F[k]);
+                    Hu[k] += B * uij[k] + C * du * d[k];
                 }
                 // each unordered pair is visited twice: half weight
                 const double dVde = 4.0 * (q12 - q6);
@@ -151,13 +125,16 @@ __global__ __launch_bounds__(256) void k_lj_vjp(VjpArgs v)
                 acc_s += 0.5 * (vE * dVds + dufs);
             }
         }
-        for (int c = 0; c < 3; c++) {
-            F[c] = group_sum<TPP>(F[c]);
-            Hu[c] = group_sum<TPP>(Hu[c]);
+        )
+        double gv[6] = {F[0], F[1], F[2], Hu[0], Hu[1], Hu[2]};
+        task_group_sum(gv, tpa, am, red);
+        for (int k = 0; k < 3; k++) {
+            F[k] = gv[k];
+            Hu[k] = gv[3 + k];
         }
         if (valid && sub == 0)
-            for (int c = 0; c < 3; c++) v.gx[c * n + i] = -vE * F[c] - Hu[c];
-    }
+            for (int k = 0; k < 3; k++) v.gx[k * n + i] = -vE * F[k] - Hu[k];
+    CELL_TASK_END
     double s[4] = {acc_e, acc_s, 0.0, 0.0};
     if (mdred::last_block_sum4(s, v.gpart, a.done, lds) && threadIdx.x == 0 && v.gout != nullptr) {
         v.gout[0] = s[0];
@@ -166,34 +143,37 @@ __global__ __launch_bounds__(256) void k_lj_vjp(VjpArgs v)
 }
 
 // ---------------------------------------------------------------- EAM pass A
-template <int TPP>
 __global__ __launch_bounds__(256) void k_eam_vjp_a(VjpArgs v)
 {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ double red[TASK_THREADS];
     const ForceArgs &a = v.f;
-    constexpr int APB = 256 / TPP;
-    const int sub = threadIdx.x % TPP, grp = threadIdx.x / TPP;
+    const Stage st = stage_slice(lds_raw, 0, a.cap, 0);
     const int64_t n = a.n;
     const int nkr = a.nk[1];
     const double x0r = a.x0[1], ihr = a.inv_h[1];
-    const int64_t ntiles = (n + APB - 1) / APB;
-    const ItemRange it = xcd_items(ntiles, 1, 0);
-    for (int64_t t = it.first; t < it.end; t += it.stride) {
-        const int64_t i = t * APB + grp;
-        const bool valid = i < n;
+    CELL_TASK_BEGIN(nullptr)
         double rho = 0.0, rdot = 0.0;
+        double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
+        double ui[3] = {0.0, 0.0, 0.0};
         if (valid) {
-            const double4 xi = a.pos[i];
-            const double ui[3] = {v.u[i], v.u[n + i], v.u[2 * n + i]};
-            double Lx, Ly, Lz;
-            atom_box(a, i, Lx, Ly, Lz);
-            const int32_t m = a.cnt[i] < a.M ? a.cnt[i] : a.M;
-            const uint32_t *row = a.nbr + i * (int64_t)a.M;
-            for (int32_t k = sub; k < m; k += TPP) {
-                const uint32_t en = row[k];
-                const int64_t j = en & MD_IDX_MASK;
-                const double4 xj = a.pos[j];
-                double d[3] = {xi.x - xj.x, xi.y - xj.y, xi.z - xj.z};
-                if (en >> MD_IDX_BITS) apply_image(en, Lx, Ly, Lz, d[0], d[1], d[2]);
+            xi = a.pos[i];
+            ui[0] = v.u[i];
+            ui[1] = v.u[n + i];
+            ui[2] = v.u[2 * n + i];
+        }
+        STAGED_SPLIT(all_staged,
+        for (int32_t q = sub; q < nq; q += tpa) {
+            const uint4 ev = row4[q];
+            const uint32_t es[4] = {ev.x, ev.y, ev.z, ev.w};
+            for (int uu = 0; uu < 4; uu++) {
+                if (4 * q + uu >= mm) break;
+                const uint32_t en = es[uu];
+                double xj, yj, zj;
+                int32_t j;
+                candidate<STAGED>(st, (int32_t)(en & MD_IDX_MASK), a.pos, xj, yj, zj, j);
+                double d[3] = {xi.x - xj, xi.y - yj, xi.z - zj};
+                if (en >> MD_IDX_BITS) apply_image_code(en, Lx, Ly, Lz, d[0], d[1], d[2]);
                 const double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
                 if (!(r2 < a.rrho2)) continue;
                 const double r = sqrt(r2);
@@ -206,8 +186,11 @@ __global__ __launch_bounds__(256) void k_eam_vjp_a(VjpArgs v)
                 rdot += (fu * ihr) * s;
             }
         }
-        rho = group_sum<TPP>(rho);
-        rdot = group_sum<TPP>(rdot);
+        )
+        double gv[2] = {rho, rdot};
+        task_group_sum(gv, tpa, am, red);
+        rho = gv[0];
+        rdot = gv[1];
         if (valid && sub == 0) {
             double F, Fp, Fpp, tt;
             int kk;
@@ -218,43 +201,47 @@ __global__ __launch_bounds__(256) void k_eam_vjp_a(VjpArgs v)
             v.fpp[i] = Fpp;
             v.rdot[i] = rdot;
         }
-    }
+    CELL_TASK_END
 }
 
 // ---------------------------------------------------------------- EAM pass B
-template <int TPP>
 __global__ __launch_bounds__(256) void k_eam_vjp_b(VjpArgs v)
 {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ double red[TASK_THREADS];
     const ForceArgs &a = v.f;
-    constexpr int APB = 256 / TPP;
-    const int sub = threadIdx.x % TPP, grp = threadIdx.x / TPP;
+    const Stage st = stage_slice(lds_raw, 0, a.cap, 0);
     const int64_t n = a.n;
     const int nkp = a.nk[0], nkr = a.nk[1];
     const double x0p = a.x0[0], ihp = a.inv_h[0], x0r = a.x0[1], ihr = a.inv_h[1];
     double *gphi = v.gtab;
     double *grho = v.gtab + 4 * (int64_t)(nkp - 1);
-    const int64_t ntiles = (n + APB - 1) / APB;
-    const ItemRange it = xcd_items(ntiles, 1, 0);
-    for (int64_t t = it.first; t < it.end; t += it.stride) {
-        const int64_t i = t * APB + grp;
-        const bool valid = i < n;
+    CELL_TASK_BEGIN(nullptr)
         double F[3] = {0.0, 0.0, 0.0}, Hu[3] = {0.0, 0.0, 0.0};
-        double vE = 0.0;
+        double vE = 0.0, fpi = 0.0, qi = 0.0;
+        double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
+        double ui[3] = {0.0, 0.0, 0.0};
         if (valid) {
-            const double4 xi = a.pos[i];
-            const double ui[3] = {v.u[i], v.u[n + i], v.u[2 * n + i]};
-            const double fpi = a.fp[i], qi = v.fpp[i] * v.rdot[i];
-            vE = v.vE[a.R > 1 ? a.rep_of[i] : 0];
-            double Lx, Ly, Lz;
-            atom_box(a, i, Lx, Ly, Lz);
-            const int32_t m = a.cnt[i] < a.M ? a.cnt[i] : a.M;
-            const uint32_t *row = a.nbr + i * (int64_t)a.M;
-            for (int32_t k = sub; k < m; k += TPP) {
-                const uint32_t en = row[k];
-                const int64_t j = en & MD_IDX_MASK;
-                const double4 xj = a.pos[j];
-                double d[3] = {xi.x - xj.x, xi.y - xj.y, xi.z - xj.z};
-                if (en >> MD_IDX_BITS) apply_image(en, Lx, Ly, Lz, d[0], d[1], d[2]);
+            xi = a.pos[i];
+            ui[0] = v.u[i];
+            ui[1] = v.u[n + i];
+            ui[2] = v.u[2 * n + i];
+            fpi = a.fp[i];
+            qi = v.fpp[i] * v.rdot[i];
+            vE = v.vE[g_.r];
+        }
+        STAGED_SPLIT(all_staged,
+        for (int32_t q = sub; q < nq; q += tpa) {
+            const uint4 ev = row4[q];
+            const uint32_t es[4] = {ev.x, ev.y, ev.z, ev.w};
+            for (int uu = 0; uu < 4; uu++) {
+                if (4 * q + uu >= mm) break;
+                const uint32_t en = es[uu];
+                double xj, yj, zj;
+                int32_t j;
+                candidate<STAGED>(st, (int32_t)(en & MD_IDX_MASK), a.pos, xj, yj, zj, j);
+                double d[3] = {xi.x - xj, xi.y - yj, xi.z - zj};
+                if (en >> MD_IDX_BITS) apply_image_code(en, Lx, Ly, Lz, d[0], d[1], d[2]);
                 const double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
                 const bool in_phi = r2 < a.rphi2, in_rho = r2 < a.rrho2;
                 if (!in_phi && !in_rho) continue;
@@ -278,12 +265,12 @@ __global__ __launch_bounds__(256) void k_eam_vjp_b(VjpArgs v)
                     rhpp = fuu * (ihr * ihr);
                 }
                 const double Fs = fpi + a.fp[j];
-                const double g = php + Fs * rhp;
+                const double gsc = php + Fs * rhp;
                 const double gg = phpp + Fs * rhpp;
-                const double q = qi + v.fpp[j] * v.rdot[j];
-                for (int c = 0; c < 3; c++) {
-                    F[c] -= g * e[c];
-                    Hu[c] += gg * s * e[c] + (g / r) * (uij[c] - s * e[c]) + q * rhp * e[c];
+                const double qq = qi + v.fpp[j] * v.rdot[j];
+                for (int k = 0; k < 3; k++) {
+                    F[k] -= gsc * e[k];
+                    Hu[k] += gg * s * e[k] + (gsc / r) * (uij[k] - s * e[k]) + qq * rhp * e[k];
                 }
                 if (v.gtab != nullptr && j > i) {
                     if (in_phi) {
@@ -299,18 +286,21 @@ __global__ __launch_bounds__(256) void k_eam_vjp_b(VjpArgs v)
                         const double dp[4] = {0.0, 1.0, 2.0 * tr, 3.0 * t2};
                         for (int p = 0; p < 4; p++)
                             atomicAdd(&grho[4 * (int64_t)kr + p],
-                                      vE * Fs * pw[p] - (s * Fs * dp[p] * ihr + q * pw[p]));
+                                      vE * Fs * pw[p] - (s * Fs * dp[p] * ihr + qq * pw[p]));
                     }
                 }
             }
         }
-        for (int c = 0; c < 3; c++) {
-            F[c] = group_sum<TPP>(F[c]);
-            Hu[c] = group_sum<TPP>(Hu[c]);
+        )
+        double gv[6] = {F[0], F[1], F[2], Hu[0], Hu[1], Hu[2]};
+        task_group_sum(gv, tpa, am, red);
+        for (int k = 0; k < 3; k++) {
+            F[k] = gv[k];
+            Hu[k] = gv[3 + k];
         }
         if (valid && sub == 0)
-            for (int c = 0; c < 3; c++) v.gx[c * n + i] = -vE * F[c] - Hu[c];
-    }
+            for (int k = 0; k < 3; k++) v.gx[k * n + i] = -vE * F[k] - Hu[k];
+    CELL_TASK_END
 }
 
 // embedding-table gradient: one entry per atom
@@ -345,32 +335,30 @@ __global__ __launch_bounds__(256) void k_eam_vjp_embed(VjpArgs v)
     }
 }
 
-#define MD_VJP_SWITCH(KERNEL)                                                                \
-    switch (tpp) {                                                                           \
-    case 4: hipLaunchKernelGGL((KERNEL<4>), dim3(grid), dim3(256), 0, s, a); break;           \
-    case 8: hipLaunchKernelGGL((KERNEL<8>), dim3(grid), dim3(256), 0, s, a); break;           \
-    case 16: hipLaunchKernelGGL((KERNEL<16>), dim3(grid), dim3(256), 0, s, a); break;         \
-    default: hipLaunchKernelGGL((KERNEL<32>), dim3(grid), dim3(256), 0, s, a); break;         \
-    }
-
 } // namespace
 
 void launch_lj_vjp(hipStream_t s, int grid, int tpp, bool mixed, const VjpArgs &a)
 {
     (void)mixed;
-    MD_VJP_SWITCH(k_lj_vjp)
+    (void)tpp;
+    allow_lds(k_lj_vjp, nbhd_lds_bytes(a.f.cap, 0));
+    hipLaunchKernelGGL(k_lj_vjp, dim3(grid), dim3(256), nbhd_lds_bytes(a.f.cap, 0), s, a);
 }
 
 void launch_eam_vjp_a(hipStream_t s, int grid, int tpp, bool mixed, const VjpArgs &a)
 {
     (void)mixed;
-    MD_VJP_SWITCH(k_eam_vjp_a)
+    (void)tpp;
+    allow_lds(k_eam_vjp_a, nbhd_lds_bytes(a.f.cap, 0));
+    hipLaunchKernelGGL(k_eam_vjp_a, dim3(grid), dim3(256), nbhd_lds_bytes(a.f.cap, 0), s, a);
 }
 
 void launch_eam_vjp_b(hipStream_t s, int grid, int tpp, bool mixed, const VjpArgs &a)
 {
     (void)mixed;
-    MD_VJP_SWITCH(k_eam_vjp_b)
+    (void)tpp;
+    allow_lds(k_eam_vjp_b, nbhd_lds_bytes(a.f.cap, 0));
+    hipLaunchKernelGGL(k_eam_vjp_b, dim3(grid), dim3(256), nbhd_lds_bytes(a.f.cap, 0), s, a);
 }
 
 void launch_eam_vjp_embed(hipStream_t s, int grid, const VjpArgs &a)
