@@ -76,6 +76,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--cap", type=int, default=0, help="LDS candidates per cell task")
     ap.add_argument("--wgpc", type=int, default=0)
+    ap.add_argument("--brick", type=str, default="", help="brick shape bx,by,bz (cells per task)")
+    ap.add_argument("--threads", type=int, default=0, help="threads per brick task")
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None,
                     help="time one path only (for profiler runs)")
     args = ap.parse_args()
@@ -102,6 +104,11 @@ def main():
         B.md_set_tuning(sysm.ctx, 0, args.cap)
     if args.wgpc:
         B.md_set_tuning(sysm.ctx, 1, args.wgpc)
+    if args.brick:
+        bx, by, bz = (int(v) for v in args.brick.split(","))
+        B.md_set_tuning(sysm.ctx, 3, bx | by << 8 | bz << 16)
+    if args.threads:
+        B.md_set_tuning(sysm.ctx, 4, args.threads)
     pos0 = torch.tensor(w.pos, dtype=torch.float64, device="cuda")
     vel0 = torch.tensor(w.vel, dtype=torch.float64, device="cuda")
     F = torch.empty_like(pos0)
@@ -136,16 +143,22 @@ def main():
             raise RuntimeError(f"{name} run ended with status {code} (flags {flags})")
         h = hist.cpu().numpy()
         etot = h[:, 0] + h[:, 1]
+        tuning = {"brick": B.md_query(sysm.ctx, 3), "threads": B.md_query(sysm.ctx, 4),
+                  "lds_candidates": B.md_query(sysm.ctx, 0), "row_capacity": B.md_query(sysm.ctx, 2),
+                  "bricks": B.md_query(sysm.ctx, 5), "grid": B.md_query(sysm.ctx, 9),
+                  "max_halo": B.md_query(sysm.ctx, 6), "max_brick_atoms": B.md_query(sysm.ctx, 7)}
+        tuning["brick"] = "x".join(str((tuning["brick"] >> s) & 255) for s in (0, 8, 16))
         start, _ = B.md_get_neighbor_list(sysm.ctx)
         nbar = float(start[-1]) / n
         results[name] = dict(
             seconds=t1 - t0, atom_steps=n * args.steps / (t1 - t0), rebuilds=int(nreb.item()),
             force_ms_avg=fms / max(fn, 1), force_launches=fn, list_ms_total=lms, list_launches=ln,
             nbar=nbar, drift=float(np.max(np.abs(etot - etot[0])) / abs(etot[0])),
-            T_end=float(2 * h[-1, 1] / (3 * n - 3)), capacity=cap)
+            T_end=float(2 * h[-1, 1] / (3 * n - 3)), capacity=cap, tuning=tuning)
         log(f"{name}: {results[name]['atom_steps'] / 1e9:.3f} G atom-steps/s, "
             f"{1e3 * (t1 - t0) / args.steps:.3f} ms/step, force kernel {results[name]['force_ms_avg'] * 1e3:.1f} us, "
-            f"rebuilds {results[name]['rebuilds']}, nbar {nbar:.2f}, drift {results[name]['drift']:.2e}")
+            f"rebuilds {results[name]['rebuilds']}, nbar {nbar:.2f}, drift {results[name]['drift']:.2e}, "
+            f"list {lms / max(ln, 1) * 1e3:.1f} us/launch, tuning {tuning}")
 
     # force error of the mixed path against the binary64 reference on a thermal snapshot
     import oracle
@@ -201,6 +214,7 @@ def main():
         "rebuilds": r["rebuilds"],
         "mean_neighbors": round(r["nbar"], 3),
         "list_ms_total": round(r["list_ms_total"], 3),
+        "tuning": r["tuning"],
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

@@ -178,14 +178,31 @@ int64_t md_get_neighbor_list(md_ctx *ctx, int64_t *start, int32_t *nbr, int64_t 
  * Pass NULL arrays to query n_cells_total only.  Synchronises. */
 int md_get_cells(md_ctx *ctx, int32_t *cell_start, int32_t *order, int64_t *n_cells_total);
 
-/* Tuning knobs (used by the autotuner): key 0 = candidates staged in LDS per
- * cell task (64..2048, a multiple of 64; the first list build picks one from
- * the largest neighbourhood, and candidates beyond it are read from global
- * memory); key 1 = most workgroups per CU in the cell-task grids (1..8);
+/* Tuning knobs (used by the autotuner).  The kernels run one workgroup per
+ * brick of bx x by x bz cells (the cell-task blocking of Sec. II.D.2).
+ * key 0 = candidates staged in LDS per brick task (64..4096, a multiple of 64,
+ *   within the device's LDS; by default the first list build picks one from
+ *   the largest brick halo, and candidates beyond it are read from global
+ *   memory);
+ * key 1 = most workgroups per CU in the brick-task grids (1..8);
  * key 2 = fixed per-atom list capacity (1..4096, rounded up to a multiple of 8;
- * reallocates, synchronises the device and drops the current list -- a small
- * value forces the overflow path).  Returns MD_OK or MD_ERR_ARG. */
+ *   reallocates, synchronises the device and drops the current list -- a small
+ *   value forces the overflow path);
+ * key 3 = brick shape bx | by << 8 | bz << 16 (1..8 cells per axis, at most 64
+ *   cells, (bx+2)(by+2)(bz+2) <= 512), or 0 to choose it from the mean
+ *   occupancy of the non-empty cells; drops the current list;
+ * key 4 = threads per brick task (128..512, a multiple of 64), or 0 to choose
+ *   them with the shape; drops the current list.
+ * Returns MD_OK or MD_ERR_ARG. */
 int md_set_tuning(md_ctx *ctx, int32_t key, int32_t value);
+
+/* Current configuration [host out]: key 0 LDS stage (candidates), 1 workgroups
+ * per CU, 2 per-atom list capacity, 3 brick shape (bx | by << 8 | bz << 16 of
+ * replica 0), 4 threads per brick task, 5 bricks in total, 6 largest brick halo
+ * (candidates) and 7 largest brick (atoms) seen by the list builds since the
+ * sizing pass (both synchronise), 8 LDS bytes a workgroup may use, 9 workgroups
+ * of the LJ force grid.  Returns MD_OK or MD_ERR_ARG. */
+int md_query(md_ctx *ctx, int32_t key, int64_t *value);
 
 /* Kernel timing with HIP events on the stream of the timed calls.
  * enable = 1: clear the counters and, from the next call on, record an event

@@ -25,7 +25,7 @@ FLAG_OVERFLOW, FLAG_NONFINITE = 1, 2
 
 EXPORTS = ["md_create", "md_destroy", "md_build_cells", "md_build_neighbor_list",
            "md_compute_forces", "md_verlet_step", "md_force_vjp", "md_get_status",
-           "md_get_neighbor_list", "md_get_cells", "md_set_tuning", "md_profile", "md_last_error"]
+           "md_get_neighbor_list", "md_get_cells", "md_set_tuning", "md_query", "md_profile", "md_last_error"]
 
 
 class MDError(RuntimeError):
@@ -71,11 +71,12 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     L.md_get_neighbor_list.restype = i64
     L.md_get_cells.argtypes = [vp, P(i32), P(i32), P(i64)]
     L.md_set_tuning.argtypes = [vp, i32, i32]
+    L.md_query.argtypes = [vp, i32, P(i64)]
     L.md_profile.argtypes = [vp, i32, P(d), P(i64), P(d), P(i64)]
     L.md_last_error.argtypes = [vp]
     L.md_last_error.restype = C.c_char_p
     for name in ("md_build_cells", "md_build_neighbor_list", "md_compute_forces", "md_verlet_step",
-                 "md_force_vjp", "md_get_status", "md_get_cells", "md_set_tuning", "md_profile"):
+                 "md_force_vjp", "md_get_status", "md_get_cells", "md_set_tuning", "md_query", "md_profile"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -240,6 +241,12 @@ def md_get_cells(ctx: Context) -> Tuple[np.ndarray, np.ndarray]:
 
 def md_set_tuning(ctx: Context, key: int, value: int):
     _check(ctx.h, load().md_set_tuning(ctx.h, int(key), int(value)))
+
+
+def md_query(ctx: Context, key: int) -> int:
+    v = C.c_int64()
+    _check(ctx.h, load().md_query(ctx.h, int(key), C.byref(v)))
+    return int(v.value)
 
 
 def md_profile(ctx: Context, enable: bool):

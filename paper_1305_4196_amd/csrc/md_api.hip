@@ -12,7 +12,7 @@
 #include <string>
 #include <vector>
 
-#include "md_nbhd.h"
+#include "md_brick.h"
 
 namespace {
 
@@ -80,8 +80,7 @@ struct md_ctx {
     std::vector<int64_t> off;
     int n_cu = 256;
     int lds_max = 65536;   // LDS bytes a workgroup may use
-    int wgpc = 8;      // most cell-task workgroups per CU
-    int tpp = 0;       // unused: lanes per atom follow each cell's occupancy
+    int wgpc = 8;      // most brick-task workgroups per CU
     std::string err;
     hipStream_t last = nullptr;
 
@@ -93,6 +92,15 @@ struct md_ctx {
     RepDesc *reps = nullptr;
     int64_t C = 0, C_alloc = 0;
     int32_t *rep_of = nullptr;
+
+    // bricks of cells (one task each)
+    int32_t bshape[3] = {0, 0, 0};   // requested brick shape (0: chosen from the cell occupancy)
+    int32_t threads_req = 0;          // requested threads per task (0: chosen with the shape)
+    int32_t threads = 256;            // threads per brick task
+    bool bricks_valid = false;
+    int64_t B = 0, brec_alloc = 0;
+    BrickDims bd{0, 0, 0};
+    int32_t *brec = nullptr;
 
     // atoms (cell-sorted)
     double4 *pos[2] = {nullptr, nullptr};
@@ -106,7 +114,8 @@ struct md_ctx {
     // list
     bool have_list = false;
     int list_kind = MD_LIST_FULL;
-    int32_t cap = 256;       // candidates staged in LDS per cell task
+    int32_t cap = 256;       // candidates staged in LDS per brick task
+    bool cap_user = false;
     int32_t M = 0;
     int64_t need_M = 0;
     uint32_t *nbr = nullptr;
@@ -152,14 +161,18 @@ struct md_ctx {
         int64_t capg = (int64_t)n_cu * per_cu;
         return (int)std::max<int64_t>(1, std::min(g, capg));
     }
-    // persistent grid of cell tasks (one 256-thread workgroup per cell): as
+    // persistent grid of brick tasks (one 256-thread workgroup per brick): as
     // many workgroups per CU as the LDS allows (160 KiB per CU), at most wgpc
-    int grid_tasks(int extra) const
+    int grid_tasks(int nextra, bool with_j) const
     {
-        const size_t per_block = nbhd_lds_bytes(cap, extra) + 2048 + 512;
+        const size_t per_block = stage_bytes(cap, nextra, with_j, bd.stride) + 512;
         int per_cu = (int)std::min<size_t>((size_t)wgpc, std::max<size_t>(1, (160 * 1024) / per_block));
-        return grid_cells(1, per_cu);
+        per_cu = std::max(1, std::min(per_cu, 32 / (threads / 64)));   // at most 32 wavefronts per CU
+        const int64_t g = std::min<int64_t>(B, (int64_t)n_cu * per_cu);
+        return (int)std::max<int64_t>(1, g);
     }
+    // list rows are allocated in groups of 64 atoms
+    int64_t n64() const { return (n + 63) / 64 * 64; }
 };
 
 namespace {
@@ -218,6 +231,7 @@ int plan_cells(md_ctx *c, const double *boxes, double rc, double skin, hipStream
         c->C_alloc = cells;
     }
     c->C = cells;
+    c->bricks_valid = false;
     if (hipMemcpyAsync(c->reps, c->reps_h.data(), sizeof(RepDesc) * c->R, hipMemcpyHostToDevice, s) !=
             hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
@@ -246,10 +260,12 @@ ListArgs list_args(md_ctx *c, const int32_t *pred, const double4 *src, int half)
 {
     ListArgs a{};
     a.pred = pred;
-    a.C = c->C;
+    a.B = c->B;
     a.R = c->R;
     a.reps = c->reps;
     a.start = c->start;
+    a.brec = c->brec;
+    a.bd = c->bd;
     a.src = src;
     a.n = c->n;
     a.nbr = c->nbr;
@@ -262,39 +278,133 @@ ListArgs list_args(md_ctx *c, const int32_t *pred, const double4 *src, int half)
     return a;
 }
 
-// largest LDS slice (candidates, a multiple of 64) a cell task may stage with
+// largest LDS stage (candidates, a multiple of 64) a brick task may use with
 // one extra binary64 array per candidate within the per-workgroup LDS limit
 int64_t cap_limit(const md_ctx *c)
 {
-    const int64_t room = c->lds_max - 4096 - (int64_t)sizeof(NbhdLds);
-    return std::max<int64_t>(64, room / (int64_t)(3 * sizeof(double) + sizeof(int32_t) + sizeof(double)) / 64 * 64);
+    const int64_t room = c->lds_max - 4096 - 4 * (int64_t)c->bd.stride;
+    return std::max<int64_t>(64, room / (int64_t)(4 * sizeof(double)) / 64 * 64);
 }
 
-// first build: count pass, then size the rows (1.25 x the largest list + margin)
+// Brick shape and workgroup size from the mean occupancy `occ` of the
+// non-empty cells: every shape of 1..4 cells per axis and every workgroup of
+// 128..512 threads is scored by the lanes that hold an atom (mean atoms per
+// brick over the threads of the rounds a brick of mean + 2 sqrt(mean) atoms
+// takes), the wavefronts per CU that the
+// LDS stage allows (saturating at 16) and the halo candidates staged per atom.
+void choose_shape(md_ctx *c, double occ, int32_t out[4])
+{
+    double best = -1.0;
+    for (int bz = 1; bz <= 4; bz++)
+        for (int by = 1; by <= 4; by++)
+            for (int bx = 1; bx <= 4; bx++)
+                for (int T = 128; T <= TASK_MAX_THREADS; T += 64) {
+                    const double cells = bx * by * bz, halo = (bx + 2) * (by + 2) * (bz + 2);
+                    const double atoms = occ * cells;
+                    // rounds of T lanes for a brick two standard deviations above the mean
+                    const double rounds = std::ceil((atoms + 2.0 * std::sqrt(atoms)) / T);
+                    const double eff = atoms / (rounds * T);
+                    const double lds = 24.0 * 1.1 * occ * halo + 4.0 * br_stride((int32_t)halo, (int32_t)cells) + 512;
+                    const double blocks = std::min<double>(c->wgpc, std::floor(160.0 * 1024 / lds));
+                    if (blocks < 1 || lds > c->lds_max) continue;
+                    const double waves = std::min(16.0, std::min(32.0, blocks * T / 64));
+                    const double score = eff * (waves / 16.0) * (1.0 - 0.01 * halo / cells);
+                    if (score > best + 1e-9) {
+                        best = score;
+                        out[0] = bx;
+                        out[1] = by;
+                        out[2] = bz;
+                        out[3] = T;
+                    }
+                }
+    if (best < 0) out[0] = out[1] = out[2] = 1, out[3] = 256;
+}
+
+// Bricks of every replica (shape clipped to the grid), record sizes, record buffer.
+int plan_bricks(md_ctx *c, hipStream_t s)
+{
+    int32_t shape[4] = {c->bshape[0], c->bshape[1], c->bshape[2], c->threads_req > 0 ? c->threads_req : 256};
+    if (shape[0] == 0) {
+        std::vector<int32_t> cs(c->C + 1);
+        if (hipMemcpyAsync(cs.data(), c->start, sizeof(int32_t) * (c->C + 1), hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return fail(c, MD_ERR_HIP, "brick plan: cell readback");
+        int64_t ne = 0;
+        for (int64_t k = 0; k < c->C; k++) ne += cs[k + 1] > cs[k];
+        choose_shape(c, (double)c->n / (double)std::max<int64_t>(1, ne), shape);
+        if (c->threads_req > 0) shape[3] = c->threads_req;
+    }
+    c->threads = shape[3];
+    int64_t bricks = 0;
+    int32_t Hm = 1, Em = 1;
+    for (int32_t r = 0; r < c->R; r++) {
+        RepDesc &d = c->reps_h[r];
+        int32_t H = 1, E = 1;
+        for (int k = 0; k < 3; k++) {
+            d.bd[k] = std::min(shape[k], d.nc[k]);
+            d.nb[k] = (d.nc[k] + d.bd[k] - 1) / d.bd[k];
+            H *= std::min(d.bd[k] + 2, d.nc[k]);
+            E *= d.bd[k];
+        }
+        d.brick_off = bricks;
+        bricks += (int64_t)d.nb[0] * d.nb[1] * d.nb[2];
+        Hm = std::max(Hm, H);
+        Em = std::max(Em, E);
+    }
+    c->bd.Hm = Hm;
+    c->bd.Em = Em;
+    c->bd.stride = br_stride(Hm, Em);
+    const int64_t words = bricks * (int64_t)c->bd.stride;
+    if (words > c->brec_alloc) {
+        if (!dalloc(&c->brec, words)) return fail(c, MD_ERR_HIP, "brick records: out of device memory");
+        c->brec_alloc = words;
+    }
+    c->B = bricks;
+    if (hipMemcpyAsync(c->reps, c->reps_h.data(), sizeof(RepDesc) * c->R, hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(c, MD_ERR_HIP, "replica descriptors: copy");
+    c->bricks_valid = true;
+    return MD_OK;
+}
+
+// first build: count pass, then size the lists (1.25 x the longest + margin)
+// and the LDS stage (the largest halo seen + 5 %)
 int size_list(md_ctx *c, const double4 *src, int half, hipStream_t s)
 {
+    if (!c->bricks_valid) {
+        int rc = plan_bricks(c, s);
+        if (rc != MD_OK) return rc;
+    }
+    if (!c->cap_user) c->cap = (int32_t)std::min<int64_t>(cap_limit(c), 2048);
     ListArgs a = list_args(c, c->one, src, half);
     a.M = 0;
     a.nbr = nullptr;
-    const int32_t zero2[2] = {0, 0};
-    if (hipMemcpyAsync(&c->ctl->max_cnt, &zero2[0], sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(&c->ctl->max_nbhd, &zero2[1], sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess)
+    const int32_t zero3[3] = {0, 0, 0};
+    if (hipMemcpyAsync(&c->ctl->max_cnt, &zero3[0], sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(&c->ctl->max_nbhd, &zero3[1], sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(&c->ctl->max_brick, &zero3[2], sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess)
         return fail(c, MD_ERR_HIP, "list sizing: reset");
-    launch_build_list(s, c->grid_tasks(0), a);
+    launch_build_list(s, c->grid_tasks(0, half != 0), c->threads, a);
     int32_t mx = 0, nbhd = 0;
     if (hipMemcpyAsync(&mx, &c->ctl->max_cnt, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipMemcpyAsync(&nbhd, &c->ctl->max_nbhd, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return fail(c, MD_ERR_HIP, "list sizing: readback");
-    // LDS slice: the largest neighbourhood seen plus 12 %, in multiples of 64,
-    // at most 1536 candidates (larger neighbourhoods read their overflow
-    // candidates from global memory)
-    c->cap = (int32_t)std::min<int64_t>(std::min<int64_t>(1536, cap_limit(c)),
-                                        std::max<int64_t>(64, ((int64_t)(1.12 * nbhd) + 63) / 64 * 64));
+    // LDS stage: the largest halo seen plus 5 %, in multiples of 64, within
+    // half a CU's LDS (larger halos read their last candidates from global memory)
+    if (!c->cap_user) {
+        const int64_t half_cu = ((160 * 1024) / 2 - 512 - 4 * (int64_t)c->bd.stride) / 32 / 64 * 64;
+        c->cap = (int32_t)std::max<int64_t>(
+            64, std::min<int64_t>(std::min<int64_t>(cap_limit(c), half_cu), ((int64_t)(1.05 * nbhd) + 63) / 64 * 64));
+    }
+    // rows: kept if they are already allocated and no overflow asked for more
+    if (c->M > 0 && c->need_M <= c->M) return MD_OK;
     int64_t want = std::max<int64_t>({(int64_t)ceil(1.25 * mx), (int64_t)mx + 16, c->need_M, 16});
     want = (want + 7) / 8 * 8;
-    if (want * c->n > (1ll << 40)) return fail(c, MD_ERR_ARG, "neighbour list too large");
-    if (!dalloc(&c->nbr, (size_t)(want * c->n))) return fail(c, MD_ERR_HIP, "list: out of device memory");
+    if (want * c->n64() > (1ll << 40)) return fail(c, MD_ERR_ARG, "neighbour list too large");
+    if (!dalloc(&c->nbr, (size_t)(want * c->n64()))) return fail(c, MD_ERR_HIP, "list: out of device memory");
     c->M = (int32_t)want;
     c->need_M = 0;
     return MD_OK;
@@ -302,7 +412,7 @@ int size_list(md_ctx *c, const double4 *src, int half, hipStream_t s)
 
 int ensure_list_capacity(md_ctx *c, const double4 *src, int half, hipStream_t s)
 {
-    if (c->M == 0 || c->need_M > c->M) return size_list(c, src, half, s);
+    if (!c->bricks_valid || c->M == 0 || c->need_M > c->M) return size_list(c, src, half, s);
     return MD_OK;
 }
 
@@ -322,8 +432,9 @@ ForceArgs force_args(md_ctx *c, const md_potential *p)
     a.nbr = c->nbr;
     a.cnt = c->cnt;
     a.M = c->M;
-    a.C = c->C;
-    a.start = c->start;
+    a.B = c->B;
+    a.brec = c->brec;
+    a.bd = c->bd;
     a.cap = c->cap;
     a.rc2 = p->rc * p->rc;
     a.lj = p->lj_params;
@@ -478,7 +589,7 @@ void md_destroy(md_ctx *c)
     dfree(c->pos[0]); dfree(c->pos[1]); dfree(c->pos_t); dfree(c->xref);
     dfree(c->vel); dfree(c->vel_t); dfree(c->force);
     dfree(c->id); dfree(c->id_t); dfree(c->cell_of); dfree(c->slot); dfree(c->perm);
-    dfree(c->count); dfree(c->start); dfree(c->nbr); dfree(c->cnt); dfree(c->rep_of);
+    dfree(c->count); dfree(c->start); dfree(c->nbr); dfree(c->cnt); dfree(c->rep_of); dfree(c->brec);
     dfree(c->eatom); dfree(c->watom); dfree(c->rho); dfree(c->fp); dfree(c->fpp); dfree(c->rdot);
     dfree(c->u_s); dfree(c->gx_s); dfree(c->partial); dfree(c->zeros_R);
     dfree(c->tab64); dfree(c->tab32); dfree(c->reps); dfree(c->ctl); dfree(c->one);
@@ -514,7 +625,7 @@ int md_build_neighbor_list(md_ctx *c, int32_t kind, void *stream)
     const int half = kind == MD_LIST_HALF;
     int rcode = ensure_list_capacity(c, c->pos[c->cur], half, s);
     if (rcode != MD_OK) return rcode;
-    launch_build_list(s, c->grid_tasks(0), list_args(c, c->one, c->pos[c->cur], half));
+    launch_build_list(s, c->grid_tasks(0, half != 0), c->threads, list_args(c, c->one, c->pos[c->cur], half));
     c->have_list = true;
     c->list_kind = kind;
     return check_hip(c, "md_build_neighbor_list");
@@ -544,15 +655,15 @@ int md_compute_forces(md_ctx *c, const md_potential *p, int32_t precision, doubl
         a.eatom = c->eatom;
         a.watom = c->watom;
     }
-    const int gf = c->grid_tasks(0), gf1 = c->grid_tasks(1);
+    const int gf = c->grid_tasks(0, false), gh = c->grid_tasks(0, true), gf1 = c->grid_tasks(1, false);
     if (p->kind == MD_POT_LJ && c->list_kind == MD_LIST_HALF) {
         launch_zero(s, c->grid_atoms(256), c->force, 3 * c->n);
-        launch_lj_half(s, gf, c->tpp, mixed, a);
+        launch_lj_half(s, gh, c->threads, mixed, a);
     } else if (p->kind == MD_POT_LJ) {
-        launch_lj_full(s, gf, c->tpp, mixed, a);
+        launch_lj_full(s, gf, c->threads, mixed, a);
     } else {
-        launch_eam_density(s, gf, c->tpp, mixed, a);
-        launch_eam_force(s, gf1, c->tpp, mixed, a);
+        launch_eam_density(s, gf, c->threads, mixed, a);
+        launch_eam_force(s, gf1, c->threads, mixed, a);
     }
     if (c->R > 1 && (energy != nullptr || virial != nullptr))
         launch_replica_sums(s, c->R, c->reps, c->eatom, c->watom, energy, virial);
@@ -593,13 +704,13 @@ int md_verlet_step(md_ctx *c, const md_potential *p, int32_t precision, int32_t 
         la.vel_dst = c->vel;
         la.id_dst = c->id;
         la.xref = c->xref;
-        launch_build_list(s, c->grid_tasks(0), la);
+        launch_build_list(s, c->grid_tasks(0, half != 0), c->threads, la);
     }
     c->have_list = true;
     c->list_kind = kind;
     hipLaunchKernelGGL(k_set_ctl, dim3(1), dim3(64), 0, s, c->ctl, 0, 1);   // count in-run rebuilds only
 
-    const int gf = c->grid_tasks(0), gf1 = c->grid_tasks(1);
+    const int gf = c->grid_tasks(0, false), gh = c->grid_tasks(0, true), gf1 = c->grid_tasks(1, false);
     auto forces_and_step = [&](int mode, int32_t *clear, int32_t *set, double *h) {
         ForceArgs a = force_args(c, p);
         a.mode = mode;
@@ -632,17 +743,17 @@ int md_verlet_step(md_ctx *c, const md_potential *p, int32_t precision, int32_t 
             g.done = &c->ctl->done[2];
             g.partial = c->partial + (size_t)c->max_grid() * 8;
             timed(c, s, c->ev_force, [&] {
-                launch_lj_half(s, gf, c->tpp, mixed, f);
+                launch_lj_half(s, gh, c->threads, mixed, f);
                 launch_integrate(s, ga, g);
             });
         } else if (p->kind == MD_POT_LJ) {
             if (mode == 1) a.outE = a.outK = a.outW = nullptr;
-            timed(c, s, c->ev_force, [&] { launch_lj_full(s, gf, c->tpp, mixed, a); });
+            timed(c, s, c->ev_force, [&] { launch_lj_full(s, gf, c->threads, mixed, a); });
         } else {
             if (mode == 1) a.outE = a.outK = a.outW = nullptr;
             timed(c, s, c->ev_force, [&] {
-                launch_eam_density(s, gf, c->tpp, mixed, a);
-                launch_eam_force(s, gf1, c->tpp, mixed, a);
+                launch_eam_density(s, gf, c->threads, mixed, a);
+                launch_eam_force(s, gf1, c->threads, mixed, a);
             });
         }
     };
@@ -661,7 +772,7 @@ int md_verlet_step(md_ctx *c, const md_potential *p, int32_t precision, int32_t 
         la.vel_dst = c->vel;
         la.id_dst = c->id;
         la.xref = c->xref;
-        timed(c, s, c->ev_list, [&] { launch_build_list(s, c->grid_tasks(0), la); });
+        timed(c, s, c->ev_list, [&] { launch_build_list(s, half ? gh : gf, c->threads, la); });
         const int mode = st < n_steps ? 2 : 3;
         forces_and_step(mode, pred, &c->ctl->rebuild[(st + 1) & 1],
                         hist != nullptr ? hist + 3 * (int64_t)(st - 1) : nullptr);
@@ -701,10 +812,10 @@ int md_force_vjp(md_ctx *c, const md_potential *p, int32_t precision, const doub
     v.gpart = c->partial + (size_t)c->max_grid() * 12;
     v.rdot = c->rdot;
     v.fpp = c->fpp;
-    const int gf = c->grid_tasks(0);
+    const int gh = c->grid_tasks(0, true);
     if (p->kind == MD_POT_LJ) {
         v.gout = g_params;
-        launch_lj_vjp(s, gf, c->tpp, false, v);
+        launch_lj_vjp(s, gh, c->threads, v);
     } else {
         v.gtab = g_params;
         if (g_params != nullptr) {
@@ -712,8 +823,8 @@ int md_force_vjp(md_ctx *c, const md_potential *p, int32_t precision, const doub
                             4 * (int64_t)(p->embed.n_knots - 1);
             launch_zero(s, 64, g_params, total);
         }
-        launch_eam_vjp_a(s, gf, c->tpp, false, v);
-        launch_eam_vjp_b(s, gf, c->tpp, false, v);
+        launch_eam_vjp_a(s, gh, c->threads, v);
+        launch_eam_vjp_b(s, gh, c->threads, v);
         if (g_params != nullptr) launch_eam_vjp_embed(s, ga, v);
     }
     if (g_pos != nullptr) launch_to_user(s, ga, c->n, c->id, c->gx_s, g_pos);
@@ -746,63 +857,37 @@ int64_t md_get_neighbor_list(md_ctx *c, int64_t *start, int32_t *nbr, int64_t ca
     if (!c->have_list) return fail(c, MD_ERR_STATE, "no list");
     if (hipStreamSynchronize(c->last) != hipSuccess) return fail(c, MD_ERR_HIP, "synchronise");
     const int64_t n = c->n;
-    std::vector<int32_t> cnt(n), id(n), cs(c->C + 1);
-    std::vector<uint32_t> rows((size_t)(n * c->M));
+    const int32_t stride = c->bd.stride;
+    std::vector<int32_t> cnt(n), id(n), rec((size_t)(c->B * stride));
+    std::vector<uint32_t> words((size_t)(c->n64() * c->M));
     if (hipMemcpy(cnt.data(), c->cnt, sizeof(int32_t) * n, hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(id.data(), c->id, sizeof(int32_t) * n, hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemcpy(cs.data(), c->start, sizeof(int32_t) * (c->C + 1), hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemcpy(rows.data(), c->nbr, sizeof(uint32_t) * rows.size(), hipMemcpyDeviceToHost) != hipSuccess)
+        hipMemcpy(rec.data(), c->brec, sizeof(int32_t) * rec.size(), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(words.data(), c->nbr, sizeof(uint32_t) * words.size(), hipMemcpyDeviceToHost) != hipSuccess)
         return fail(c, MD_ERR_HIP, "list readback");
-    // walk the cells exactly as the cell tasks do: neighbourhood order, one row
-    // of capacity M per sorted atom
-    std::vector<int64_t> len(n, 0), row0(n, 0);
-    std::vector<int32_t> soff_all((size_t)c->C * 28), sbeg_all((size_t)c->C * 28);
-    for (int32_t r = 0; r < c->R; r++) {
-        const RepDesc &d = c->reps_h[r];
-        const int64_t ncell = (int64_t)d.nc[0] * d.nc[1] * d.nc[2];
-        for (int64_t lc = 0; lc < ncell; lc++) {
-            const int64_t cell = d.cell_off + lc;
-            const int32_t cx = (int32_t)(lc % d.nc[0]), cy = (int32_t)((lc / d.nc[0]) % d.nc[1]);
-            const int32_t cz = (int32_t)(lc / ((int64_t)d.nc[0] * d.nc[1]));
-            int64_t nb[27];
-            int32_t run = 0;
-            int32_t *soff = &soff_all[(size_t)cell * 28], *sbeg = &sbeg_all[(size_t)cell * 28];
-            for (int s = 0; s < 27; s++) {
-                const int32_t x = (cx + s % 3 - 1 + d.nc[0]) % d.nc[0];
-                const int32_t y = (cy + (s / 3) % 3 - 1 + d.nc[1]) % d.nc[1];
-                const int32_t z = (cz + s / 9 - 1 + d.nc[2]) % d.nc[2];
-                nb[s] = d.cell_off + x + (int64_t)d.nc[0] * (y + (int64_t)d.nc[1] * z);
-                bool dup = false;
-                for (int k = 0; k < s; k++) dup |= nb[k] == nb[s];
-                soff[s] = run;
-                sbeg[s] = dup ? 0 : cs[nb[s]];
-                if (!dup) run += cs[nb[s] + 1] - cs[nb[s]];
-            }
-            soff[27] = run;
-            for (int32_t i = cs[cell]; i < cs[cell + 1]; i++) {
-                len[id[i]] = std::min<int64_t>(cnt[i], c->M);
-                row0[i] = (int64_t)i * c->M;
-            }
-        }
-    }
+    std::vector<int64_t> len(n, 0);
+    for (int64_t i = 0; i < n; i++) len[id[i]] = std::min<int64_t>(cnt[i], c->M);
     start[0] = 0;
     for (int64_t u = 0; u < n; u++) start[u + 1] = start[u] + len[u];
     const int64_t total = start[n];
     if (nbr == nullptr || total > capacity) return total;
-    // cell of each sorted atom, to find its neighbourhood
-    std::vector<int64_t> cell_of_atom(n);
-    for (int64_t cell = 0; cell < c->C; cell++)
-        for (int32_t i = cs[cell]; i < cs[cell + 1]; i++) cell_of_atom[i] = cell;
-    for (int64_t i = 0; i < n; i++) {
-        const int64_t u = id[i];
-        const int32_t *soff = &soff_all[(size_t)cell_of_atom[i] * 28];
-        const int32_t *sbeg = &sbeg_all[(size_t)cell_of_atom[i] * 28];
-        for (int64_t k = 0; k < len[u]; k++) {
-            const int32_t g = (int32_t)(rows[(size_t)(row0[i] + k)] & MD_IDX_MASK);
-            int s = 26;
-            while (s > 0 && soff[s] > g) s--;
-            nbr[start[u] + k] = id[sbeg[s] + (g - soff[s])];
-        }
+    // every atom belongs to exactly one brick; its entries index that brick's halo
+    for (int64_t b = 0; b < c->B; b++) {
+        const int32_t *r = &rec[(size_t)(b * stride)];
+        const int32_t H = r[BR_H], E = r[BR_E];
+        const int32_t *soff = r + br_soff(c->bd), *sbeg = r + br_sbeg(c->bd);
+        const int32_t *aoff = r + br_aoff(c->bd), *abeg = r + br_abeg(c->bd);
+        for (int32_t e = 0; e < E; e++)
+            for (int32_t a = aoff[e]; a < aoff[e + 1]; a++) {
+                const int64_t i = abeg[e] + (a - aoff[e]);
+                const int64_t u = id[i];
+                for (int64_t p = 0; p < len[u]; p++) {
+                    const int32_t k = (int32_t)(words[(size_t)ell_word(i, p, c->M)] & MD_IDX_MASK);
+                    int32_t h = H - 1;
+                    while (h > 0 && soff[h] > k) h--;
+                    nbr[start[u] + p] = id[sbeg[h] + (k - soff[h])];
+                }
+            }
     }
     return total;
 }
@@ -823,8 +908,11 @@ int md_get_cells(md_ctx *c, int32_t *cell_start, int32_t *order, int64_t *ncells
 int md_set_tuning(md_ctx *c, int32_t key, int32_t value)
 {
     if (c == nullptr) return MD_ERR_ARG;
-    if (key == 0 && value >= 64 && value <= 2048 && value % 64 == 0 && value <= cap_limit(c)) {
+    // the largest record a brick of at most 64 cells can need
+    const int64_t cap_max = (c->lds_max - 4096 - 4 * (int64_t)br_stride(512, 64)) / (int64_t)(4 * sizeof(double));
+    if (key == 0 && value >= 64 && value <= 4096 && value % 64 == 0 && value <= cap_max) {
         c->cap = value;
+        c->cap_user = true;
         return MD_OK;
     }
     if (key == 1 && value >= 1 && value <= 8) {
@@ -835,13 +923,65 @@ int md_set_tuning(md_ctx *c, int32_t key, int32_t value)
         // fixed per-atom list capacity (tests of the overflow path force a small one)
         if (hipDeviceSynchronize() != hipSuccess) return fail(c, MD_ERR_HIP, "synchronise");
         const int32_t m = (value + 7) / 8 * 8;
-        if (!dalloc(&c->nbr, (size_t)m * (size_t)c->n)) return fail(c, MD_ERR_HIP, "list: out of device memory");
+        if (!dalloc(&c->nbr, (size_t)m * (size_t)c->n64())) return fail(c, MD_ERR_HIP, "list: out of device memory");
         c->M = m;
         c->need_M = 0;
         c->have_list = false;
         return MD_OK;
     }
-    return fail(c, MD_ERR_ARG, "tuning: key 0 in 64..2048 (multiple of 64), key 1 in 1..8, key 2 in 1..4096");
+    if (key == 3) {
+        const int32_t bx = value & 255, by = (value >> 8) & 255, bz = (value >> 16) & 255;
+        if (value == 0) {
+            c->bshape[0] = c->bshape[1] = c->bshape[2] = 0;
+        } else {
+            if (bx < 1 || by < 1 || bz < 1 || bx > 8 || by > 8 || bz > 8 || (value >> 24) != 0 ||
+                bx * by * bz > 64 || (bx + 2) * (by + 2) * (bz + 2) > 512)
+                return fail(c, MD_ERR_ARG, "tuning: brick shape needs 1..8 cells per axis, at most 64 cells");
+            c->bshape[0] = bx;
+            c->bshape[1] = by;
+            c->bshape[2] = bz;
+        }
+        c->bricks_valid = false;
+        c->have_list = false;
+        return MD_OK;
+    }
+    if (key == 4 && (value == 0 || (value >= 128 && value <= TASK_MAX_THREADS && value % 64 == 0))) {
+        c->threads_req = value;
+        c->bricks_valid = false;
+        c->have_list = false;
+        return MD_OK;
+    }
+    return fail(c, MD_ERR_ARG, "tuning: key 0 in 64..4096 (multiple of 64, within the LDS), key 1 in 1..8, key 2 in 1..4096, "
+                               "key 3 a brick shape, key 4 threads per task (0 or 128..512, multiple of 64)");
+}
+
+int md_query(md_ctx *c, int32_t key, int64_t *value)
+{
+    if (c == nullptr || value == nullptr) return MD_ERR_ARG;
+    switch (key) {
+    case 0: *value = c->cap; return MD_OK;
+    case 1: *value = c->wgpc; return MD_OK;
+    case 2: *value = c->M; return MD_OK;
+    case 3:
+        *value = c->bricks_valid ? (int64_t)c->reps_h[0].bd[0] | (int64_t)c->reps_h[0].bd[1] << 8 |
+                                       (int64_t)c->reps_h[0].bd[2] << 16
+                                 : 0;
+        return MD_OK;
+    case 4: *value = c->threads; return MD_OK;
+    case 5: *value = c->B; return MD_OK;
+    case 6:
+    case 7: {
+        if (c->last != nullptr && hipStreamSynchronize(c->last) != hipSuccess) return fail(c, MD_ERR_HIP, "synchronise");
+        DevCtl h{};
+        if (hipMemcpy(&h, c->ctl, sizeof(DevCtl), hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(c, MD_ERR_HIP, "status readback");
+        *value = key == 6 ? h.max_nbhd : h.max_brick;
+        return MD_OK;
+    }
+    case 8: *value = c->lds_max; return MD_OK;
+    case 9: *value = c->bricks_valid ? c->grid_tasks(0, false) : 0; return MD_OK;
+    default: return fail(c, MD_ERR_ARG, "query: key 0..9");
+    }
 }
 
 int md_profile(md_ctx *c, int32_t enable, double *force_ms, int64_t *force_n, double *list_ms,

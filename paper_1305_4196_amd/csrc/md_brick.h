@@ -1,0 +1,407 @@
+// md_brick.h -- cell tasks blocked into bricks of cells (Sec. II.A, II.D.2).
+//
+// A task is one workgroup working on a brick of bx x by x bz cells (the blocking
+// of Sec. II.D.2; its shape is a tuning parameter).  The brick's halo is the
+// distinct cells of the (bx+2) x (by+2) x (bz+2) block around it: along an axis
+// with origin o, extent e and n cells the halo coordinates are
+//   (o - 1 + t) mod n,  t = 0 .. min(e + 2, n) - 1,
+// which are distinct and, when e + 2 > n, cover the axis once.  The atoms of the
+// halo cells, concatenated in halo order (x fastest), are the task's
+// candidates; halo cell h holds candidates soff[h] .. soff[h+1]-1, the first of
+// them at sorted index sbeg[h].  Every neighbour of every atom of the brick is
+// a candidate, so the tasks stage the candidates in LDS once and read all
+// neighbours from there.  A list entry holds the candidate index (low 26 bits)
+// and the image code (high 6 bits) fixed when the list was built.
+//
+// Each lane owns one atom of its brick (lane t of a workgroup of T threads
+// takes the brick's atoms t, t + T, ...; T is a multiple of 64 up to 512), so
+// the atom's sums stay in registers and no atom is written by two lanes: the
+// cell-task invariant of Sec. II.A by ownership.
+//
+// Brick record (int32, one per brick, written by the list build, read by the
+// force and adjoint tasks so that they skip the setup):
+//   [BR_TOTAL] candidates  [BR_ATOMS] atoms  [BR_REP] replica  [BR_H] halo cells
+//   [BR_E] own cells  [BR_IMG] 1 if a pair of the brick may cross the box
+//   soff[Hm+1]  sbeg[Hm]  aoff[Em+1]  abeg[Em]
+// (aoff/abeg: the same for the brick's own cells, in x-fastest order.)
+//
+// List layout (interleaved rows): entry p of sorted atom i is word
+//   ((i/64) * M/4 + p/4) * 256 + (i%64) * 4 + p%4
+// so lane i reads its entries four at a time (one 16-byte load) and the 64
+// atoms of a row group read 1 KiB contiguously.  M is a multiple of 8.
+#pragma once
+
+#include "md_internal.h"
+
+constexpr int TASK_MAX_THREADS = 512;
+
+enum { BR_TOTAL = 0, BR_ATOMS = 1, BR_REP = 2, BR_H = 3, BR_E = 4, BR_IMG = 5, BR_HDR = 8 };
+
+__host__ __device__ inline int32_t br_soff(const BrickDims &d) { (void)d; return BR_HDR; }
+__host__ __device__ inline int32_t br_sbeg(const BrickDims &d) { return BR_HDR + d.Hm + 1; }
+__host__ __device__ inline int32_t br_aoff(const BrickDims &d) { return BR_HDR + 2 * d.Hm + 1; }
+__host__ __device__ inline int32_t br_abeg(const BrickDims &d) { return BR_HDR + 2 * d.Hm + d.Em + 2; }
+__host__ __device__ inline int32_t br_stride(int32_t Hm, int32_t Em)
+{
+    return (BR_HDR + 2 * Hm + 2 * Em + 2 + 3) / 4 * 4;
+}
+
+// word index of entry p of sorted atom i in the interleaved list
+__host__ __device__ inline int64_t ell_word(int64_t i, int64_t p, int32_t M)
+{
+    return (((i >> 6) * (M >> 2) + (p >> 2)) << 8) + ((i & 63) << 2) + (p & 3);
+}
+
+// allow a kernel to take `bytes` of dynamic LDS
+template <typename K>
+inline void allow_lds(K kernel, size_t bytes)
+{
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+// dynamic LDS of a task: staged (x, y, z) (binary64, interleaved) of `cap`
+// candidates, `nextra` more binary64 per candidate, their sorted indices
+// (optional) and the brick record
+__host__ __device__ inline size_t stage_bytes(int cap, int nextra, bool with_j, int32_t stride)
+{
+    return (size_t)cap * ((3 + nextra) * sizeof(double) + (with_j ? sizeof(int32_t) : 0)) +
+           (size_t)stride * sizeof(int32_t);
+}
+
+#ifdef __HIPCC__
+
+struct Stage {
+    double *xyz;        // x, y, z of candidate g at xyz[3g .. 3g+2]
+    double *ex;         // extra k of candidate g at ex[k * cap + g] (null if none)
+    int32_t *j;         // sorted index of each candidate (null if not staged)
+    int32_t *rec;       // brick record
+    int cap;
+};
+
+__device__ __forceinline__ Stage stage_slice(void *base, int cap, int nextra, bool with_j)
+{
+    Stage s;
+    s.cap = cap;
+    s.xyz = (double *)base;
+    s.ex = nextra ? s.xyz + 3 * (size_t)cap : nullptr;
+    int32_t *p = (int32_t *)(s.xyz + 3 * (size_t)cap + (size_t)nextra * cap);
+    s.j = with_j ? p : nullptr;
+    s.rec = with_j ? p + cap : p;
+    return s;
+}
+
+// geometry of brick b (list build only; the other tasks read the record)
+struct BrickGeom {
+    int32_t r;
+    int32_t o[3], e[3], hn[3], nc[3];
+    int64_t cell_off;
+};
+
+__device__ __forceinline__ BrickGeom brick_geom(const RepDesc *reps, int32_t R, int64_t b)
+{
+    int32_t r = 0;
+    if (R > 1) {
+        int32_t lo = 0, hi = R - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (reps[mid].brick_off <= b) lo = mid; else hi = mid - 1;
+        }
+        r = lo;
+    }
+    const RepDesc &rep = reps[r];
+    BrickGeom g;
+    g.r = r;
+    g.cell_off = rep.cell_off;
+    // fewer than 2^31 bricks per replica: 32-bit division suffices
+    uint32_t lb = (uint32_t)(b - rep.brick_off);
+    uint32_t bi[3];
+    bi[0] = lb % (uint32_t)rep.nb[0];
+    lb /= (uint32_t)rep.nb[0];
+    bi[1] = lb % (uint32_t)rep.nb[1];
+    bi[2] = lb / (uint32_t)rep.nb[1];
+    for (int d = 0; d < 3; d++) {
+        g.nc[d] = rep.nc[d];
+        g.o[d] = (int32_t)bi[d] * rep.bd[d];
+        g.e[d] = min(rep.bd[d], rep.nc[d] - g.o[d]);
+        g.hn[d] = min(g.e[d] + 2, rep.nc[d]);
+    }
+    return g;
+}
+
+// In-place exclusive scan of a[0..n) by one wavefront (all 64 lanes call it);
+// a[n] receives the total.
+__device__ __forceinline__ void wave_scan_lds(int32_t *a, int32_t n)
+{
+    const int lane = threadIdx.x & 63;
+    const int32_t per = (n + 63) >> 6;
+    const int32_t b = lane * per;
+    const int32_t e = b + per < n ? b + per : n;
+    int32_t s = 0;
+    for (int32_t k = b; k < e; k++) s += a[k];
+    int32_t inc = s;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    int32_t run = inc - s;
+    for (int32_t k = b; k < e; k++) {
+        const int32_t v = a[k];
+        a[k] = run;
+        run += v;
+    }
+    if (lane == 63) a[n] = inc;
+    wave_sync();
+}
+
+// Builds the record of brick g in LDS (block-wide; ends with a barrier).
+__device__ __forceinline__ void brick_setup(const Stage &s, const BrickDims &d, const BrickGeom &g,
+                                            const int32_t *start)
+{
+    int32_t *rec = s.rec;
+    int32_t *soff = rec + br_soff(d), *sbeg = rec + br_sbeg(d);
+    int32_t *aoff = rec + br_aoff(d), *abeg = rec + br_abeg(d);
+    const int32_t H = g.hn[0] * g.hn[1] * g.hn[2];
+    const int32_t E = g.e[0] * g.e[1] * g.e[2];
+    const int64_t nx = g.nc[0], nxy = (int64_t)g.nc[0] * g.nc[1];
+    for (int32_t h = threadIdx.x; h < H; h += blockDim.x) {
+        const int32_t px = h % g.hn[0], t = h / g.hn[0];
+        const int32_t py = t % g.hn[1], pz = t / g.hn[1];
+        const int32_t cx = (g.o[0] - 1 + px + g.nc[0]) % g.nc[0];
+        const int32_t cy = (g.o[1] - 1 + py + g.nc[1]) % g.nc[1];
+        const int32_t cz = (g.o[2] - 1 + pz + g.nc[2]) % g.nc[2];
+        const int64_t cell = g.cell_off + cx + nx * cy + nxy * cz;
+        const int32_t b0 = start[cell];
+        soff[h] = start[cell + 1] - b0;
+        sbeg[h] = b0;
+    }
+    for (int32_t e = threadIdx.x; e < E; e += blockDim.x) {
+        const int32_t ex = e % g.e[0], t = e / g.e[0];
+        const int32_t ey = t % g.e[1], ez = t / g.e[1];
+        const int64_t cell = g.cell_off + (g.o[0] + ex) + nx * (g.o[1] + ey) + nxy * (g.o[2] + ez);
+        const int32_t b0 = start[cell];
+        aoff[e] = start[cell + 1] - b0;
+        abeg[e] = b0;
+    }
+    __syncthreads();
+    // (workgroups have at least two wavefronts)
+    const int w = threadIdx.x >> 6;
+    if (w == 0) wave_scan_lds(soff, H);
+    if (w == 1) wave_scan_lds(aoff, E);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        rec[BR_TOTAL] = soff[H];
+        rec[BR_ATOMS] = aoff[E];
+        rec[BR_REP] = g.r;
+        rec[BR_H] = H;
+        rec[BR_E] = E;
+        bool img = false;
+        for (int k = 0; k < 3; k++)
+            img |= g.nc[k] < 5 || g.o[k] == 0 || g.o[k] + g.e[k] == g.nc[k];
+        rec[BR_IMG] = img ? 1 : 0;
+    }
+    __syncthreads();
+}
+
+// halo cell holding candidate k (largest h with soff[h] <= k)
+__device__ __forceinline__ int32_t halo_cell(const Stage &s, int32_t k)
+{
+    const int32_t *soff = s.rec + BR_HDR;
+    int32_t lo = 0, hi = s.rec[BR_H] - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (soff[mid] <= k) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int32_t candidate_index(const Stage &s, const BrickDims &d, int32_t k)
+{
+    const int32_t h = halo_cell(s, k);
+    return s.rec[br_sbeg(d) + h] + (k - s.rec[BR_HDR + h]);
+}
+
+// sorted index of the brick's atom la (la < atoms); *e receives its own cell
+__device__ __forceinline__ int64_t brick_atom(const Stage &s, const BrickDims &d, int32_t la,
+                                              int32_t *e = nullptr)
+{
+    const int32_t *aoff = s.rec + br_aoff(d);
+    int32_t lo = 0, hi = s.rec[BR_E] - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (aoff[mid] <= la) lo = mid; else hi = mid - 1;
+    }
+    if (e != nullptr) *e = lo;
+    return s.rec[br_abeg(d) + lo] + (la - aoff[lo]);
+}
+
+// Copies the record of brick b into LDS and stages its first `cap` candidates
+// (block-wide; ends with a barrier).  extra0/extra1 (may be null) are staged
+// as extras 0 and 1.
+__device__ __forceinline__ void brick_load(const Stage &s, const BrickDims &d, const int32_t *grec,
+                                           const double4 *pos, const double *extra0,
+                                           const double *extra1)
+{
+    for (int32_t t = threadIdx.x; t < d.stride; t += blockDim.x) s.rec[t] = grec[t];
+    __syncthreads();
+    const int32_t total = s.rec[BR_TOTAL];
+    const int32_t lim = total < s.cap ? total : s.cap;
+    for (int32_t k = threadIdx.x; k < lim; k += blockDim.x) {
+        const int32_t g = candidate_index(s, d, k);
+        const double4 p = pos[g];
+        s.xyz[3 * k] = p.x;
+        s.xyz[3 * k + 1] = p.y;
+        s.xyz[3 * k + 2] = p.z;
+        if (s.j != nullptr) s.j[k] = g;
+        if (extra0 != nullptr) s.ex[k] = extra0[g];
+        if (extra1 != nullptr) s.ex[s.cap + k] = extra1[g];
+    }
+    __syncthreads();
+}
+
+// 1/x in binary64: hardware reciprocal refined by two Newton steps (within
+// 1 ulp of the correctly rounded quotient, without the scaled-division sequence)
+__device__ __forceinline__ double rcp64(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// the image shift of a list entry, as an addition: bit 0 adds L, bit 1
+// subtracts it (d + 0 leaves every non-zero d unchanged)
+__device__ __forceinline__ double image_shift(uint32_t code, uint32_t add_bit, double L)
+{
+    return (code & add_bit) ? L : ((code & (add_bit << 1)) ? -L : 0.0);
+}
+
+// Position of candidate k.  STAGED = true: the whole halo is in LDS (pure LDS
+// reads); false: candidates past the staged part come from global memory.  The
+// two are separate instantiations chosen once per brick, so the common path
+// never merges LDS and global addresses into flat loads.
+template <bool STAGED>
+__device__ __forceinline__ void candidate_pos(const Stage &s, const BrickDims &d, int32_t k,
+                                              const double4 *pos, double &x, double &y, double &z)
+{
+    if (STAGED || k < s.cap) {
+        const double *q = s.xyz + 3 * k;
+        x = q[0];
+        y = q[1];
+        z = q[2];
+    } else {
+        const double4 p = pos[candidate_index(s, d, k)];
+        x = p.x;
+        y = p.y;
+        z = p.z;
+    }
+}
+
+template <bool STAGED>
+__device__ __forceinline__ int32_t candidate_j(const Stage &s, const BrickDims &d, int32_t k)
+{
+    if (STAGED || k < s.cap) return s.j[k];
+    return candidate_index(s, d, k);
+}
+
+// Walks the list of one atom four entries at a time, prefetching the next
+// 16-byte group, and calls body(ok, k, j-entry, dx, dy, dz, r2) for every slot;
+// slots past the list's end come with ok = false and a valid dummy candidate.
+template <bool STAGED, bool IMG, typename Body>
+__device__ __forceinline__ void walk_list(const Stage &s, const BrickDims &d, const double4 *pos,
+                                          const uint32_t *nbr, int64_t i, int32_t M, int32_t mm,
+                                          const double4 &xi, double Lx, double Ly, double Lz,
+                                          Body &&body)
+{
+    const uint4 *row = reinterpret_cast<const uint4 *>(nbr) + (((i >> 6) * (int64_t)(M >> 2)) << 6) + (i & 63);
+    const int32_t nq = (mm + 3) >> 2;
+    // two groups in flight: the load for group q + 2 is issued while q is used
+    uint4 n1 = make_uint4(0u, 0u, 0u, 0u), n2 = n1;
+    if (nq > 0) n1 = row[0];
+    if (nq > 1) n2 = row[64];
+    for (int32_t q = 0; q < nq; q++) {
+        const uint4 ev = n1;
+        n1 = n2;
+        if (q + 2 < nq) n2 = row[(int64_t)(q + 2) << 6];
+        const uint32_t es[4] = {ev.x, ev.y, ev.z, ev.w};
+        const int32_t rem = mm - 4 * q;
+        // the four positions first, then the four pairs
+        double px[4], py[4], pz[4];
+        _Pragma("unroll")
+        for (int u = 0; u < 4; u++)
+            candidate_pos<STAGED>(s, d, (int32_t)((u < rem ? es[u] : 0u) & MD_IDX_MASK), pos, px[u], py[u], pz[u]);
+        _Pragma("unroll")
+        for (int u = 0; u < 4; u++) {
+            const bool ok = u < rem;
+            const uint32_t en = ok ? es[u] : 0u;
+            const int32_t k = (int32_t)(en & MD_IDX_MASK);
+            double dx = xi.x - px[u], dy = xi.y - py[u], dz = xi.z - pz[u];
+            if (IMG) {
+                const uint32_t c = en >> MD_IDX_BITS;
+                dx = dx + image_shift(c, 1u, Lx);
+                dy = dy + image_shift(c, 4u, Ly);
+                dz = dz + image_shift(c, 16u, Lz);
+            }
+            const double r2 = (dx * dx + dy * dy) + dz * dz;
+            body(ok, k, dx, dy, dz, r2);
+        }
+    }
+}
+
+// runs the block once per (STAGED, IMG) combination (both uniform per brick)
+#define STAGE_IMG_SPLIT(ALL_STAGED, HAS_IMG, ...)                                         \
+    if (ALL_STAGED) {                                                                     \
+        constexpr bool STAGED = true;                                                     \
+        if (HAS_IMG) {                                                                    \
+            constexpr bool IMG = true;                                                    \
+            __VA_ARGS__                                                                   \
+        } else {                                                                          \
+            constexpr bool IMG = false;                                                   \
+            __VA_ARGS__                                                                   \
+        }                                                                                 \
+    } else {                                                                              \
+        constexpr bool STAGED = false;                                                    \
+        constexpr bool IMG = true;                                                        \
+        __VA_ARGS__                                                                       \
+    }
+
+#define STAGED_SPLIT(ALL_STAGED, ...)                                                     \
+    if (ALL_STAGED) {                                                                     \
+        constexpr bool STAGED = true;                                                     \
+        __VA_ARGS__                                                                       \
+    } else {                                                                              \
+        constexpr bool STAGED = false;                                                    \
+        __VA_ARGS__                                                                       \
+    }
+
+// ---------------------------------------------------------------- brick-task loop
+// Persistent grid: each workgroup takes bricks from its XCD's range, loads the
+// record and stages the halo, then its lanes take the brick's atoms (la =
+// a0 + thread) in rounds of blockDim.x.  Defines for the body: st_rec-derived natoms,
+// rep_r, Lx/Ly/Lz, all_staged, has_img, valid, la, i (sorted index), mm (list
+// length, capped at M).
+#define BRICK_TASK_BEGIN(ST, POS, EXTRA0, EXTRA1)                                          \
+    const ItemRange it_ = xcd_items(a.B, 1, 0);                                           \
+    for (int64_t b_ = it_.first; b_ < it_.end; b_ += it_.stride) {                        \
+        const int32_t *grec_ = a.brec + b_ * (int64_t)a.bd.stride;                        \
+        const int32_t natoms = grec_[BR_ATOMS];                                           \
+        if (natoms == 0) continue;                                                        \
+        __syncthreads();                                                                  \
+        brick_load(ST, a.bd, grec_, POS, EXTRA0, EXTRA1);                                 \
+        const int32_t rep_r = ST.rec[BR_REP];                                             \
+        const bool has_img = ST.rec[BR_IMG] != 0;                                         \
+        const bool all_staged = ST.rec[BR_TOTAL] <= ST.cap;                               \
+        const RepDesc &rep_ = a.reps[rep_r];                                              \
+        const double Lx = rep_.L[0], Ly = rep_.L[1], Lz = rep_.L[2];                      \
+        for (int32_t a0_ = 0; a0_ < natoms; a0_ += (int32_t)blockDim.x) {                        \
+            const int32_t la = a0_ + (int32_t)threadIdx.x;                                \
+            const bool valid = la < natoms;                                               \
+            const int64_t i = valid ? brick_atom(ST, a.bd, la) : 0;                       \
+            const int32_t mm = valid ? min(a.cnt[i], a.M) : 0;
+
+#define BRICK_TASK_END                                                                    \
+        }                                                                                 \
+    }
+
+#endif

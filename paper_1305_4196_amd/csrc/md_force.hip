@@ -1,13 +1,19 @@
 // md_force.hip -- LJ and FS-EAM forces over Verlet lists, fused with velocity Verlet.
 //
-// Work decomposition: TPP consecutive lanes own one atom i of the cell-sorted
-// order and stride through its list row; their partial sums are combined by a
-// butterfly inside the group.  With the full list every pair appears in both
-// rows and each atom's force is written only by its own lane group, so no
-// particle is updated by two workers at once -- the invariant the cell-task
-// schedule of Sec. II.A/II.B exists to guarantee, here obtained by ownership
-// instead of by a dependent schedule.  The half-list kernel is the Newton-3
-// alternative (Sec. II.D.3) with binary64 atomics on the partner atom.
+// Work decomposition: brick tasks (md_brick.h).  One lane owns one atom of its
+// brick, walks the atom's list four entries at a time and reads every neighbour
+// from the brick's halo staged in LDS; the atom's sums stay in the lane's
+// registers.  With the full list every pair appears in both lists and each
+// atom's force is written only by its own lane, so no particle is updated by
+// two workers at once -- the invariant the cell-task schedule of Sec. II.A/II.B
+// exists to guarantee, here obtained by ownership instead of by a dependent
+// schedule.  The half-list kernel is the Newton-3 alternative (Sec. II.D.3) with
+// binary64 atomics on the partner atom.
+//
+// The pair loop has no data-dependent branches: slots past the end of a list
+// and pairs beyond the cutoff are computed and then masked, and the image shift
+// is an addition of +-L or 0 (instantiated only for bricks that touch a box
+// face).
 //
 // Precision (MIXED = false: all binary64):
 //   displacement, image shift, r2 and the r2 < rc^2 test are always binary64
@@ -15,15 +21,15 @@
 //   pair scalar (LJ 24 eps (2 q12 - q6)/r2 and V; EAM table polynomials) is
 //   evaluated in binary32, then projected and accumulated in binary64.
 //
-// Integration (mode): after the group's forces are known, lane 0 of the group
-// applies the velocity-Verlet pieces of this atom (the per-particle loop of
-// Sec. II.A) -- the closing half kick of the current step, the kinetic energy,
-// the opening half kick and drift of the next -- and flags a rebuild when the
-// displacement since the last build exceeds skin/2.  Drifted positions go to a
-// second buffer because other groups still gather the current ones.
+// Integration (mode): once the atom's force is known, its lane applies the
+// velocity-Verlet pieces of this atom (the per-particle loop of Sec. II.A) --
+// the closing half kick of the current step, the kinetic energy, the opening
+// half kick and drift of the next -- and flags a rebuild when the displacement
+// since the last build exceeds skin/2.  Drifted positions go to a second buffer
+// because other tasks still gather the current ones.
 #include <math.h>
 
-#include "md_nbhd.h"
+#include "md_brick.h"
 #include "md_reduce.h"
 
 namespace {
@@ -73,7 +79,7 @@ __device__ __forceinline__ void embed64(const ForceArgs &a, double rho, double &
     Fp = fu * a.inv_h[2];
 }
 
-// Per-atom epilogue run by lane 0 of the group.
+// Per-atom epilogue, run by the atom's lane.
 __device__ __forceinline__ void finish_atom(const ForceArgs &a, int64_t i, const double4 &xi,
                                             double fx, double fy, double fz, double e, double w,
                                             double &accE, double &accW, double &accK,
@@ -137,151 +143,109 @@ __device__ __forceinline__ void finish_block(const ForceArgs &a, double accE, do
     }
 }
 
+// ---------------------------------------------------------------- LJ pair scalar
+// f_s = 24 eps (2 q12 - q6) / r2 and V = 4 eps (q12 - q6), q6 = (sigma^2/r2)^3,
+// both zero unless `in`
+template <bool MIXED>
+__device__ __forceinline__ void lj_pair(bool in, double r2, double s2, double e4, double e24, float s2f,
+                                        float e4f, float e24f, double &fs, double &V)
+{
+    if (MIXED) {
+        const float ir2 = __builtin_amdgcn_rcpf((float)r2);
+        const float q2 = s2f * ir2;
+        const float q6 = q2 * q2 * q2;
+        const float q12 = q6 * q6;
+        const float f = e24f * (2.0f * q12 - q6) * ir2;
+        const float v = e4f * (q12 - q6);
+        fs = in ? (double)f : 0.0;
+        V = in ? (double)v : 0.0;
+    } else {
+        const double ir2 = rcp64(r2);
+        const double q2 = s2 * ir2;
+        const double q6 = q2 * q2 * q2;
+        const double q12 = q6 * q6;
+        const double f = e24 * (2.0 * q12 - q6) * ir2;
+        const double v = e4 * (q12 - q6);
+        fs = in ? f : 0.0;
+        V = in ? v : 0.0;
+    }
+}
+
 // ---------------------------------------------------------------- LJ, full list
 template <bool MIXED>
-__global__ __launch_bounds__(256) void k_lj_full(ForceArgs a)
+__global__ __launch_bounds__(TASK_MAX_THREADS) void k_lj_full(ForceArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    __shared__ double red[TASK_THREADS];
-    __shared__ double lds[16];
-    const Stage st = stage_slice(lds_raw, 0, a.cap, 0);
+    __shared__ double lds[4 * TASK_MAX_THREADS / 64];
+    const Stage st = stage_slice(lds_raw, a.cap, 0, false);
     if (a.flag_clear != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *a.flag_clear = 0;
     const double eps = a.lj[0], sig = a.lj[1];
     const double s2 = sig * sig, e4 = 4.0 * eps, e24 = 24.0 * eps;
     const float s2f = (float)s2, e4f = (float)e4, e24f = (float)e24;
+    const double rc2 = a.rc2;
     double accE = 0.0, accW = 0.0, accK = 0.0;
-    CELL_TASK_BEGIN(nullptr)
+    BRICK_TASK_BEGIN(st, a.pos, nullptr, nullptr)
         double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0, w = 0.0;
-        double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
-        if (valid) xi = a.pos[i];
-        STAGED_SPLIT(all_staged,
-        for (int32_t q = sub; q < nq; q += tpa) {
-            const uint4 ev = row4[q];
-            const uint32_t es[4] = {ev.x, ev.y, ev.z, ev.w};
-_Pragma("unroll")
-            for (int u = 0; u < 4; u++) {
-                if (4 * q + u < mm) {
-                    const uint32_t en = es[u];
-                    double xj, yj, zj;
-                    candidate_pos<STAGED>(st, (int32_t)(en & MD_IDX_MASK), a.pos, xj, yj, zj);
-                    double dx = xi.x - xj, dy = xi.y - yj, dz = xi.z - zj;
-                    if (en >> MD_IDX_BITS) apply_image_code(en, Lx, Ly, Lz, dx, dy, dz);
-                    const double r2 = (dx * dx + dy * dy) + dz * dz;
-                    if (r2 < a.rc2) {
-                        if (MIXED) {
-                            const float ir2 = __builtin_amdgcn_rcpf((float)r2);
-                            const float q2 = s2f * ir2;
-                            const float q6 = q2 * q2 * q2;
-                            const float q12 = q6 * q6;
-                            const float fs = e24f * (2.0f * q12 - q6) * ir2;
-                            const double fsd = (double)fs;
-                            fx = fma(fsd, dx, fx);
-                            fy = fma(fsd, dy, fy);
-                            fz = fma(fsd, dz, fz);
-                            e += (double)(e4f * (q12 - q6));
-                            w += fsd * r2;
-                        } else {
-                            const double ir2 = rcp64(r2);
-                            const double q2 = s2 * ir2;
-                            const double q6 = q2 * q2 * q2;
-                            const double q12 = q6 * q6;
-                            const double fs = e24 * (2.0 * q12 - q6) * ir2;
-                            fx = fma(fs, dx, fx);
-                            fy = fma(fs, dy, fy);
-                            fz = fma(fs, dz, fz);
-                            e += e4 * (q12 - q6);
-                            w += fs * r2;
-                        }
-                    }
-                }
-            }
-        }
+        const double4 xi = a.pos[i];
+        STAGE_IMG_SPLIT(all_staged, has_img,
+            walk_list<STAGED, IMG>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
+                [&](bool ok, int32_t, double dx, double dy, double dz, double r2) {
+                    double fs, V;
+                    lj_pair<MIXED>(ok && r2 < rc2, r2, s2, e4, e24, s2f, e4f, e24f, fs, V);
+                    fx = fma(fs, dx, fx);
+                    fy = fma(fs, dy, fy);
+                    fz = fma(fs, dz, fz);
+                    e += V;
+                    w += fs * r2;
+                });
         )
-        double gv[5] = {fx, fy, fz, e, w};
-        task_group_sum(gv, tpa, am, red);
-        fx = gv[0];
-        fy = gv[1];
-        fz = gv[2];
-        e = gv[3];
-        w = gv[4];
-        if (valid && sub == 0) finish_atom(a, i, xi, fx, fy, fz, 0.5 * e, 0.5 * w, accE, accW, accK);
-    CELL_TASK_END
+        if (valid) finish_atom(a, i, xi, fx, fy, fz, 0.5 * e, 0.5 * w, accE, accW, accK);
+    BRICK_TASK_END
     finish_block(a, accE, accW, accK, lds);
 }
 
 // ---------------------------------------------------------------- LJ, half list + atomics
 template <bool MIXED>
-__global__ __launch_bounds__(256) void k_lj_half(ForceArgs a)
+__global__ __launch_bounds__(TASK_MAX_THREADS) void k_lj_half(ForceArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    __shared__ double red[TASK_THREADS];
-    __shared__ double lds[16];
-    const Stage st = stage_slice(lds_raw, 0, a.cap, 0);
+    __shared__ double lds[4 * TASK_MAX_THREADS / 64];
+    const Stage st = stage_slice(lds_raw, a.cap, 0, true);
     const double eps = a.lj[0], sig = a.lj[1];
     const double s2 = sig * sig, e4 = 4.0 * eps, e24 = 24.0 * eps;
     const float s2f = (float)s2, e4f = (float)e4, e24f = (float)e24;
+    const double rc2 = a.rc2;
     const int64_t n = a.n;
     double accE = 0.0, accW = 0.0;
-    CELL_TASK_BEGIN(nullptr)
+    BRICK_TASK_BEGIN(st, a.pos, nullptr, nullptr)
         double fx = 0.0, fy = 0.0, fz = 0.0;
-        double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
-        if (valid) xi = a.pos[i];
-        STAGED_SPLIT(all_staged,
-        for (int32_t q = sub; q < nq; q += tpa) {
-            const uint4 ev = row4[q];
-            const uint32_t es[4] = {ev.x, ev.y, ev.z, ev.w};
-_Pragma("unroll")
-            for (int u = 0; u < 4; u++) {
-                if (4 * q + u < mm) {
-                    const uint32_t en = es[u];
-                    double xj, yj, zj;
-                    int32_t j;
-                    candidate<STAGED>(st, (int32_t)(en & MD_IDX_MASK), a.pos, xj, yj, zj, j);
-                    double dx = xi.x - xj, dy = xi.y - yj, dz = xi.z - zj;
-                    if (en >> MD_IDX_BITS) apply_image_code(en, Lx, Ly, Lz, dx, dy, dz);
-                    const double r2 = (dx * dx + dy * dy) + dz * dz;
-                    if (r2 < a.rc2) {
-                        double fs, V;
-                        if (MIXED) {
-                            const float ir2 = __builtin_amdgcn_rcpf((float)r2);
-                            const float q2 = s2f * ir2;
-                            const float q6 = q2 * q2 * q2;
-                            const float q12 = q6 * q6;
-                            fs = (double)(e24f * (2.0f * q12 - q6) * ir2);
-                            V = (double)(e4f * (q12 - q6));
-                        } else {
-                            const double ir2 = rcp64(r2);
-                            const double q2 = s2 * ir2;
-                            const double q6 = q2 * q2 * q2;
-                            const double q12 = q6 * q6;
-                            fs = e24 * (2.0 * q12 - q6) * ir2;
-                            V = e4 * (q12 - q6);
-                        }
-                        const double px = fs * dx, py = fs * dy, pz = fs * dz;
-                        fx += px;
-                        fy += py;
-                        fz += pz;
+        const double4 xi = a.pos[i];
+        STAGE_IMG_SPLIT(all_staged, has_img,
+            walk_list<STAGED, IMG>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
+                [&](bool ok, int32_t k, double dx, double dy, double dz, double r2) {
+                    const bool in = ok && r2 < rc2;
+                    double fs, V;
+                    lj_pair<MIXED>(in, r2, s2, e4, e24, s2f, e4f, e24f, fs, V);
+                    const double px = fs * dx, py = fs * dy, pz = fs * dz;
+                    fx += px;
+                    fy += py;
+                    fz += pz;
+                    if (in) {
+                        const int32_t j = candidate_j<STAGED>(st, a.bd, k);
                         atomicAdd(&a.force[j], -px);
                         atomicAdd(&a.force[n + j], -py);
                         atomicAdd(&a.force[2 * n + j], -pz);
-                        accE += V;
-                        accW += fs * r2;
                     }
-                }
-            }
-        }
+                    accE += V;
+                    accW += fs * r2;
+                });
         )
-        double gv[3] = {fx, fy, fz};
-        task_group_sum(gv, tpa, am, red);
-        fx = gv[0];
-        fy = gv[1];
-        fz = gv[2];
-        if (valid && sub == 0) {
+        if (valid) {
             atomicAdd(&a.force[i], fx);
             atomicAdd(&a.force[n + i], fy);
             atomicAdd(&a.force[2 * n + i], fz);
         }
-    CELL_TASK_END
+    BRICK_TASK_END
     double v[4] = {accE, accW, 0.0, 0.0};
     if (a.outE == nullptr && a.outW == nullptr) return;
     if (mdred::last_block_sum4(v, a.partial, a.done, lds) && threadIdx.x == 0) {
@@ -294,7 +258,7 @@ _Pragma("unroll")
 // consumed forces are cleared for the next atomic accumulation
 __global__ __launch_bounds__(256) void k_integrate(ForceArgs a)
 {
-    __shared__ double lds[16];
+    __shared__ double lds[4 * TASK_MAX_THREADS / 64];
     if (a.flag_clear != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *a.flag_clear = 0;
     const int64_t n = a.n;
     double accE = 0.0, accW = 0.0, accK = 0.0;
@@ -320,163 +284,96 @@ __global__ __launch_bounds__(256) void k_integrate(ForceArgs a)
 
 // ---------------------------------------------------------------- EAM pass 1: density
 template <bool MIXED>
-__global__ __launch_bounds__(256) void k_eam_density(ForceArgs a)
+__global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_density(ForceArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    __shared__ double red[TASK_THREADS];
-    const Stage st = stage_slice(lds_raw, 0, a.cap, 0);
+    const Stage st = stage_slice(lds_raw, a.cap, 0, false);
     const int nk = a.nk[1];
-    const double x0 = a.x0[1], ih = a.inv_h[1];
-    CELL_TASK_BEGIN(nullptr)
+    const double x0 = a.x0[1], ih = a.inv_h[1], rrho2 = a.rrho2;
+    BRICK_TASK_BEGIN(st, a.pos, nullptr, nullptr)
         double rho = 0.0;
-        double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
-        if (valid) xi = a.pos[i];
-        STAGED_SPLIT(all_staged,
-        for (int32_t q = sub; q < nq; q += tpa) {
-            const uint4 ev = row4[q];
-            const uint32_t es[4] = {ev.x, ev.y, ev.z, ev.w};
-_Pragma("unroll")
-            for (int u = 0; u < 4; u++) {
-                if (4 * q + u < mm) {
-                    const uint32_t en = es[u];
-                    double xj, yj, zj;
-                    candidate_pos<STAGED>(st, (int32_t)(en & MD_IDX_MASK), a.pos, xj, yj, zj);
-                    double dx = xi.x - xj, dy = xi.y - yj, dz = xi.z - zj;
-                    if (en >> MD_IDX_BITS) apply_image_code(en, Lx, Ly, Lz, dx, dy, dz);
-                    const double r2 = (dx * dx + dy * dy) + dz * dz;
-                    if (r2 < a.rrho2) {
-                        const double uu = (sqrt(r2) - x0) * ih;
-                        if (MIXED) {
-                            float f, fu;
-                            spl32(a.tabf[1], uu, nk, f, fu);
-                            rho += (double)f;
-                        } else {
-                            double f, fu;
-                            spl64(a.tab[1], uu, nk, f, fu);
-                            rho += f;
-                        }
+        const double4 xi = a.pos[i];
+        STAGE_IMG_SPLIT(all_staged, has_img,
+            walk_list<STAGED, IMG>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
+                [&](bool ok, int32_t, double, double, double, double r2) {
+                    const bool in = ok && r2 < rrho2;
+                    const double uu = (sqrt(r2) - x0) * ih;
+                    double f;
+                    if (MIXED) {
+                        float ff, fu;
+                        spl32(a.tabf[1], uu, nk, ff, fu);
+                        f = (double)ff;
+                    } else {
+                        double fu;
+                        spl64(a.tab[1], uu, nk, f, fu);
                     }
-                }
-            }
-        }
+                    rho += in ? f : 0.0;
+                });
         )
-        double gv[1] = {rho};
-        task_group_sum(gv, tpa, am, red);
-        rho = gv[0];
-        if (valid && sub == 0) {
+        if (valid) {
             double F, Fp;
             embed64(a, rho, F, Fp);
             a.rho[i] = rho;
             a.fp[i] = Fp;
         }
-    CELL_TASK_END
+    BRICK_TASK_END
 }
 
 // ---------------------------------------------------------------- EAM pass 2: forces
 template <bool MIXED>
-__global__ __launch_bounds__(256) void k_eam_force(ForceArgs a)
+__global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_force(ForceArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    __shared__ double red[TASK_THREADS];
-    __shared__ double lds[16];
-    const Stage st = stage_slice(lds_raw, 0, a.cap, 1);
+    __shared__ double lds[4 * TASK_MAX_THREADS / 64];
+    const Stage st = stage_slice(lds_raw, a.cap, 1, false);
     if (a.flag_clear != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *a.flag_clear = 0;
     const int nkp = a.nk[0], nkr = a.nk[1];
     const double x0p = a.x0[0], ihp = a.inv_h[0], x0r = a.x0[1], ihr = a.inv_h[1];
+    const double rphi2 = a.rphi2, rrho2 = a.rrho2;
     double accE = 0.0, accW = 0.0, accK = 0.0;
-    CELL_TASK_BEGIN(a.fp)
+    BRICK_TASK_BEGIN(st, a.pos, a.fp, nullptr)
         double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0, w = 0.0;
-        double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
-        double fpi = 0.0;
-        if (valid) {
-            xi = a.pos[i];
-            fpi = a.fp[i];
-        }
-        STAGED_SPLIT(all_staged,
-        for (int32_t q = sub; q < nq; q += tpa) {
-            const uint4 ev = row4[q];
-            const uint32_t es[4] = {ev.x, ev.y, ev.z, ev.w};
-_Pragma("unroll")
-            for (int u = 0; u < 4; u++) {
-                if (4 * q + u < mm) {
-                    const uint32_t en = es[u];
-                    const int32_t gg = (int32_t)(en & MD_IDX_MASK);
-                    double xj, yj, zj, fpj;
-                    if (STAGED || gg < st.cap) {
-                        xj = st.x[gg];
-                        yj = st.y[gg];
-                        zj = st.z[gg];
-                        fpj = st.ex[gg];
+        const double4 xi = a.pos[i];
+        const double fpi = a.fp[i];
+        STAGE_IMG_SPLIT(all_staged, has_img,
+            walk_list<STAGED, IMG>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
+                [&](bool ok, int32_t k, double dx, double dy, double dz, double r2) {
+                    const bool in_phi = ok && r2 < rphi2, in_rho = ok && r2 < rrho2;
+                    const double fpj = (STAGED || k < st.cap) ? st.ex[k] : a.fp[candidate_index(st, a.bd, k)];
+                    const double r = sqrt(r2);
+                    const double ir = rcp64(r);
+                    double gsc, ep;
+                    if (MIXED) {
+                        float f, fu, g, h;
+                        spl32(a.tabf[0], (r - x0p) * ihp, nkp, f, fu);
+                        spl32(a.tabf[1], (r - x0r) * ihr, nkr, g, h);
+                        const float gp = in_phi ? fu * (float)ihp : 0.0f;
+                        const float gr = in_rho ? (float)(fpi + fpj) * h * (float)ihr : 0.0f;
+                        gsc = (double)(gp + gr);
+                        ep = in_phi ? (double)f : 0.0;
                     } else {
-                        const int32_t j = nbhd_index(*st.L, gg);
-                        const double4 p = a.pos[j];
-                        xj = p.x;
-                        yj = p.y;
-                        zj = p.z;
-                        fpj = a.fp[j];
+                        double f, fu, g, h;
+                        spl64(a.tab[0], (r - x0p) * ihp, nkp, f, fu);
+                        spl64(a.tab[1], (r - x0r) * ihr, nkr, g, h);
+                        const double gp = in_phi ? fu * ihp : 0.0;
+                        const double gr = in_rho ? (fpi + fpj) * (h * ihr) : 0.0;
+                        gsc = gp + gr;
+                        ep = in_phi ? f : 0.0;
                     }
-                    double dx = xi.x - xj, dy = xi.y - yj, dz = xi.z - zj;
-                    if (en >> MD_IDX_BITS) apply_image_code(en, Lx, Ly, Lz, dx, dy, dz);
-                    const double r2 = (dx * dx + dy * dy) + dz * dz;
-                    const bool in_phi = r2 < a.rphi2, in_rho = r2 < a.rrho2;
-                    if (in_phi || in_rho) {
-                        const double r = sqrt(r2);
-                        const double ir = rcp64(r);
-                        double gsc, ep;
-                        if (MIXED) {
-                            float gf = 0.0f, epf = 0.0f;
-                            if (in_phi) {
-                                float f, fu;
-                                spl32(a.tabf[0], (r - x0p) * ihp, nkp, f, fu);
-                                gf += fu * (float)ihp;
-                                epf += f;
-                            }
-                            if (in_rho) {
-                                float f, fu;
-                                spl32(a.tabf[1], (r - x0r) * ihr, nkr, f, fu);
-                                gf += (float)(fpi + fpj) * fu * (float)ihr;
-                            }
-                            gsc = (double)gf;
-                            ep = (double)epf;
-                        } else {
-                            gsc = 0.0;
-                            ep = 0.0;
-                            if (in_phi) {
-                                double f, fu;
-                                spl64(a.tab[0], (r - x0p) * ihp, nkp, f, fu);
-                                gsc += fu * ihp;
-                                ep += f;
-                            }
-                            if (in_rho) {
-                                double f, fu;
-                                spl64(a.tab[1], (r - x0r) * ihr, nkr, f, fu);
-                                gsc += (fpi + fpj) * (fu * ihr);
-                            }
-                        }
-                        const double gr = gsc * ir;
-                        fx = fma(-gr, dx, fx);
-                        fy = fma(-gr, dy, fy);
-                        fz = fma(-gr, dz, fz);
-                        e += ep;
-                        w -= gsc * r;
-                    }
-                }
-            }
-        }
+                    const double grr = (in_phi || in_rho) ? gsc * ir : 0.0;
+                    fx = fma(-grr, dx, fx);
+                    fy = fma(-grr, dy, fy);
+                    fz = fma(-grr, dz, fz);
+                    e += ep;
+                    w -= (in_phi || in_rho) ? gsc * r : 0.0;
+                });
         )
-        double gv[5] = {fx, fy, fz, e, w};
-        task_group_sum(gv, tpa, am, red);
-        fx = gv[0];
-        fy = gv[1];
-        fz = gv[2];
-        e = gv[3];
-        w = gv[4];
-        if (valid && sub == 0) {
+        if (valid) {
             double F, Fp;
             embed64(a, a.rho[i], F, Fp);
             finish_atom(a, i, xi, fx, fy, fz, F + 0.5 * e, 0.5 * w, accE, accW, accK);
         }
-    CELL_TASK_END
+    BRICK_TASK_END
     finish_block(a, accE, accW, accK, lds);
 }
 
@@ -548,7 +445,7 @@ __global__ __launch_bounds__(256) void k_replica_sums(const RepDesc *__restrict_
                                                       const double *__restrict__ watom,
                                                       double *energy, double *virial)
 {
-    __shared__ double lds[16];
+    __shared__ double lds[4 * TASK_MAX_THREADS / 64];
     const RepDesc &r = reps[blockIdx.x];
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t i = r.atom_off + threadIdx.x; i < r.atom_end; i += blockDim.x) {
@@ -562,40 +459,36 @@ __global__ __launch_bounds__(256) void k_replica_sums(const RepDesc *__restrict_
     }
 }
 
-#define MD_LAUNCH_CELLS(KERNEL, EXTRA)                                                     \
-    const size_t lds = nbhd_lds_bytes(a.cap, EXTRA);                                \
+#define MD_LAUNCH_TASKS(KERNEL, NEXTRA, WITH_J)                                          \
+    const size_t lds = stage_bytes(a.cap, NEXTRA, WITH_J, a.bd.stride);                    \
     if (mixed) {                                                                            \
         allow_lds(KERNEL<true>, lds);                                                       \
-        hipLaunchKernelGGL((KERNEL<true>), dim3(grid), dim3(256), lds, s, a);               \
+        hipLaunchKernelGGL((KERNEL<true>), dim3(grid), dim3(threads), lds, s, a);           \
     } else {                                                                                \
         allow_lds(KERNEL<false>, lds);                                                      \
-        hipLaunchKernelGGL((KERNEL<false>), dim3(grid), dim3(256), lds, s, a);              \
+        hipLaunchKernelGGL((KERNEL<false>), dim3(grid), dim3(threads), lds, s, a);          \
     }
 
 } // namespace
 
-void launch_lj_full(hipStream_t s, int grid, int tpp, bool mixed, const ForceArgs &a)
+void launch_lj_full(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a)
 {
-    (void)tpp;
-    MD_LAUNCH_CELLS(k_lj_full, 0)
+    MD_LAUNCH_TASKS(k_lj_full, 0, false)
 }
 
-void launch_lj_half(hipStream_t s, int grid, int tpp, bool mixed, const ForceArgs &a)
+void launch_lj_half(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a)
 {
-    (void)tpp;
-    MD_LAUNCH_CELLS(k_lj_half, 0)
+    MD_LAUNCH_TASKS(k_lj_half, 0, true)
 }
 
-void launch_eam_density(hipStream_t s, int grid, int tpp, bool mixed, const ForceArgs &a)
+void launch_eam_density(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a)
 {
-    (void)tpp;
-    MD_LAUNCH_CELLS(k_eam_density, 0)
+    MD_LAUNCH_TASKS(k_eam_density, 0, false)
 }
 
-void launch_eam_force(hipStream_t s, int grid, int tpp, bool mixed, const ForceArgs &a)
+void launch_eam_force(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a)
 {
-    (void)tpp;
-    MD_LAUNCH_CELLS(k_eam_force, 1)
+    MD_LAUNCH_TASKS(k_eam_force, 1, false)
 }
 
 void launch_integrate(hipStream_t s, int grid, const ForceArgs &a)

@@ -6,12 +6,12 @@
 //   force    double[3][N]
 //   xref     double4[N]  positions at the last list build
 //   id       int32[N]    user index of each sorted slot
-//   nbr      uint32[N*M] Verlet list, one contiguous segment per cell (rows of
-//            the cell's atoms back to back, each padded to 4 entries); entry =
-//            candidate index in the cell's neighbourhood (low 26 bits) | image
-//            code (high 6 bits, 2 per axis: 01 = add L, 10 = subtract L) fixed
-//            when the list is built
+//   nbr      uint32[ceil(N/64)*64*M] Verlet lists, interleaved by groups of 64
+//            atoms and 4 entries (md_brick.h); entry = candidate index in the
+//            brick's halo (low 26 bits) | image code (high 6 bits, 2 per axis:
+//            01 = add L, 10 = subtract L) fixed when the list is built
 //   cnt      int32[N]    list length of each atom
+//   brec     int32[B*stride] one record per brick of cells (md_brick.h)
 // Positions are wrapped into [0, L) when the cells are built; between builds they
 // move freely and each pair uses the image fixed at build time (exact as long as
 // no atom moves more than skin/2, which the rebuild trigger guarantees).
@@ -34,9 +34,12 @@
 struct RepDesc {
     double L[3];
     double hL[3];
-    int32_t nc[3];
+    int32_t nc[3];      // cells per axis
+    int32_t bd[3];      // brick extent per axis (cells), <= nc
+    int32_t nb[3];      // bricks per axis
     int32_t pad;
     int64_t cell_off;   // first global cell of this replica
+    int64_t brick_off;  // first global brick of this replica
     int64_t atom_off;   // first atom (user and sorted order agree on replica ranges)
     int64_t atom_end;
 };
@@ -48,8 +51,8 @@ struct DevCtl {
     int32_t max_cnt;      // largest per-atom list length of the last build
     int32_t max_cell;     // largest cell occupancy of the last build
     int32_t nrebuild;     // rebuilds performed inside md_verlet_step
-    int32_t max_nbhd;     // largest cell-task neighbourhood (candidates) seen
-    int32_t pad;
+    int32_t max_nbhd;     // largest brick halo (candidates) seen
+    int32_t max_brick;    // largest brick (atoms) seen
     uint32_t done[4];     // last-block counters (one per reduction site)
 };
 
@@ -73,13 +76,20 @@ void launch_copy_back(hipStream_t s, int grid, const int32_t *pred, int64_t n,
                       const double4 *pos_t, const double *vel_t, const int32_t *id_t,
                       double4 *pos, double *vel, int32_t *id, double4 *xref);
 
+// brick record sizes: halo cells and own cells of the largest brick, record stride
+struct BrickDims {
+    int32_t Hm, Em, stride;
+};
+
 // neighbour list
 struct ListArgs {
     const int32_t *pred;      // predicate word (build only if non-zero), may point at a constant 1
-    int64_t C;                // total cells
+    int64_t B;                // total bricks
     int32_t R;
     const RepDesc *reps;
     const int32_t *start;     // cell_start[C+1]
+    int32_t *brec;            // brick records (written)
+    BrickDims bd;
     const double4 *src;       // sorted positions the list is built from
     int64_t n;
     uint32_t *nbr;
@@ -87,7 +97,7 @@ struct ListArgs {
     int32_t M;
     double rl2;
     int half;
-    int32_t cap;              // candidates staged in LDS per cell task
+    int32_t cap;              // candidates staged in LDS per brick task
     // optional copy of the freshly sorted state into the working buffers
     const double *vel_src;
     const int32_t *id_src;
@@ -97,7 +107,7 @@ struct ListArgs {
     double4 *xref;
     DevCtl *ctl;
 };
-void launch_build_list(hipStream_t s, int grid, const ListArgs &a);
+void launch_build_list(hipStream_t s, int grid, int threads, const ListArgs &a);
 
 // forces
 struct ForceArgs {
@@ -114,9 +124,10 @@ struct ForceArgs {
     const uint32_t *nbr;
     const int32_t *cnt;
     int32_t M;
-    int64_t C;                // cells
-    const int32_t *start;     // cell_start[C+1]
-    int32_t cap;              // candidates staged in LDS per cell task
+    int64_t B;                // bricks
+    const int32_t *brec;      // brick records
+    BrickDims bd;
+    int32_t cap;              // candidates staged in LDS per brick task
     double rc2;
     const double *lj;         // device {eps, sigma}
     // EAM
@@ -145,10 +156,10 @@ struct ForceArgs {
     double *watom;            // per-atom virial, or null
     DevCtl *ctl;
 };
-void launch_lj_full(hipStream_t s, int grid, int tpp, bool mixed, const ForceArgs &a);
-void launch_lj_half(hipStream_t s, int grid, int tpp, bool mixed, const ForceArgs &a);
-void launch_eam_density(hipStream_t s, int grid, int tpp, bool mixed, const ForceArgs &a);
-void launch_eam_force(hipStream_t s, int grid, int tpp, bool mixed, const ForceArgs &a);
+void launch_lj_full(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a);
+void launch_lj_half(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a);
+void launch_eam_density(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a);
+void launch_eam_force(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a);
 void launch_integrate(hipStream_t s, int grid, const ForceArgs &a);
 void launch_zero(hipStream_t s, int grid, double *p, int64_t n);
 void launch_replica_sums(hipStream_t s, int32_t R, const RepDesc *reps, const double *eatom,
@@ -174,9 +185,9 @@ struct VjpArgs {
     double *fpp;              // EAM F''
     double *gout;             // LJ: 2 doubles out (final)
 };
-void launch_lj_vjp(hipStream_t s, int grid, int tpp, bool mixed, const VjpArgs &a);
-void launch_eam_vjp_a(hipStream_t s, int grid, int tpp, bool mixed, const VjpArgs &a);
-void launch_eam_vjp_b(hipStream_t s, int grid, int tpp, bool mixed, const VjpArgs &a);
+void launch_lj_vjp(hipStream_t s, int grid, int threads, const VjpArgs &a);
+void launch_eam_vjp_a(hipStream_t s, int grid, int threads, const VjpArgs &a);
+void launch_eam_vjp_b(hipStream_t s, int grid, int threads, const VjpArgs &a);
 void launch_eam_vjp_embed(hipStream_t s, int grid, const VjpArgs &a);
 
 // ---------------------------------------------------------------- device helpers

@@ -1,100 +1,172 @@
-// md_list.hip -- Verlet neighbor lists built cell by cell (Sec. II.A).
+// md_list.hip -- Verlet neighbour lists built brick by brick (Sec. II.A, II.C).
 //
-// One workgroup per cell (a "cell task", md_nbhd.h).  The neighbourhood's
-// candidates (the atoms of the distinct cells of the 3x3x3 block) are staged in
-// LDS once; candidates beyond the staged part are read from global memory.  The
-// four wavefronts share the centre cell's atoms (atom s0 + w, s0 + w + 4, ...),
-// and for each atom the 64 lanes test all candidates:
+// One workgroup per brick of cells (md_brick.h).  It builds the brick's record
+// (halo and own-cell offsets), writes it out for the force and adjoint tasks,
+// and stages the halo's positions in LDS.  Each lane then owns one atom of the
+// brick and scans the atoms of the distinct cells of the 3x3x3 block around the
+// atom's cell (along an axis of 2 cells the block has 2 distinct layers):
 //   d = x_i - x_j;  d > L/2 -> d - L,  d < -L/2 -> d + L;  r2 = (dx*dx + dy*dy) + dz*dz
-// in binary64 with contraction off, kept iff r2 < (rc + skin)^2 and j != i (and,
-// for the half list, j after i in the sorted order).  Hits are compacted with a
-// ballot and a lane prefix count into the atom's own row, so every row has
-// exactly one writer and no atomics are needed (each task owns its lists,
-// Sec. II.C).  An entry holds the candidate index and the image code.
+// in binary64 with contraction off, keeping j iff r2 < (rc + skin)^2 and j != i
+// (and, for the half list, j after i in the sorted order).  The lane appends
+// to its own atom's list only, so every list has exactly one writer and no
+// atomics are needed (each task owns its lists, Sec. II.C).
 //
-// Interior cells: along an axis with at least 5 cells, no neighbour of a cell
-// that is not on the box face can be more than 2 cell widths (< L/2) away, so
-// the minimum-image branch never fires and is skipped -- the arithmetic (and so
-// the pair set) is unchanged.
-#include "md_nbhd.h"
+// The three cells of a stencil row along x are consecutive in the halo order
+// (or, on a grid of at most bx + 1 cells, wrap around it), so each of the 9
+// rows is one or two contiguous candidate ranges, scanned four candidates at a
+// time: their positions are read first, then tested, then the hits appended.
+//
+// Interior cells: along an axis with at least 5 cells, a neighbour of a cell
+// that is not on the box face is at most 2 cell widths (< L/2) away, so the
+// minimum-image test never fires and is skipped -- the arithmetic, and so the
+// pair set, is unchanged.  Bricks that touch no box face skip it entirely.
+#include "md_brick.h"
 
 namespace {
 
-__global__ __launch_bounds__(256) void k_build_list(ListArgs a)
+template <bool STAGED, bool IMG, bool HALF>
+__device__ __forceinline__ void scan_atom(const ListArgs &a, const Stage &st, const BrickGeom &g,
+                                          int64_t i, int32_t e, int32_t &ni_out)
+{
+    const int32_t *soff = st.rec + br_soff(a.bd), *sbeg = st.rec + br_sbeg(a.bd);
+    const int32_t lc[3] = {e % g.e[0], (e / g.e[0]) % g.e[1], e / (g.e[0] * g.e[1])};
+    int32_t np[3];
+    bool wrap[3];
+    for (int d = 0; d < 3; d++) {
+        const int32_t c = g.o[d] + lc[d];
+        np[d] = g.nc[d] >= 3 ? 3 : 2;
+        wrap[d] = IMG && !(g.nc[d] >= 5 && c >= 1 && c <= g.nc[d] - 2);
+    }
+    // halo position of stencil layer s (offset s - 1) along axis d: (lc + s) mod nc
+    const int32_t hown = (lc[0] + 1) % g.nc[0] + g.hn[0] * ((lc[1] + 1) % g.nc[1] + g.hn[1] * ((lc[2] + 1) % g.nc[2]));
+    const int32_t kself = soff[hown] + (int32_t)(i - sbeg[hown]);
+    const RepDesc &rep = a.reps[g.r];
+    const double Lx = rep.L[0], Ly = rep.L[1], Lz = rep.L[2];
+    const double hx = rep.hL[0], hy = rep.hL[1], hz = rep.hL[2];
+    const double rl2 = a.rl2;
+    const double4 xi = a.src[i];
+    // entry p of this atom is word base + (p / 4) * 256 + p % 4
+    uint32_t *base = a.nbr + (((i >> 6) * (int64_t)(a.M >> 2)) << 8) + ((i & 63) << 2);
+    const int32_t M = a.nbr == nullptr ? 0 : a.M;
+    const int32_t xa = lc[0] % g.nc[0];
+    const int32_t x1 = xa + np[0] < g.hn[0] ? xa + np[0] : g.hn[0];
+    const int32_t x2 = xa + np[0] - x1;   // wrapped part of the row: positions [0, x2)
+    int32_t ni = 0;
+    for (int sz = 0; sz < np[2]; sz++)
+        for (int sy = 0; sy < np[1]; sy++) {
+            const int32_t rowh = g.hn[0] * ((lc[1] + sy) % g.nc[1] + g.hn[1] * ((lc[2] + sz) % g.nc[2]));
+            for (int part = 0; part < 2; part++) {
+                const int32_t kb = part == 0 ? soff[rowh + xa] : soff[rowh];
+                const int32_t ke = part == 0 ? soff[rowh + x1] : soff[rowh + x2];
+                for (int32_t k0 = kb; k0 < ke; k0 += 4) {
+                    // phase 1: the four candidates' positions (and sorted indices)
+                    double px[4], py[4], pz[4];
+                    int64_t pj[4];
+                    _Pragma("unroll")
+                    for (int u = 0; u < 4; u++) {
+                        const int32_t kk = k0 + u < ke ? k0 + u : kb;
+                        pj[u] = 0;
+                        if (STAGED || kk < st.cap) {
+                            const double *q = st.xyz + 3 * kk;
+                            px[u] = q[0];
+                            py[u] = q[1];
+                            pz[u] = q[2];
+                            if (HALF) pj[u] = st.j[kk];
+                        } else {
+                            const int32_t j = candidate_index(st, a.bd, kk);
+                            const double4 p = a.src[j];
+                            px[u] = p.x;
+                            py[u] = p.y;
+                            pz[u] = p.z;
+                            pj[u] = j;
+                        }
+                    }
+                    // phase 2: distance test
+                    bool hit[4];
+                    uint32_t code[4];
+                    _Pragma("unroll")
+                    for (int u = 0; u < 4; u++) {
+                        double dx = xi.x - px[u], dy = xi.y - py[u], dz = xi.z - pz[u];
+                        code[u] = 0;
+                        if (IMG) {
+                            const bool gx = wrap[0] && dx > hx, lx = wrap[0] && dx < -hx;
+                            const bool gy = wrap[1] && dy > hy, ly = wrap[1] && dy < -hy;
+                            const bool gz = wrap[2] && dz > hz, lz = wrap[2] && dz < -hz;
+                            dx = gx ? dx - Lx : (lx ? dx + Lx : dx);
+                            dy = gy ? dy - Ly : (ly ? dy + Ly : dy);
+                            dz = gz ? dz - Lz : (lz ? dz + Lz : dz);
+                            code[u] = (gx ? 2u : (lx ? 1u : 0u)) | (gy ? 8u : (ly ? 4u : 0u)) |
+                                      (gz ? 32u : (lz ? 16u : 0u));
+                        }
+                        const double r2 = (dx * dx + dy * dy) + dz * dz;
+                        const int32_t k = k0 + u;
+                        hit[u] = (k < ke) && (r2 < rl2) && (k != kself) && (!HALF || pj[u] > i);
+                    }
+                    // phase 3: append the hits in candidate order
+                    _Pragma("unroll")
+                    for (int u = 0; u < 4; u++) {
+                        if (hit[u]) {
+                            if (ni < M)
+                                base[((int64_t)(ni >> 2) << 8) + (ni & 3)] =
+                                    (uint32_t)(k0 + u) | (code[u] << MD_IDX_BITS);
+                            ni++;
+                        }
+                    }
+                }
+            }
+        }
+    ni_out = ni;
+}
+
+__global__ __launch_bounds__(TASK_MAX_THREADS) void k_build_list(ListArgs a)
 {
     if (*a.pred == 0) return;
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    __shared__ int32_t smax[4], stot[4];
+    __shared__ int32_t smax[TASK_MAX_THREADS / 64], stot[TASK_MAX_THREADS / 64], sbr[TASK_MAX_THREADS / 64];
+    const Stage st = stage_slice(lds_raw, a.cap, 0, a.half != 0);
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    const Stage st = stage_slice(lds_raw, 0, a.cap, 0);
-    const ItemRange it = xcd_items(a.C, 1, 0);
-    int32_t wave_max = 0, wave_tot = 0;
+    const ItemRange it = xcd_items(a.B, 1, 0);
+    int32_t my_max = 0, my_tot = 0, my_br = 0;
 
-    for (int64_t c = it.first; c < it.end; c += it.stride) {
-        const int32_t s0 = a.start[c], s1 = a.start[c + 1];
-        if (s1 == s0) continue;
-        const CellGeom g = cell_geom(a.reps, a.R, c);
+    for (int64_t b = it.first; b < it.end; b += it.stride) {
+        const BrickGeom g = brick_geom(a.reps, a.R, b);
         __syncthreads();
-        if (w == 0) nbhd_setup(a.reps, g, a.start, *st.L);
-        __syncthreads();
-        task_stage(st, a.src, nullptr);
-        __syncthreads();
-        const int32_t total = st.L->soff[27];
-        wave_tot = total > wave_tot ? total : wave_tot;
-
-        const RepDesc &rep = a.reps[g.r];
-        const double Lx = rep.L[0], Ly = rep.L[1], Lz = rep.L[2];
-        const double hx = rep.hL[0], hy = rep.hL[1], hz = rep.hL[2];
-        const bool wrapx = !(g.nx >= 5 && g.cx >= 1 && g.cx <= g.nx - 2);
-        const bool wrapy = !(g.ny >= 5 && g.cy >= 1 && g.cy <= g.ny - 2);
-        const bool wrapz = !(g.nz >= 5 && g.cz >= 1 && g.cz <= g.nz - 2);
-        const int32_t gself0 = nbhd_centre(*st.L);
-        const bool all_staged = total <= st.cap;
-
-        for (int32_t i = s0 + w; i < s1; i += 4) {
-            const double4 xi = a.src[i];
-            const int32_t gself = gself0 + (i - s0);
-            const int64_t row = i * (int64_t)a.M;
-            int32_t ni = 0;
-            STAGED_SPLIT(all_staged,
-            for (int32_t k0 = 0; k0 < total; k0 += 64) {
-                const int32_t k = k0 + lane;
-                bool hit = false;
-                uint32_t code = 0;
-                if (k < total) {
-                    double xj, yj, zj;
-                    int32_t j;
-                    candidate<STAGED>(st, k, a.src, xj, yj, zj, j);
-                    double dx = xi.x - xj, dy = xi.y - yj, dz = xi.z - zj;
-                    if (wrapx) {
-                        if (dx > hx) { dx = dx - Lx; code |= 2u; }
-                        else if (dx < -hx) { dx = dx + Lx; code |= 1u; }
-                    }
-                    if (wrapy) {
-                        if (dy > hy) { dy = dy - Ly; code |= 8u; }
-                        else if (dy < -hy) { dy = dy + Ly; code |= 4u; }
-                    }
-                    if (wrapz) {
-                        if (dz > hz) { dz = dz - Lz; code |= 32u; }
-                        else if (dz < -hz) { dz = dz + Lz; code |= 16u; }
-                    }
-                    const double r2 = (dx * dx + dy * dy) + dz * dz;
-                    hit = (r2 < a.rl2) && (k != gself) && (!a.half || j > i);
-                }
-                const uint64_t mask = __ballot(hit);
-                const int32_t p = ni + (int32_t)lanes_below(mask);
-                if (hit && p < a.M) a.nbr[row + p] = (uint32_t)k | (code << MD_IDX_BITS);
-                ni += __popcll(mask);
-            }
-            )
-            if (lane == 0) a.cnt[i] = ni;
-            wave_max = ni > wave_max ? ni : wave_max;
+        brick_setup(st, a.bd, g, a.start);
+        int32_t *grec = a.brec + b * (int64_t)a.bd.stride;
+        for (int32_t t = threadIdx.x; t < a.bd.stride; t += blockDim.x) grec[t] = st.rec[t];
+        const int32_t natoms = st.rec[BR_ATOMS];
+        if (natoms == 0) continue;
+        const int32_t total = st.rec[BR_TOTAL];
+        my_tot = total > my_tot ? total : my_tot;
+        my_br = natoms > my_br ? natoms : my_br;
+        const int32_t lim = total < st.cap ? total : st.cap;
+        for (int32_t k = threadIdx.x; k < lim; k += blockDim.x) {
+            const int32_t jj = candidate_index(st, a.bd, k);
+            const double4 p = a.src[jj];
+            st.xyz[3 * k] = p.x;
+            st.xyz[3 * k + 1] = p.y;
+            st.xyz[3 * k + 2] = p.z;
+            if (st.j != nullptr) st.j[k] = jj;
         }
-
-        // copy the freshly sorted state of this cell into the working buffers
-        if (a.pos_dst != nullptr) {
-            for (int32_t i = s0 + threadIdx.x; i < s1; i += 256) {
+        __syncthreads();
+        const bool all_staged = total <= st.cap;
+        const bool has_img = st.rec[BR_IMG] != 0;
+        for (int32_t a0 = 0; a0 < natoms; a0 += (int32_t)blockDim.x) {
+            const int32_t la = a0 + (int32_t)threadIdx.x;
+            if (la >= natoms) continue;
+            int32_t e;
+            const int64_t i = brick_atom(st, a.bd, la, &e);
+            int32_t ni = 0;
+            if (a.half) {
+                STAGE_IMG_SPLIT(all_staged, has_img, scan_atom<STAGED, IMG, true>(a, st, g, i, e, ni);)
+            } else {
+                STAGE_IMG_SPLIT(all_staged, has_img, scan_atom<STAGED, IMG, false>(a, st, g, i, e, ni);)
+            }
+            a.cnt[i] = ni;
+            my_max = ni > my_max ? ni : my_max;
+            // copy the freshly sorted state of this atom into the working buffers
+            if (a.pos_dst != nullptr) {
                 const double4 p = a.src[i];
                 a.pos_dst[i] = p;
                 a.xref[i] = p;
@@ -108,28 +180,36 @@ __global__ __launch_bounds__(256) void k_build_list(ListArgs a)
         }
     }
     // one atomic per workgroup (a per-atom atomic on one word would serialise in L2)
+    for (int o = 32; o > 0; o >>= 1) {
+        my_max = max(my_max, __shfl_xor(my_max, o, 64));
+        my_tot = max(my_tot, __shfl_xor(my_tot, o, 64));
+        my_br = max(my_br, __shfl_xor(my_br, o, 64));
+    }
     if (lane == 0) {
-        smax[w] = wave_max;
-        stot[w] = wave_tot;
+        smax[w] = my_max;
+        stot[w] = my_tot;
+        sbr[w] = my_br;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int32_t m = smax[0], t = stot[0];
-        for (int k = 1; k < 4; k++) {
-            m = smax[k] > m ? smax[k] : m;
-            t = stot[k] > t ? stot[k] : t;
+        int32_t m = smax[0], t = stot[0], q = sbr[0];
+        for (int k = 1; k < (int)(blockDim.x >> 6); k++) {
+            m = max(m, smax[k]);
+            t = max(t, stot[k]);
+            q = max(q, sbr[k]);
         }
         atomicMax(&a.ctl->max_cnt, m);
         atomicMax(&a.ctl->max_nbhd, t);
+        atomicMax(&a.ctl->max_brick, q);
         if (m > a.M && a.M > 0) atomicOr(&a.ctl->err, MD_FLAG_OVERFLOW);
     }
 }
 
 } // namespace
 
-void launch_build_list(hipStream_t s, int grid, const ListArgs &a)
+void launch_build_list(hipStream_t s, int grid, int threads, const ListArgs &a)
 {
-    const size_t lds = nbhd_lds_bytes(a.cap, 0);
+    const size_t lds = stage_bytes(a.cap, 0, a.half != 0, a.bd.stride);
     allow_lds(k_build_list, lds);
-    hipLaunchKernelGGL(k_build_list, dim3(grid), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(k_build_list, dim3(grid), dim3(threads), lds, s, a);
 }

@@ -17,16 +17,22 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// sums v[0..3] over a 256-thread block; every thread receives the totals
-__device__ __forceinline__ void block_sum4(double v[4], double *lds /* [16] */)
+// sums v[0..3] over a block of up to 512 threads (a multiple of 64); every
+// thread receives the totals, added wave by wave in wave order
+__device__ __forceinline__ void block_sum4(double v[4], double *lds /* [4 * waves] */)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nw = (int)(blockDim.x >> 6);
     for (int c = 0; c < 4; c++) v[c] = wave_sum(v[c]);
     __syncthreads();
     if (lane == 0)
         for (int c = 0; c < 4; c++) lds[w * 4 + c] = v[c];
     __syncthreads();
-    for (int c = 0; c < 4; c++) v[c] = ((lds[c] + lds[4 + c]) + lds[8 + c]) + lds[12 + c];
+    for (int c = 0; c < 4; c++) {
+        double t = lds[c];
+        for (int k = 1; k < nw; k++) t += lds[4 * k + c];
+        v[c] = t;
+    }
     __syncthreads();
 }
 

@@ -14,13 +14,13 @@
 //        g = phi' + (F'_i + F'_j) rho';  table coefficient (k, p) gradients are
 //        histograms over pairs (phi, rho) and atoms (embedding) of t^p and
 //        p t^(p-1)/h weights.
-// The kernels are cell tasks like the force kernels (md_nbhd.h).  The full list
-// visits every pair from both atoms, so position terms need no atomics; pair
-// parameter terms are taken once per pair (j after i).  The adjoint always
-// evaluates in binary64.
+// The kernels are brick tasks like the force kernels (md_brick.h), one lane per
+// atom.  The full list visits every pair from both atoms, so position terms
+// need no atomics; pair parameter terms are taken once per pair (j after i).
+// The adjoint always evaluates in binary64.
 #include <math.h>
 
-#include "md_nbhd.h"
+#include "md_brick.h"
 #include "md_reduce.h"
 
 namespace {
@@ -66,75 +66,53 @@ __device__ __forceinline__ void embed_full(const ForceArgs &a, double rho, doubl
 }
 
 // ---------------------------------------------------------------- LJ
-__global__ __launch_bounds__(256) void k_lj_vjp(VjpArgs v)
+__global__ __launch_bounds__(TASK_MAX_THREADS) void k_lj_vjp(VjpArgs v)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    __shared__ double red[TASK_THREADS];
-    __shared__ double lds[16];
+    __shared__ double lds[4 * TASK_MAX_THREADS / 64];
     const ForceArgs &a = v.f;
-    const Stage st = stage_slice(lds_raw, 0, a.cap, 0);
+    const Stage st = stage_slice(lds_raw, a.cap, 0, true);
     const int64_t n = a.n;
     const double eps = a.lj[0], sig = a.lj[1];
     const double s2 = sig * sig;
+    const double rc2 = a.rc2;
     double acc_e = 0.0, acc_s = 0.0;
-    CELL_TASK_BEGIN(nullptr)
+    BRICK_TASK_BEGIN(st, a.pos, nullptr, nullptr)
         double F[3] = {0.0, 0.0, 0.0}, Hu[3] = {0.0, 0.0, 0.0};
-        double vE = 0.0;
-        double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
-        double ui[3] = {0.0, 0.0, 0.0};
-        if (valid) {
-            xi = a.pos[i];
-            ui[0] = v.u[i];
-            ui[1] = v.u[n + i];
-            ui[2] = v.u[2 * n + i];
-            vE = v.vE[g_.r];
-        }
+        const double vE = v.vE[rep_r];
+        const double4 xi = a.pos[i];
+        const double ui[3] = {v.u[i], v.u[n + i], v.u[2 * n + i]};
         STAGED_SPLIT(all_staged,
-        for (int32_t q = sub; q < nq; q += tpa) {
-            const uint4 ev = row4[q];
-            const uint32_t es[4] = {ev.x, ev.y, ev.z, ev.w};
-            for (int uu = 0; uu < 4; uu++) {
-                if (4 * q + uu >= mm) break;
-                const uint32_t en = es[uu];
-                double xj, yj, zj;
-                int32_t j;
-                candidate<STAGED>(st, (int32_t)(en & MD_IDX_MASK), a.pos, xj, yj, zj, j);
-                double d[3] = {xi.x - xj, xi.y - yj, xi.z - zj};
-                if (en >> MD_IDX_BITS) apply_image_code(en, Lx, Ly, Lz, d[0], d[1], d[2]);
-                const double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
-                if (!(r2 < a.rc2)) continue;
-                const double ir2 = rcp64(r2);
-                const double q2 = s2 * ir2;
-                const double q6 = q2 * q2 * q2;
-                const double q12 = q6 * q6;
-                const double fs = 24.0 * eps * (2.0 * q12 - q6) * ir2;
-                const double B = -fs;
-                const double C = 96.0 * eps * (7.0 * q12 - 2.0 * q6) * (ir2 * ir2);
-                const double uij[3] = {ui[0] - v.u[j], ui[1] - v.u[n + j], ui[2] - v.u[2 * n + j]};
-                const double du = (d[0] * uij[0] + d[1] * uij[1]) + d[2] * uij[2];
-                for (int k = 0; k < 3; k++) {
-                    F[k] = fma(fs, d[k], F[k]);
-                    Hu[k] += B * uij[k] + C * du * d[k];
-                }
-                // each unordered pair is visited twice: half weight
-                const double dVde = 4.0 * (q12 - q6);
-                const double dVds = 24.0 * eps * (2.0 * q12 - q6) / sig;
-                const double dufe = du * 24.0 * (2.0 * q12 - q6) * ir2;
-                const double dufs = du * 144.0 * eps * (4.0 * q12 - q6) * ir2 / sig;
-                acc_e += 0.5 * (vE * dVde + dufe);
-                acc_s += 0.5 * (vE * dVds + dufs);
-            }
-        }
+            walk_list<STAGED, true>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
+                [&](bool ok, int32_t k, double dx, double dy, double dz, double r2) {
+                    if (!ok || !(r2 < rc2)) return;
+                    const int32_t j = candidate_j<STAGED>(st, a.bd, k);
+                    const double d[3] = {dx, dy, dz};
+                    const double ir2 = rcp64(r2);
+                    const double q2 = s2 * ir2;
+                    const double q6 = q2 * q2 * q2;
+                    const double q12 = q6 * q6;
+                    const double fs = 24.0 * eps * (2.0 * q12 - q6) * ir2;
+                    const double B = -fs;
+                    const double C = 96.0 * eps * (7.0 * q12 - 2.0 * q6) * (ir2 * ir2);
+                    const double uij[3] = {ui[0] - v.u[j], ui[1] - v.u[n + j], ui[2] - v.u[2 * n + j]};
+                    const double du = (d[0] * uij[0] + d[1] * uij[1]) + d[2] * uij[2];
+                    for (int c = 0; c < 3; c++) {
+                        F[c] = fma(fs, d[c], F[c]);
+                        Hu[c] += B * uij[c] + C * du * d[c];
+                    }
+                    // each unordered pair is visited twice: half weight
+                    const double dVde = 4.0 * (q12 - q6);
+                    const double dVds = 24.0 * eps * (2.0 * q12 - q6) / sig;
+                    const double dufe = du * 24.0 * (2.0 * q12 - q6) * ir2;
+                    const double dufs = du * 144.0 * eps * (4.0 * q12 - q6) * ir2 / sig;
+                    acc_e += 0.5 * (vE * dVde + dufe);
+                    acc_s += 0.5 * (vE * dVds + dufs);
+                });
         )
-        double gv[6] = {F[0], F[1], F[2], Hu[0], Hu[1], Hu[2]};
-        task_group_sum(gv, tpa, am, red);
-        for (int k = 0; k < 3; k++) {
-            F[k] = gv[k];
-            Hu[k] = gv[3 + k];
-        }
-        if (valid && sub == 0)
-            for (int k = 0; k < 3; k++) v.gx[k * n + i] = -vE * F[k] - Hu[k];
-    CELL_TASK_END
+        if (valid)
+            for (int c = 0; c < 3; c++) v.gx[c * n + i] = -vE * F[c] - Hu[c];
+    BRICK_TASK_END
     double s[4] = {acc_e, acc_s, 0.0, 0.0};
     if (mdred::last_block_sum4(s, v.gpart, a.done, lds) && threadIdx.x == 0 && v.gout != nullptr) {
         v.gout[0] = s[0];
@@ -143,55 +121,34 @@ __global__ __launch_bounds__(256) void k_lj_vjp(VjpArgs v)
 }
 
 // ---------------------------------------------------------------- EAM pass A
-__global__ __launch_bounds__(256) void k_eam_vjp_a(VjpArgs v)
+__global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_vjp_a(VjpArgs v)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    __shared__ double red[TASK_THREADS];
     const ForceArgs &a = v.f;
-    const Stage st = stage_slice(lds_raw, 0, a.cap, 0);
+    const Stage st = stage_slice(lds_raw, a.cap, 0, true);
     const int64_t n = a.n;
     const int nkr = a.nk[1];
-    const double x0r = a.x0[1], ihr = a.inv_h[1];
-    CELL_TASK_BEGIN(nullptr)
+    const double x0r = a.x0[1], ihr = a.inv_h[1], rrho2 = a.rrho2;
+    BRICK_TASK_BEGIN(st, a.pos, nullptr, nullptr)
         double rho = 0.0, rdot = 0.0;
-        double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
-        double ui[3] = {0.0, 0.0, 0.0};
-        if (valid) {
-            xi = a.pos[i];
-            ui[0] = v.u[i];
-            ui[1] = v.u[n + i];
-            ui[2] = v.u[2 * n + i];
-        }
+        const double4 xi = a.pos[i];
+        const double ui[3] = {v.u[i], v.u[n + i], v.u[2 * n + i]};
         STAGED_SPLIT(all_staged,
-        for (int32_t q = sub; q < nq; q += tpa) {
-            const uint4 ev = row4[q];
-            const uint32_t es[4] = {ev.x, ev.y, ev.z, ev.w};
-            for (int uu = 0; uu < 4; uu++) {
-                if (4 * q + uu >= mm) break;
-                const uint32_t en = es[uu];
-                double xj, yj, zj;
-                int32_t j;
-                candidate<STAGED>(st, (int32_t)(en & MD_IDX_MASK), a.pos, xj, yj, zj, j);
-                double d[3] = {xi.x - xj, xi.y - yj, xi.z - zj};
-                if (en >> MD_IDX_BITS) apply_image_code(en, Lx, Ly, Lz, d[0], d[1], d[2]);
-                const double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
-                if (!(r2 < a.rrho2)) continue;
-                const double r = sqrt(r2);
-                int kk;
-                double tt, f, fu, fuu;
-                spl_full(a.tab[1], (r - x0r) * ihr, nkr, kk, tt, f, fu, fuu);
-                const double uij[3] = {ui[0] - v.u[j], ui[1] - v.u[n + j], ui[2] - v.u[2 * n + j]};
-                const double s = ((d[0] * uij[0] + d[1] * uij[1]) + d[2] * uij[2]) / r;
-                rho += f;
-                rdot += (fu * ihr) * s;
-            }
-        }
+            walk_list<STAGED, true>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
+                [&](bool ok, int32_t k, double dx, double dy, double dz, double r2) {
+                    if (!ok || !(r2 < rrho2)) return;
+                    const int32_t j = candidate_j<STAGED>(st, a.bd, k);
+                    const double r = sqrt(r2);
+                    int kk;
+                    double tt, f, fu, fuu;
+                    spl_full(a.tab[1], (r - x0r) * ihr, nkr, kk, tt, f, fu, fuu);
+                    const double uij[3] = {ui[0] - v.u[j], ui[1] - v.u[n + j], ui[2] - v.u[2 * n + j]};
+                    const double s = ((dx * uij[0] + dy * uij[1]) + dz * uij[2]) / r;
+                    rho += f;
+                    rdot += (fu * ihr) * s;
+                });
         )
-        double gv[2] = {rho, rdot};
-        task_group_sum(gv, tpa, am, red);
-        rho = gv[0];
-        rdot = gv[1];
-        if (valid && sub == 0) {
+        if (valid) {
             double F, Fp, Fpp, tt;
             int kk;
             bool lin;
@@ -201,106 +158,83 @@ __global__ __launch_bounds__(256) void k_eam_vjp_a(VjpArgs v)
             v.fpp[i] = Fpp;
             v.rdot[i] = rdot;
         }
-    CELL_TASK_END
+    BRICK_TASK_END
 }
 
 // ---------------------------------------------------------------- EAM pass B
-__global__ __launch_bounds__(256) void k_eam_vjp_b(VjpArgs v)
+__global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_vjp_b(VjpArgs v)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    __shared__ double red[TASK_THREADS];
     const ForceArgs &a = v.f;
-    const Stage st = stage_slice(lds_raw, 0, a.cap, 0);
+    const Stage st = stage_slice(lds_raw, a.cap, 0, true);
     const int64_t n = a.n;
     const int nkp = a.nk[0], nkr = a.nk[1];
     const double x0p = a.x0[0], ihp = a.inv_h[0], x0r = a.x0[1], ihr = a.inv_h[1];
+    const double rphi2 = a.rphi2, rrho2 = a.rrho2;
     double *gphi = v.gtab;
     double *grho = v.gtab + 4 * (int64_t)(nkp - 1);
-    CELL_TASK_BEGIN(nullptr)
+    BRICK_TASK_BEGIN(st, a.pos, nullptr, nullptr)
         double F[3] = {0.0, 0.0, 0.0}, Hu[3] = {0.0, 0.0, 0.0};
-        double vE = 0.0, fpi = 0.0, qi = 0.0;
-        double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
-        double ui[3] = {0.0, 0.0, 0.0};
-        if (valid) {
-            xi = a.pos[i];
-            ui[0] = v.u[i];
-            ui[1] = v.u[n + i];
-            ui[2] = v.u[2 * n + i];
-            fpi = a.fp[i];
-            qi = v.fpp[i] * v.rdot[i];
-            vE = v.vE[g_.r];
-        }
+        const double vE = v.vE[rep_r];
+        const double4 xi = a.pos[i];
+        const double ui[3] = {v.u[i], v.u[n + i], v.u[2 * n + i]};
+        const double fpi = a.fp[i];
+        const double qi = v.fpp[i] * v.rdot[i];
         STAGED_SPLIT(all_staged,
-        for (int32_t q = sub; q < nq; q += tpa) {
-            const uint4 ev = row4[q];
-            const uint32_t es[4] = {ev.x, ev.y, ev.z, ev.w};
-            for (int uu = 0; uu < 4; uu++) {
-                if (4 * q + uu >= mm) break;
-                const uint32_t en = es[uu];
-                double xj, yj, zj;
-                int32_t j;
-                candidate<STAGED>(st, (int32_t)(en & MD_IDX_MASK), a.pos, xj, yj, zj, j);
-                double d[3] = {xi.x - xj, xi.y - yj, xi.z - zj};
-                if (en >> MD_IDX_BITS) apply_image_code(en, Lx, Ly, Lz, d[0], d[1], d[2]);
-                const double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
-                const bool in_phi = r2 < a.rphi2, in_rho = r2 < a.rrho2;
-                if (!in_phi && !in_rho) continue;
-                const double r = sqrt(r2);
-                const double e[3] = {d[0] / r, d[1] / r, d[2] / r};
-                const double uij[3] = {ui[0] - v.u[j], ui[1] - v.u[n + j], ui[2] - v.u[2 * n + j]};
-                const double s = (e[0] * uij[0] + e[1] * uij[1]) + e[2] * uij[2];
-                double ph = 0.0, php = 0.0, phpp = 0.0, rh = 0.0, rhp = 0.0, rhpp = 0.0;
-                double tp = 0.0, tr = 0.0;
-                int kp = 0, kr = 0;
-                if (in_phi) {
-                    double fu, fuu;
-                    spl_full(a.tab[0], (r - x0p) * ihp, nkp, kp, tp, ph, fu, fuu);
-                    php = fu * ihp;
-                    phpp = fuu * (ihp * ihp);
-                }
-                if (in_rho) {
-                    double fu, fuu;
-                    spl_full(a.tab[1], (r - x0r) * ihr, nkr, kr, tr, rh, fu, fuu);
-                    rhp = fu * ihr;
-                    rhpp = fuu * (ihr * ihr);
-                }
-                const double Fs = fpi + a.fp[j];
-                const double gsc = php + Fs * rhp;
-                const double gg = phpp + Fs * rhpp;
-                const double qq = qi + v.fpp[j] * v.rdot[j];
-                for (int k = 0; k < 3; k++) {
-                    F[k] -= gsc * e[k];
-                    Hu[k] += gg * s * e[k] + (gsc / r) * (uij[k] - s * e[k]) + qq * rhp * e[k];
-                }
-                if (v.gtab != nullptr && j > i) {
+            walk_list<STAGED, true>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
+                [&](bool ok, int32_t k, double dx, double dy, double dz, double r2) {
+                    const bool in_phi = r2 < rphi2, in_rho = r2 < rrho2;
+                    if (!ok || (!in_phi && !in_rho)) return;
+                    const int32_t j = candidate_j<STAGED>(st, a.bd, k);
+                    const double r = sqrt(r2);
+                    const double e[3] = {dx / r, dy / r, dz / r};
+                    const double uij[3] = {ui[0] - v.u[j], ui[1] - v.u[n + j], ui[2] - v.u[2 * n + j]};
+                    const double s = (e[0] * uij[0] + e[1] * uij[1]) + e[2] * uij[2];
+                    double ph = 0.0, php = 0.0, phpp = 0.0, rh = 0.0, rhp = 0.0, rhpp = 0.0;
+                    double tp = 0.0, tr = 0.0;
+                    int kp = 0, kr = 0;
                     if (in_phi) {
-                        const double t2 = tp * tp;
-                        const double pw[4] = {1.0, tp, t2, t2 * tp};
-                        const double dp[4] = {0.0, 1.0, 2.0 * tp, 3.0 * t2};
-                        for (int p = 0; p < 4; p++)
-                            atomicAdd(&gphi[4 * (int64_t)kp + p], vE * pw[p] - s * dp[p] * ihp);
+                        double fu, fuu;
+                        spl_full(a.tab[0], (r - x0p) * ihp, nkp, kp, tp, ph, fu, fuu);
+                        php = fu * ihp;
+                        phpp = fuu * (ihp * ihp);
                     }
                     if (in_rho) {
-                        const double t2 = tr * tr;
-                        const double pw[4] = {1.0, tr, t2, t2 * tr};
-                        const double dp[4] = {0.0, 1.0, 2.0 * tr, 3.0 * t2};
-                        for (int p = 0; p < 4; p++)
-                            atomicAdd(&grho[4 * (int64_t)kr + p],
-                                      vE * Fs * pw[p] - (s * Fs * dp[p] * ihr + qq * pw[p]));
+                        double fu, fuu;
+                        spl_full(a.tab[1], (r - x0r) * ihr, nkr, kr, tr, rh, fu, fuu);
+                        rhp = fu * ihr;
+                        rhpp = fuu * (ihr * ihr);
                     }
-                }
-            }
-        }
+                    const double Fs = fpi + a.fp[j];
+                    const double gsc = php + Fs * rhp;
+                    const double gg = phpp + Fs * rhpp;
+                    const double qq = qi + v.fpp[j] * v.rdot[j];
+                    for (int c = 0; c < 3; c++) {
+                        F[c] -= gsc * e[c];
+                        Hu[c] += gg * s * e[c] + (gsc / r) * (uij[c] - s * e[c]) + qq * rhp * e[c];
+                    }
+                    if (v.gtab != nullptr && j > i) {
+                        if (in_phi) {
+                            const double t2 = tp * tp;
+                            const double pw[4] = {1.0, tp, t2, t2 * tp};
+                            const double dp[4] = {0.0, 1.0, 2.0 * tp, 3.0 * t2};
+                            for (int p = 0; p < 4; p++)
+                                atomicAdd(&gphi[4 * (int64_t)kp + p], vE * pw[p] - s * dp[p] * ihp);
+                        }
+                        if (in_rho) {
+                            const double t2 = tr * tr;
+                            const double pw[4] = {1.0, tr, t2, t2 * tr};
+                            const double dp[4] = {0.0, 1.0, 2.0 * tr, 3.0 * t2};
+                            for (int p = 0; p < 4; p++)
+                                atomicAdd(&grho[4 * (int64_t)kr + p],
+                                          vE * Fs * pw[p] - (s * Fs * dp[p] * ihr + qq * pw[p]));
+                        }
+                    }
+                });
         )
-        double gv[6] = {F[0], F[1], F[2], Hu[0], Hu[1], Hu[2]};
-        task_group_sum(gv, tpa, am, red);
-        for (int k = 0; k < 3; k++) {
-            F[k] = gv[k];
-            Hu[k] = gv[3 + k];
-        }
-        if (valid && sub == 0)
-            for (int k = 0; k < 3; k++) v.gx[k * n + i] = -vE * F[k] - Hu[k];
-    CELL_TASK_END
+        if (valid)
+            for (int c = 0; c < 3; c++) v.gx[c * n + i] = -vE * F[c] - Hu[c];
+    BRICK_TASK_END
 }
 
 // embedding-table gradient: one entry per atom
@@ -337,28 +271,25 @@ __global__ __launch_bounds__(256) void k_eam_vjp_embed(VjpArgs v)
 
 } // namespace
 
-void launch_lj_vjp(hipStream_t s, int grid, int tpp, bool mixed, const VjpArgs &a)
+void launch_lj_vjp(hipStream_t s, int grid, int threads, const VjpArgs &a)
 {
-    (void)mixed;
-    (void)tpp;
-    allow_lds(k_lj_vjp, nbhd_lds_bytes(a.f.cap, 0));
-    hipLaunchKernelGGL(k_lj_vjp, dim3(grid), dim3(256), nbhd_lds_bytes(a.f.cap, 0), s, a);
+    const size_t lds = stage_bytes(a.f.cap, 0, true, a.f.bd.stride);
+    allow_lds(k_lj_vjp, lds);
+    hipLaunchKernelGGL(k_lj_vjp, dim3(grid), dim3(threads), lds, s, a);
 }
 
-void launch_eam_vjp_a(hipStream_t s, int grid, int tpp, bool mixed, const VjpArgs &a)
+void launch_eam_vjp_a(hipStream_t s, int grid, int threads, const VjpArgs &a)
 {
-    (void)mixed;
-    (void)tpp;
-    allow_lds(k_eam_vjp_a, nbhd_lds_bytes(a.f.cap, 0));
-    hipLaunchKernelGGL(k_eam_vjp_a, dim3(grid), dim3(256), nbhd_lds_bytes(a.f.cap, 0), s, a);
+    const size_t lds = stage_bytes(a.f.cap, 0, true, a.f.bd.stride);
+    allow_lds(k_eam_vjp_a, lds);
+    hipLaunchKernelGGL(k_eam_vjp_a, dim3(grid), dim3(threads), lds, s, a);
 }
 
-void launch_eam_vjp_b(hipStream_t s, int grid, int tpp, bool mixed, const VjpArgs &a)
+void launch_eam_vjp_b(hipStream_t s, int grid, int threads, const VjpArgs &a)
 {
-    (void)mixed;
-    (void)tpp;
-    allow_lds(k_eam_vjp_b, nbhd_lds_bytes(a.f.cap, 0));
-    hipLaunchKernelGGL(k_eam_vjp_b, dim3(grid), dim3(256), nbhd_lds_bytes(a.f.cap, 0), s, a);
+    const size_t lds = stage_bytes(a.f.cap, 0, true, a.f.bd.stride);
+    allow_lds(k_eam_vjp_b, lds);
+    hipLaunchKernelGGL(k_eam_vjp_b, dim3(grid), dim3(threads), lds, s, a);
 }
 
 void launch_eam_vjp_embed(hipStream_t s, int grid, const VjpArgs &a)

@@ -129,6 +129,68 @@ def test_half_list_bit_exact(name):
     assert all(rank[j] > rank[i] for i, j in got)
 
 
+# ---------------------------------------------------------------- brick shapes
+# (bx, by, bz) cells per task, and a small LDS stage that sends part of every
+# halo through the global-memory path
+SHAPES = [((1, 1, 1), 0), ((2, 2, 3), 0), ((4, 4, 4), 0), ((3, 1, 2), 0), ((8, 8, 1), 0), ((2, 2, 3), 64)]
+
+
+def shaped_system(w, shape, cap):
+    s = MDSystem.from_workload(w)
+    B.md_set_tuning(s.ctx, 3, shape[0] | shape[1] << 8 | shape[2] << 16)
+    if cap:
+        B.md_set_tuning(s.ctx, 0, cap)
+    return s
+
+
+@pytest.mark.parametrize("name", ["box_2x3x5", "fcc2048_thermal", "ragged_6859"])
+@pytest.mark.parametrize("shape,cap", SHAPES)
+def test_brick_shapes_lists_and_forces(name, shape, cap):
+    w = materialise(lj_cases()[name])
+    L = w.boxes[0]
+    x = oracle.wrap(w.pos, L)
+    s = shaped_system(w, shape, cap)
+    s.build(B.MD_LIST_FULL)
+    start, nbr = s.neighbor_list()
+    os_, on = oracle.neighbor_list(x, L, w.pot.rc + w.skin, full=True)
+    assert np.array_equal(start, os_)
+    assert user_pairs(start, nbr) == user_pairs(os_, on)
+    Fo, Eo, Wo = oracle.forces(x, L, w.pot, skin=w.skin)
+    for kind in (B.MD_LIST_FULL, B.MD_LIST_HALF):
+        F, E, Wv = s.forces(B.MD_FP64, kind)
+        assert rel(F.cpu().numpy(), Fo) <= FP64_TOL
+        assert E.item() == pytest.approx(Eo, rel=FP64_TOL, abs=1e-12)
+        assert Wv.item() == pytest.approx(Wo, rel=FP64_TOL, abs=1e-12)
+    s.build(B.MD_LIST_HALF)
+    hs, hn = oracle.neighbor_list(x, L, w.pot.rc + w.skin, full=False)
+    assert user_pairs(*s.neighbor_list()) == user_pairs(hs, hn)
+
+
+@pytest.mark.parametrize("shape,cap", [((2, 2, 2), 0), ((1, 2, 3), 64)])
+def test_brick_shapes_eam_and_vjp(shape, cap):
+    w = eam_case(5, 8, sd=0.08)
+    L = w.boxes[0]
+    x = oracle.wrap(w.pos, L)
+    s = shaped_system(w, shape, cap)
+    F, E, Wv = s.forces(B.MD_FP64)
+    Fo, Eo, Wo = oracle.forces(x, L, w.pot, skin=w.skin)
+    assert rel(F.cpu().numpy(), Fo) <= 1e-11
+    assert E.item() == pytest.approx(Eo, rel=1e-12)
+    u = np.random.default_rng(22).normal(size=w.pos.shape)
+    gx, gp = s.vjp(u, np.array([0.4]))
+    gxo, gphi, grho, gemb = oracle.vjp(x, L, w.pot, u, 0.4, skin=w.skin)
+    assert rel(gx.cpu().numpy(), gxo) <= 1e-11
+    gpo = np.concatenate([gphi.ravel(), grho.ravel(), gemb.ravel()])
+    assert rel(gp.cpu().numpy(), gpo) <= 1e-10
+
+
+def test_bad_brick_shape_is_rejected():
+    s = MDSystem.from_workload(W.lj_small())
+    for v in (0 | 1 << 8 | 1 << 16, 9 | 1 << 8 | 1 << 16, 5 | 5 << 8 | 5 << 16):
+        with pytest.raises(B.MDError):
+            B.md_set_tuning(s.ctx, 3, v)
+
+
 # ---------------------------------------------------------------- LJ forces
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("kind", [B.MD_LIST_FULL, B.MD_LIST_HALF])
