@@ -44,31 +44,57 @@ __global__ void k_load_user(int64_t n, const double *__restrict__ pos_user,
     }
 }
 
+// Atoms arrive in the previous cell order, so neighbouring lanes usually fall
+// into the same cell: each run of equal cells among consecutive lanes of a
+// wavefront takes its slots with one atomic add by the run's first lane.
 __global__ void k_bin(const int32_t *__restrict__ pred, int64_t n, const RepDesc *__restrict__ reps,
                       const int32_t *__restrict__ rep_of, double4 *__restrict__ pos,
                       int32_t *__restrict__ cell_of, int32_t *__restrict__ slot,
                       int32_t *__restrict__ count)
 {
     if (*pred == 0) return;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const RepDesc &r = reps[rep_of[i]];
-        double4 p = pos[i];
-        p.x = wrap1(p.x, r.L[0]);
-        p.y = wrap1(p.y, r.L[1]);
-        p.z = wrap1(p.z, r.L[2]);
-        pos[i] = p;
-        int32_t cx = cell_coord(p.x, r.nc[0], r.L[0]);
-        int32_t cy = cell_coord(p.y, r.nc[1], r.L[1]);
-        int32_t cz = cell_coord(p.z, r.nc[2], r.L[2]);
-        int64_t c = r.cell_off + cx + (int64_t)r.nc[0] * (cy + (int64_t)r.nc[1] * cz);
-        cell_of[i] = (int32_t)c;
-        slot[i] = atomicAdd(&count[c], 1);
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += stride) {
+        const int64_t i = base + threadIdx.x;
+        const bool valid = i < n;
+        int32_t c = -1;
+        if (valid) {
+            const RepDesc &r = reps[rep_of[i]];
+            double4 p = pos[i];
+            p.x = wrap1(p.x, r.L[0]);
+            p.y = wrap1(p.y, r.L[1]);
+            p.z = wrap1(p.z, r.L[2]);
+            pos[i] = p;
+            const int32_t cx = cell_coord(p.x, r.nc[0], r.L[0]);
+            const int32_t cy = cell_coord(p.y, r.nc[1], r.L[1]);
+            const int32_t cz = cell_coord(p.z, r.nc[2], r.L[2]);
+            c = (int32_t)(r.cell_off + cx + (int64_t)r.nc[0] * (cy + (int64_t)r.nc[1] * cz));
+            cell_of[i] = c;
+        }
+        const int32_t prev = __shfl_up(c, 1, 64);
+        const bool head = valid && (lane == 0 || prev != c);
+        const uint64_t heads = __ballot(head);
+        const uint64_t live = __ballot(valid);
+        // first lane of this lane's run, and the first lane after it
+        const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+        const int leader = 63 - __clzll(heads & upto);
+        const uint64_t after = lane == 63 ? 0ull : (heads & ~upto);
+        const int nlive = __popcll(live);
+        int32_t b = 0;
+        if (head) {
+            const int next = after != 0 ? __ffsll((long long)after) - 1 : nlive;
+            b = atomicAdd(&count[c], next - lane);
+        }
+        b = __shfl(b, leader, 64);
+        if (valid) slot[i] = b + (lane - leader);
     }
 }
 
-// Exclusive scan of the cell counts by one workgroup of 1024 threads; each
-// thread owns a contiguous chunk.  The counts are cleared for the next build.
+// Exclusive scan of the cell counts by one workgroup of 1024 threads, in
+// chunks of 8192 cells: each thread takes 8 consecutive counts, the threads'
+// totals are scanned across the workgroup, and a carry links the chunks.  The
+// counts are cleared for the next build.
 __global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ pred, int64_t C,
                                                int32_t *__restrict__ count,
                                                int32_t *__restrict__ start, DevCtl *ctl)
@@ -77,48 +103,70 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ pred,
     __shared__ int32_t wsum[16];
     __shared__ int32_t wmax[16];
     const int t = threadIdx.x;
-    const int64_t chunk = (C + 1023) / 1024;
-    const int64_t lo = t * chunk < C ? t * chunk : C;
-    const int64_t hi = lo + chunk < C ? lo + chunk : C;
-    int32_t s = 0, mx = 0;
-    for (int64_t k = lo; k < hi; k++) {
-        int32_t v = count[k];
-        s += v;
-        mx = v > mx ? v : mx;
-    }
-    // inclusive scan within the wave, then across the 16 waves
     const int lane = t & 63, wv = t >> 6;
-    int32_t inc = s;
-    for (int o = 1; o < 64; o <<= 1) {
-        int32_t y = __shfl_up(inc, o, 64);
-        if (lane >= o) inc += y;
+    int32_t carry = 0, mx = 0;
+    for (int64_t c0 = 0; c0 < C; c0 += 8192) {
+        const int64_t k0 = c0 + 8 * (int64_t)t;
+        int32_t v[8];
+        if (k0 + 8 <= C) {
+            const int4 a = reinterpret_cast<const int4 *>(count + k0)[0];
+            const int4 b = reinterpret_cast<const int4 *>(count + k0)[1];
+            v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+            v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+        } else {
+            for (int q = 0; q < 8; q++) v[q] = k0 + q < C ? count[k0 + q] : 0;
+        }
+        int32_t s = 0;
+        for (int q = 0; q < 8; q++) {
+            s += v[q];
+            mx = v[q] > mx ? v[q] : mx;
+        }
+        int32_t inc = s;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t y = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += y;
+        }
+        if (lane == 63) wsum[wv] = inc;
+        __syncthreads();
+        int32_t before = 0, total = 0;
+        for (int w = 0; w < 16; w++) {
+            const int32_t ws = wsum[w];
+            before += w < wv ? ws : 0;
+            total += ws;
+        }
+        int32_t run = carry + before + inc - s;
+        int32_t o[8];
+        for (int q = 0; q < 8; q++) {
+            o[q] = run;
+            run += v[q];
+        }
+        if (k0 + 8 <= C) {
+            reinterpret_cast<int4 *>(start + k0)[0] = make_int4(o[0], o[1], o[2], o[3]);
+            reinterpret_cast<int4 *>(start + k0)[1] = make_int4(o[4], o[5], o[6], o[7]);
+            reinterpret_cast<int4 *>(count + k0)[0] = make_int4(0, 0, 0, 0);
+            reinterpret_cast<int4 *>(count + k0)[1] = make_int4(0, 0, 0, 0);
+        } else {
+            for (int q = 0; q < 8; q++)
+                if (k0 + q < C) {
+                    start[k0 + q] = o[q];
+                    count[k0 + q] = 0;
+                }
+        }
+        carry += total;
+        __syncthreads();
     }
     for (int o = 32; o > 0; o >>= 1) {
-        int32_t y = __shfl_xor(mx, o, 64);
+        const int32_t y = __shfl_xor(mx, o, 64);
         mx = y > mx ? y : mx;
     }
-    if (lane == 63) wsum[wv] = inc;
     if (lane == 0) wmax[wv] = mx;
     __syncthreads();
     if (t == 0) {
-        int32_t run = 0, m = 0;
-        for (int w = 0; w < 16; w++) {
-            int32_t v = wsum[w];
-            wsum[w] = run;
-            run += v;
-            m = wmax[w] > m ? wmax[w] : m;
-        }
-        start[C] = run;
+        int32_t m = 0;
+        for (int w = 0; w < 16; w++) m = wmax[w] > m ? wmax[w] : m;
+        start[C] = carry;
         ctl->max_cell = m;
         ctl->nrebuild += 1;
-    }
-    __syncthreads();
-    int32_t run = wsum[wv] + inc - s;
-    for (int64_t k = lo; k < hi; k++) {
-        int32_t v = count[k];
-        start[k] = run;
-        run += v;
-        count[k] = 0;
     }
 }
 

@@ -2,19 +2,22 @@
 //
 // One workgroup per brick of cells (md_brick.h).  It builds the brick's record
 // (halo and own-cell offsets), writes it out for the force and adjoint tasks,
-// and stages the halo's positions in LDS.  Each lane then owns one atom of the
-// brick and scans the atoms of the distinct cells of the 3x3x3 block around the
-// atom's cell (along an axis of 2 cells the block has 2 distinct layers):
+// and stages the halo's positions in LDS.  Each wavefront then takes one of the
+// brick's cells and tests every atom of it against the atoms of the distinct
+// cells of the 3x3x3 block around the cell (along an axis of 2 cells the block
+// has 2 distinct layers):
 //   d = x_i - x_j;  d > L/2 -> d - L,  d < -L/2 -> d + L;  r2 = (dx*dx + dy*dy) + dz*dz
 // in binary64 with contraction off, keeping j iff r2 < (rc + skin)^2 and j != i
-// (and, for the half list, j after i in the sorted order).  The lane appends
-// to its own atom's list only, so every list has exactly one writer and no
-// atomics are needed (each task owns its lists, Sec. II.C).
+// (and, for the half list, j after i in the sorted order).  Only the wavefront
+// of atom i's cell appends to i's list, so every list has exactly one writer
+// and no atomics are needed (each task owns its lists, Sec. II.C).
 //
 // The three cells of a stencil row along x are consecutive in the halo order
 // (or, on a grid of at most bx + 1 cells, wrap around it), so each of the 9
-// rows is one or two contiguous candidate ranges, scanned four candidates at a
-// time: their positions are read first, then tested, then the hits appended.
+// rows is one or two contiguous candidate ranges.  The cell's candidates are
+// held in registers, 9 x 64 at a time, and reused by all atoms of the cell.
+// Cells of more than 128 atoms fall back to one lane per atom, scanning the
+// candidates four at a time.
 //
 // Interior cells: along an axis with at least 5 cells, a neighbour of a cell
 // that is not on the box face is at most 2 cell widths (< L/2) away, so the
@@ -118,11 +121,197 @@ __device__ __forceinline__ void scan_atom(const ListArgs &a, const Stage &st, co
     ni_out = ni;
 }
 
-__global__ __launch_bounds__(TASK_MAX_THREADS) void k_build_list(ListArgs a)
+// One wavefront, one own cell e of the brick: the cell's stencil rows are
+// concatenated into one candidate sequence, loaded into registers in tiles of
+// TILE x 64 (one candidate per lane and chunk), and every atom of the cell (a
+// uniform value per iteration) is tested against the tile.  The cell's atoms
+// (up to 128) are held one per lane and broadcast with readlane.  Hits are
+// compacted with a ballot, so atom a's entries keep the candidate order; the
+// running list length is a scalar while the atom is tested and is kept in lane
+// a between tiles.
+constexpr int TILE = 4;
+
+__device__ __forceinline__ double readlane_f64(double v, int l)
+{
+    const uint64_t u = __double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), l);
+    return __longlong_as_double((int64_t)(((uint64_t)hi << 32) | lo));
+}
+
+template <bool HALF>
+__device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, const BrickGeom &g,
+                                          int32_t e, int32_t na, int32_t *runs, int32_t &my_max)
+{
+    const int lane = threadIdx.x & 63;
+    const int32_t *soff = st.rec + br_soff(a.bd);
+    const int32_t *abeg = st.rec + br_abeg(a.bd);
+    const int32_t lc[3] = {e % g.e[0], (e / g.e[0]) % g.e[1], e / (g.e[0] * g.e[1])};
+    int32_t np[3];
+    bool wrap[3];
+    for (int d = 0; d < 3; d++) {
+        const int32_t c = g.o[d] + lc[d];
+        np[d] = g.nc[d] >= 3 ? 3 : 2;
+        wrap[d] = !(g.nc[d] >= 5 && c >= 1 && c <= g.nc[d] - 2);
+    }
+    const int32_t hown = (lc[0] + 1) % g.nc[0] + g.hn[0] * ((lc[1] + 1) % g.nc[1] + g.hn[1] * ((lc[2] + 1) % g.nc[2]));
+    const int32_t k_own = soff[hown];          // candidate index of the cell's first atom
+    const int64_t i0 = abeg[e];                // sorted index of the cell's first atom
+    // runs of the stencil rows in LDS: runs[0..nr) first candidates,
+    // runs[32..32+nr] prefix of their lengths, runs[31] = nr
+    if (lane == 0) {
+        const int32_t xa = lc[0] % g.nc[0];
+        const int32_t x1 = xa + np[0] < g.hn[0] ? xa + np[0] : g.hn[0];
+        const int32_t x2 = xa + np[0] - x1;
+        int32_t nr = 0, tot = 0;
+        for (int sz = 0; sz < np[2]; sz++)
+            for (int sy = 0; sy < np[1]; sy++) {
+                const int32_t rowh = g.hn[0] * ((lc[1] + sy) % g.nc[1] + g.hn[1] * ((lc[2] + sz) % g.nc[2]));
+                for (int part = 0; part < 2; part++) {
+                    const int32_t kb = part == 0 ? soff[rowh + xa] : soff[rowh];
+                    const int32_t ke = part == 0 ? soff[rowh + x1] : soff[rowh + x2];
+                    if (ke > kb) {
+                        runs[nr] = kb;
+                        runs[32 + nr] = tot;
+                        tot += ke - kb;
+                        nr++;
+                    }
+                }
+            }
+        runs[32 + nr] = tot;
+        runs[31] = nr;
+    }
+    wave_sync();
+    const int32_t nr = runs[31];
+    const int32_t ncand = runs[32 + nr];
+    const RepDesc &rep = a.reps[g.r];
+    const double Lx = rep.L[0], Ly = rep.L[1], Lz = rep.L[2];
+    const double hx = rep.hL[0], hy = rep.hL[1], hz = rep.hL[2];
+    const double rl2 = a.rl2;
+    const int32_t M = a.nbr == nullptr ? 0 : a.M;
+    int32_t cnt0 = 0, cnt1 = 0;                // list lengths of atoms lane and 64 + lane
+    double ax0 = 0.0, ay0 = 0.0, az0 = 0.0, ax1 = 0.0, ay1 = 0.0, az1 = 0.0;
+    {
+        const int32_t k0 = k_own + lane, k1 = k_own + 64 + lane;
+        if (lane < na) {
+            if (k0 < st.cap) {
+                ax0 = st.xyz[3 * k0];
+                ay0 = st.xyz[3 * k0 + 1];
+                az0 = st.xyz[3 * k0 + 2];
+            } else {
+                const double4 p = a.src[i0 + lane];
+                ax0 = p.x;
+                ay0 = p.y;
+                az0 = p.z;
+            }
+        }
+        if (lane + 64 < na) {
+            if (k1 < st.cap) {
+                ax1 = st.xyz[3 * k1];
+                ay1 = st.xyz[3 * k1 + 1];
+                az1 = st.xyz[3 * k1 + 2];
+            } else {
+                const double4 p = a.src[i0 + 64 + lane];
+                ax1 = p.x;
+                ay1 = p.y;
+                az1 = p.z;
+            }
+        }
+    }
+    for (int32_t t0 = 0; t0 < ncand; t0 += 64 * TILE) {
+        const int32_t nch = min(TILE, (ncand - t0 + 63) >> 6);
+        double cx[TILE], cy[TILE], cz[TILE];
+        int32_t ck[TILE];
+        int64_t cj[TILE];
+        _Pragma("unroll")
+        for (int c = 0; c < TILE; c++) {
+            const int32_t v = t0 + 64 * c + lane;
+            int32_t k = k_own;
+            if (c < nch && v < ncand) {
+                int32_t lo = 0, hi = nr - 1;
+                while (lo < hi) {
+                    const int32_t mid = (lo + hi + 1) >> 1;
+                    if (runs[32 + mid] <= v) lo = mid; else hi = mid - 1;
+                }
+                k = runs[lo] + (v - runs[32 + lo]);
+            }
+            ck[c] = (c < nch && v < ncand) ? k : -1;
+            cj[c] = 0;
+            if (k < st.cap) {
+                const double *q = st.xyz + 3 * k;
+                cx[c] = q[0];
+                cy[c] = q[1];
+                cz[c] = q[2];
+                if (HALF) cj[c] = st.j[k];
+            } else {
+                const int32_t j = candidate_index(st, a.bd, k);
+                const double4 p = a.src[j];
+                cx[c] = p.x;
+                cy[c] = p.y;
+                cz[c] = p.z;
+                cj[c] = j;
+            }
+        }
+        for (int32_t at = 0; at < na; at++) {
+            const int64_t i = i0 + at;
+            const int32_t kself = k_own + at;
+            const bool lo_half = at < 64;
+            const int l = lo_half ? at : at - 64;
+            const double xi = readlane_f64(lo_half ? ax0 : ax1, l);
+            const double yi = readlane_f64(lo_half ? ay0 : ay1, l);
+            const double zi = readlane_f64(lo_half ? az0 : az1, l);
+            int32_t ni = t0 == 0 ? 0 : __builtin_amdgcn_readlane(lo_half ? cnt0 : cnt1, l);
+            uint32_t *base = a.nbr + (((i >> 6) * (int64_t)(a.M >> 2)) << 8) + ((i & 63) << 2);
+            _Pragma("unroll")
+            for (int c = 0; c < TILE; c++) {
+                if (c < nch) {
+                    double dx = xi - cx[c], dy = yi - cy[c], dz = zi - cz[c];
+                    uint32_t code = 0;
+                    if (wrap[0]) {
+                        const bool gt = dx > hx, lt = dx < -hx;
+                        dx = gt ? dx - Lx : (lt ? dx + Lx : dx);
+                        code |= gt ? 2u : (lt ? 1u : 0u);
+                    }
+                    if (wrap[1]) {
+                        const bool gt = dy > hy, lt = dy < -hy;
+                        dy = gt ? dy - Ly : (lt ? dy + Ly : dy);
+                        code |= gt ? 8u : (lt ? 4u : 0u);
+                    }
+                    if (wrap[2]) {
+                        const bool gt = dz > hz, lt = dz < -hz;
+                        dz = gt ? dz - Lz : (lt ? dz + Lz : dz);
+                        code |= gt ? 32u : (lt ? 16u : 0u);
+                    }
+                    const double r2 = (dx * dx + dy * dy) + dz * dz;
+                    const bool hit = (ck[c] >= 0) & (r2 < rl2) & (ck[c] != kself) & (!HALF | (cj[c] > i));
+                    const uint64_t mask = __ballot(hit);
+                    if (mask != 0) {
+                        const int32_t p = ni + (int32_t)lanes_below(mask);
+                        if (hit && p < M) base[((int64_t)(p >> 2) << 8) + (p & 3)] = (uint32_t)ck[c] | (code << MD_IDX_BITS);
+                        ni += (int32_t)__popcll(mask);
+                    }
+                }
+            }
+            if (lo_half) cnt0 = lane == l ? ni : cnt0;
+            else cnt1 = lane == l ? ni : cnt1;
+        }
+    }
+    if (lane < na) {
+        a.cnt[i0 + lane] = cnt0;
+        my_max = cnt0 > my_max ? cnt0 : my_max;
+    }
+    if (lane + 64 < na) {
+        a.cnt[i0 + 64 + lane] = cnt1;
+        my_max = cnt1 > my_max ? cnt1 : my_max;
+    }
+}
+
+__global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_build_list(ListArgs a)
 {
     if (*a.pred == 0) return;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ int32_t smax[TASK_MAX_THREADS / 64], stot[TASK_MAX_THREADS / 64], sbr[TASK_MAX_THREADS / 64];
+    __shared__ int32_t runs_lds[64 * (TASK_MAX_THREADS / 64)];
     const Stage st = stage_slice(lds_raw, a.cap, 0, a.half != 0);
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
@@ -152,29 +341,41 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_build_list(ListArgs a)
         __syncthreads();
         const bool all_staged = total <= st.cap;
         const bool has_img = st.rec[BR_IMG] != 0;
-        for (int32_t a0 = 0; a0 < natoms; a0 += (int32_t)blockDim.x) {
-            const int32_t la = a0 + (int32_t)threadIdx.x;
-            if (la >= natoms) continue;
-            int32_t e;
-            const int64_t i = brick_atom(st, a.bd, la, &e);
-            int32_t ni = 0;
-            if (a.half) {
-                STAGE_IMG_SPLIT(all_staged, has_img, scan_atom<STAGED, IMG, true>(a, st, g, i, e, ni);)
+        const int32_t E = st.rec[BR_E];
+        const int32_t *aoff = st.rec + br_aoff(a.bd);
+        // own cells: one wavefront per cell (cells of more than 128 atoms: one lane per atom)
+        for (int32_t e = w; e < E; e += (int32_t)(blockDim.x >> 6)) {
+            const int32_t na = aoff[e + 1] - aoff[e];
+            if (na == 0) continue;
+            if (na <= 128) {
+                if (a.half) scan_cell<true>(a, st, g, e, na, runs_lds + 64 * w, my_max);
+                else scan_cell<false>(a, st, g, e, na, runs_lds + 64 * w, my_max);
             } else {
-                STAGE_IMG_SPLIT(all_staged, has_img, scan_atom<STAGED, IMG, false>(a, st, g, i, e, ni);)
+                for (int32_t at = lane; at < na; at += 64) {
+                    const int64_t i = st.rec[br_abeg(a.bd) + e] + at;
+                    int32_t ni = 0;
+                    if (a.half) {
+                        STAGE_IMG_SPLIT(all_staged, has_img, scan_atom<STAGED, IMG, true>(a, st, g, i, e, ni);)
+                    } else {
+                        STAGE_IMG_SPLIT(all_staged, has_img, scan_atom<STAGED, IMG, false>(a, st, g, i, e, ni);)
+                    }
+                    a.cnt[i] = ni;
+                    my_max = ni > my_max ? ni : my_max;
+                }
             }
-            a.cnt[i] = ni;
-            my_max = ni > my_max ? ni : my_max;
-            // copy the freshly sorted state of this atom into the working buffers
+            // copy the freshly sorted state of the cell's atoms into the working buffers
             if (a.pos_dst != nullptr) {
-                const double4 p = a.src[i];
-                a.pos_dst[i] = p;
-                a.xref[i] = p;
-                a.id_dst[i] = a.id_src[i];
-                if (a.vel_dst != nullptr) {
-                    a.vel_dst[i] = a.vel_src[i];
-                    a.vel_dst[a.n + i] = a.vel_src[a.n + i];
-                    a.vel_dst[2 * a.n + i] = a.vel_src[2 * a.n + i];
+                for (int32_t at = lane; at < na; at += 64) {
+                    const int64_t i = st.rec[br_abeg(a.bd) + e] + at;
+                    const double4 p = a.src[i];
+                    a.pos_dst[i] = p;
+                    a.xref[i] = p;
+                    a.id_dst[i] = a.id_src[i];
+                    if (a.vel_dst != nullptr) {
+                        a.vel_dst[i] = a.vel_src[i];
+                        a.vel_dst[a.n + i] = a.vel_src[a.n + i];
+                        a.vel_dst[2 * a.n + i] = a.vel_src[2 * a.n + i];
+                    }
                 }
             }
         }

@@ -166,6 +166,25 @@ def test_brick_shapes_lists_and_forces(name, shape, cap):
     assert user_pairs(*s.neighbor_list()) == user_pairs(hs, hn)
 
 
+@pytest.mark.parametrize("kind", [B.MD_LIST_FULL, B.MD_LIST_HALF])
+@pytest.mark.parametrize("shape,cap", [((1, 1, 1), 0), ((2, 2, 2), 256)])
+def test_dense_cells_lists(kind, shape, cap):
+    """Cells of about 150 atoms (the one-lane-per-atom fallback of the build)."""
+    w = random_box((6.0, 6.0, 6.0), 1200, 5)
+    L = w.boxes[0]
+    x = oracle.wrap(w.pos, L)
+    s = shaped_system(w, shape, cap)
+    s.build(kind)
+    start, nbr = s.neighbor_list()
+    pi, pj = oracle.pairs_brute(x, L, w.pot.rc + w.skin, full=(kind == B.MD_LIST_FULL))
+    got = user_pairs(start, nbr)
+    if kind == B.MD_LIST_FULL:
+        assert got == set(zip(pi.tolist(), pj.tolist()))
+    else:
+        assert {(min(a, b), max(a, b)) for a, b in got} == {(min(a, b), max(a, b)) for a, b in zip(pi.tolist(), pj.tolist())}
+        assert len(got) == len(pi)
+
+
 @pytest.mark.parametrize("shape,cap", [((2, 2, 2), 0), ((1, 2, 3), 64)])
 def test_brick_shapes_eam_and_vjp(shape, cap):
     w = eam_case(5, 8, sd=0.08)
