@@ -24,10 +24,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, datasheet
-FP64_VECTOR_TFLOPS = 78.6        # MI355X, datasheet
-ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # non-packed vector lane-ops/s (256 CU x 64 lanes x 2.4 GHz)
-FORCE_SOURCES = ["paper_1305_4196_amd/csrc/md_force.hip", "paper_1305_4196_amd/csrc/md_internal.h",
-                 "paper_1305_4196_amd/csrc/md_reduce.h"]
+# vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s (an FMA is one
+# op; = the 78.6 TFLOP/s binary64 vector peak counted in FMAs)
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# algorithmic lane-ops of the LJ pair loop: every listed pair 9 (displacement 3,
+# r^2 5, cutoff test 1); a pair inside rc 17 more (1/r^2 1, q2 1, q6 2, q12 1,
+# 2 q12 - q6 2, f_s 2, V 2, force accumulation 3, energy 1, virial 2)
+OPS_LISTED, OPS_INSIDE = 9, 17
+FORCE_SOURCES = ["paper_1305_4196_amd/csrc/md_force.hip", "paper_1305_4196_amd/csrc/md_brick.h",
+                 "paper_1305_4196_amd/csrc/md_internal.h", "paper_1305_4196_amd/csrc/md_reduce.h"]
 
 
 def log(msg):
@@ -71,7 +76,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--cap", type=int, default=0, help="LDS candidates per cell task")
@@ -148,8 +153,7 @@ def main():
                   "bricks": B.md_query(sysm.ctx, 5), "grid": B.md_query(sysm.ctx, 9),
                   "max_halo": B.md_query(sysm.ctx, 6), "max_brick_atoms": B.md_query(sysm.ctx, 7)}
         tuning["brick"] = "x".join(str((tuning["brick"] >> s) & 255) for s in (0, 8, 16))
-        start, _ = B.md_get_neighbor_list(sysm.ctx)
-        nbar = float(start[-1]) / n
+        nbar = B.md_query(sysm.ctx, 10) / n
         results[name] = dict(
             seconds=t1 - t0, atom_steps=n * args.steps / (t1 - t0), rebuilds=int(nreb.item()),
             force_ms_avg=fms / max(fn, 1), force_launches=fn, list_ms_total=lms, list_launches=ln,
@@ -169,15 +173,33 @@ def main():
     sample = np.random.default_rng(7).choice(n, size=512, replace=False).astype(np.int32)
     Fo, _ = oracle.lj_atoms(snap, w.boxes[0], sample, w.pot.eps, w.pot.sigma, w.pot.rc)
     err_mixed = float(np.linalg.norm(Fm[:, sample] - Fo) / np.linalg.norm(Fo))
+    # listed and interacting pairs of the sampled atoms (minimum image, binary64)
+    st_, nb_ = B.md_get_neighbor_list(s2.ctx)
+    L = w.boxes[0]
+    listed = inside = 0
+    for u in sample:
+        js = nb_[st_[u]:st_[u + 1]]
+        d = snap[:, js] - snap[:, u:u + 1]
+        d -= L[:, None] * np.round(d / L[:, None])
+        r2 = (d * d).sum(axis=0)
+        listed += js.size
+        inside += int((r2 < w.pot.rc ** 2).sum())
+    inside_frac = inside / max(listed, 1)
     err_fp64 = float(np.linalg.norm(Fd[:, sample] - Fo) / np.linalg.norm(Fo))
     log(f"force error vs reference (512 sampled atoms): mixed {err_mixed:.2e}, fp64 {err_fp64:.2e}")
 
     main_name = "mixed" if "mixed" in results else "fp64"
     r = results[main_name]
-    # algorithmic bytes per atom-step of the fused LJ force kernel: list 4 nbar
-    # + x read 24 + v read/write 48 + x' write 24 + x_ref read 24
-    bytes_per_atom = 4.0 * r["nbar"] + 120.0
-    achieved = n * bytes_per_atom / (r["force_ms_avg"] * 1e-3) / 1e9
+    # The fused LJ force kernel is bound by vector ALU issue, not HBM: its
+    # algorithmic lane-ops per atom-step are OPS_LISTED per listed pair plus
+    # OPS_INSIDE per pair inside rc; its algorithmic bytes per atom-step are
+    # list 4 nbar + x read 24 + v read/write 48 + x' write 24 + x_ref read 24.
+    t_s = r["force_ms_avg"] * 1e-3
+    nbar = r["nbar"]
+    ops_per_atom = OPS_LISTED * nbar + OPS_INSIDE * nbar * inside_frac
+    bytes_per_atom = 4.0 * nbar + 120.0
+    achieved_alu = n * ops_per_atom / t_s / 1e12
+    achieved_hbm = n * bytes_per_atom / t_s / 1e9
     traffic = None
     tf = os.path.join(ROOT, "profiles", "traffic_lj_force.json")
     if os.path.exists(tf):
@@ -185,11 +207,14 @@ def main():
             t = json.load(f)
         if t.get("source_hash") == source_hash(FORCE_SOURCES) and t.get("path") == main_name:
             traffic = t.get("hbm_bytes_per_launch")
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_lj_full (cell-task LJ forces + velocity Verlet, fused)",
+    roofline = {"bound": "alu", "achieved": round(achieved_alu, 3), "peak": round(ALU_PEAK_TOPS, 2),
+                "unit": "T lane-ops/s", "frac": round(achieved_alu / ALU_PEAK_TOPS, 4), "traffic": traffic,
+                "kernel": "k_lj_full (brick-task LJ forces + velocity Verlet, fused)",
                 "kernel_avg_us": round(r["force_ms_avg"] * 1e3, 2),
-                "bytes_per_atom_step": round(bytes_per_atom, 1)}
+                "ops_per_atom_step": round(ops_per_atom, 1), "inside_rc_fraction": round(inside_frac, 4),
+                "hbm": {"achieved": round(achieved_hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved_hbm / HBM_PEAK_GBS, 4),
+                        "bytes_per_atom_step": round(bytes_per_atom, 1)}}
 
     line = {
         "metric": "atom-steps/s (forces+neighbor rebuild), FP32-mixed vs FP64 path at stated error",
@@ -206,6 +231,10 @@ def main():
         "fp64_path": ({"value": round(results["fp64"]["atom_steps"], 1),
                        "ms_per_step": round(1e3 * results["fp64"]["seconds"] / args.steps, 4),
                        "force_kernel_us": round(results["fp64"]["force_ms_avg"] * 1e3, 2),
+                       "alu_frac": round(n * ops_per_atom / (results["fp64"]["force_ms_avg"] * 1e-3) / 1e12
+                                         / ALU_PEAK_TOPS, 4),
+                       "hbm_frac": round(n * bytes_per_atom / (results["fp64"]["force_ms_avg"] * 1e-3) / 1e9
+                                         / HBM_PEAK_GBS, 4),
                        "energy_drift": results["fp64"]["drift"], "rebuilds": results["fp64"]["rebuilds"]}
                       if "fp64" in results else None),
         "mixed_force_rel_err": err_mixed,

@@ -201,7 +201,8 @@ int md_set_tuning(md_ctx *ctx, int32_t key, int32_t value);
  * replica 0), 4 threads per brick task, 5 bricks in total, 6 largest brick halo
  * (candidates) and 7 largest brick (atoms) seen by the list builds since the
  * sizing pass (both synchronise), 8 LDS bytes a workgroup may use, 9 workgroups
- * of the LJ force grid.  Returns MD_OK or MD_ERR_ARG. */
+ * of the LJ force grid, 10 entries of the current list (synchronises).
+ * Returns MD_OK, MD_ERR_ARG, MD_ERR_STATE (key 10 without a list) or MD_ERR_HIP. */
 int md_query(md_ctx *ctx, int32_t key, int64_t *value);
 
 /* Kernel timing with HIP events on the stream of the timed calls.

@@ -980,7 +980,18 @@ int md_query(md_ctx *c, int32_t key, int64_t *value)
     }
     case 8: *value = c->lds_max; return MD_OK;
     case 9: *value = c->bricks_valid ? c->grid_tasks(0, false) : 0; return MD_OK;
-    default: return fail(c, MD_ERR_ARG, "query: key 0..9");
+    case 10: {
+        if (!c->have_list) return fail(c, MD_ERR_STATE, "no list");
+        if (c->last != nullptr && hipStreamSynchronize(c->last) != hipSuccess) return fail(c, MD_ERR_HIP, "synchronise");
+        std::vector<int32_t> cnt(c->n);
+        if (hipMemcpy(cnt.data(), c->cnt, sizeof(int32_t) * c->n, hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(c, MD_ERR_HIP, "list length readback");
+        int64_t t = 0;
+        for (int32_t v : cnt) t += std::min(v, c->M);
+        *value = t;
+        return MD_OK;
+    }
+    default: return fail(c, MD_ERR_ARG, "query: key 0..10");
     }
 }
 

@@ -144,30 +144,27 @@ __device__ __forceinline__ void finish_block(const ForceArgs &a, double accE, do
 }
 
 // ---------------------------------------------------------------- LJ pair scalar
-// f_s = 24 eps (2 q12 - q6) / r2 and V = 4 eps (q12 - q6), q6 = (sigma^2/r2)^3,
-// both zero unless `in`
+// f_s = 24 eps (2 q12 - q6) / r2 and V = 4 eps (q12 - q6), q6 = (sigma^2/r2)^3.
+// Outside the cutoff (or for an empty slot) 1/r2 is replaced by 0, which makes
+// both exactly zero without further selects.
 template <bool MIXED>
 __device__ __forceinline__ void lj_pair(bool in, double r2, double s2, double e4, double e24, float s2f,
                                         float e4f, float e24f, double &fs, double &V)
 {
     if (MIXED) {
-        const float ir2 = __builtin_amdgcn_rcpf((float)r2);
+        const float ir2 = in ? __builtin_amdgcn_rcpf((float)r2) : 0.0f;
         const float q2 = s2f * ir2;
         const float q6 = q2 * q2 * q2;
         const float q12 = q6 * q6;
-        const float f = e24f * (2.0f * q12 - q6) * ir2;
-        const float v = e4f * (q12 - q6);
-        fs = in ? (double)f : 0.0;
-        V = in ? (double)v : 0.0;
+        fs = (double)(e24f * (2.0f * q12 - q6) * ir2);
+        V = (double)(e4f * (q12 - q6));
     } else {
-        const double ir2 = rcp64(r2);
+        const double ir2 = in ? rcp64(r2) : 0.0;
         const double q2 = s2 * ir2;
         const double q6 = q2 * q2 * q2;
         const double q12 = q6 * q6;
-        const double f = e24 * (2.0 * q12 - q6) * ir2;
-        const double v = e4 * (q12 - q6);
-        fs = in ? f : 0.0;
-        V = in ? v : 0.0;
+        fs = e24 * (2.0 * q12 - q6) * ir2;
+        V = e4 * (q12 - q6);
     }
 }
 
