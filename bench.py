@@ -83,8 +83,13 @@ def main():
     ap.add_argument("--wgpc", type=int, default=0)
     ap.add_argument("--brick", type=str, default="", help="brick shape bx,by,bz (cells per task)")
     ap.add_argument("--threads", type=int, default=0, help="threads per brick task")
+    ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None,
                     help="time one path only (for profiler runs)")
+    ap.add_argument("--workload", default="lj_fcc_1048576",
+                    choices=["lj_fcc_1048576", "lj_cluster_slab", "fs_eam_1418342", "replicas_lj_512",
+                             "replicas_eam_512"],
+                    help="the default is the headline workload; the others print their own line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -101,6 +106,12 @@ def main():
     from paper_1305_4196_amd.system import MDSystem
 
     torch.cuda.set_device(0)
+    if args.workload.startswith("replicas_"):
+        bench_batch(args, args.workload.split("_")[1])
+        return
+    if args.workload != "lj_fcc_1048576":
+        bench_other(args, args.workload)
+        return
     w = W.lj_bulk()
     n = w.n
     log(f"workload {w.name}: N={n}, L={w.boxes[0, 0]:.4f}, steps={args.steps}, warmup={args.warmup}")
@@ -251,6 +262,164 @@ def main():
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     else:
         line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+def _tune(B, sysm, args):
+    if args.cap:
+        B.md_set_tuning(sysm.ctx, 0, args.cap)
+    if args.wgpc:
+        B.md_set_tuning(sysm.ctx, 1, args.wgpc)
+    if args.brick:
+        bx, by, bz = (int(v) for v in args.brick.split(","))
+        B.md_set_tuning(sysm.ctx, 3, bx | by << 8 | bz << 16)
+    if args.threads:
+        B.md_set_tuning(sysm.ctx, 4, args.threads)
+    if args.tune:
+        from paper_1305_4196_amd import tune
+        best = tune.tune(sysm, precision=B.MD_MIXED)
+        log(f"tuned: brick {best['shape']} on {best['threads']} threads ({best['ms']:.3f} ms per force + "
+            f"amortised build)")
+
+
+def bench_other(args, name):
+    """atom-steps/s of md_verlet_step on the inhomogeneous LJ system or the EAM
+    crystal, both paths, with the force error of the mixed path."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_1305_4196_amd import binding as B
+    from paper_1305_4196_amd import workloads as W
+    from paper_1305_4196_amd.system import MDSystem
+
+    w = W.WORKLOADS[name]()
+    n = w.n
+    steps = args.steps if args.steps != 1000 or name != "fs_eam_1418342" else w.steps
+    log(f"workload {w.name}: N={n}, steps={steps}, warmup={args.warmup}")
+    sysm = MDSystem.from_workload(w)
+    _tune(B, sysm, args)
+    pos0 = torch.tensor(w.pos, dtype=torch.float64, device="cuda")
+    vel0 = torch.tensor(w.vel, dtype=torch.float64, device="cuda")
+    F = torch.empty_like(pos0)
+    hist = torch.zeros((steps, 3), dtype=torch.float64, device="cuda")
+    nreb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    res = {}
+    for pname, prec in (("mixed", B.MD_MIXED), ("fp64", B.MD_FP64)):
+        if args.only and args.only != pname:
+            continue
+        # a run whose lists overflow is repeated from the same state once the
+        # context has grown the rows (the documented capacity protocol)
+        for attempt in range(4):
+            sysm.pos.copy_(pos0)
+            sysm.vel.copy_(vel0)
+            B.md_build_cells(sysm.ctx, sysm.pos, sysm.boxes, w.pot.rc, w.skin)
+            if args.warmup:
+                B.md_verlet_step(sysm.ctx, sysm.dpot, prec, B.MD_LIST_FULL, sysm.pos, sysm.vel, F, w.dt,
+                                 w.mass, args.warmup, None, None)
+            torch.cuda.synchronize()
+            B.md_profile(sysm.ctx, True)
+            t0 = time.perf_counter()
+            B.md_verlet_step(sysm.ctx, sysm.dpot, prec, B.MD_LIST_FULL, sysm.pos, sysm.vel, F, w.dt, w.mass,
+                             steps, hist, nreb)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            fms, fn, lms, ln = B.md_profile(sysm.ctx, False)
+            code = B.md_get_status(sysm.ctx)[0]
+            if code != B.MD_ERR_CAPACITY:
+                break
+            log(f"{pname}: list rows overflowed, repeating with capacity {B.md_query(sysm.ctx, 2)}")
+        if code != B.MD_OK:
+            raise RuntimeError(f"{pname} run ended with status {code}")
+        h = hist.cpu().numpy()
+        et = h[:, 0] + h[:, 1]
+        res[pname] = {"atom_steps_per_s": round(n * steps / (t1 - t0), 1),
+                      "ms_per_step": round(1e3 * (t1 - t0) / steps, 4),
+                      "force_us": round(1e3 * fms / max(fn, 1), 2), "rebuilds": int(nreb.item()),
+                      "list_ms_total": round(lms, 3),
+                      "energy_drift": float(np.max(np.abs(et - et[0])) / max(abs(et[0]), 1e-300)),
+                      "mean_neighbors": round(B.md_query(sysm.ctx, 10) / n, 3),
+                      "brick": B.md_query(sysm.ctx, 3), "threads": B.md_query(sysm.ctx, 4)}
+        log(f"{pname}: {res[pname]}")
+    # force error of the mixed path on a thermal snapshot
+    snap = W.thermal_snapshot(w, 0.05)
+    s2 = MDSystem(snap, w.boxes, w.offsets, w.pot, w.skin)
+    Fm = s2.forces(B.MD_MIXED)[0].cpu().numpy()
+    L = w.boxes[0]
+    if w.pot.kind == "lj":
+        sample = np.random.default_rng(7).choice(n, size=512, replace=False).astype(np.int32)
+        Fo, _ = oracle.lj_atoms(snap, L, sample, w.pot.eps, w.pot.sigma, w.pot.rc)
+        err = float(np.linalg.norm(Fm[:, sample] - Fo) / np.linalg.norm(Fo))
+    else:
+        Fo, _, _ = oracle.forces(oracle.wrap(snap, L), L, w.pot, skin=w.skin)
+        err = float(np.linalg.norm(Fm - Fo) / np.linalg.norm(Fo))
+    main = res.get("mixed") or res.get("fp64")
+    print(json.dumps({"metric": "atom-steps/s (forces+neighbor rebuild), FP32-mixed vs FP64 path at stated error",
+                      "value": main["atom_steps_per_s"], "unit": "atom-steps/s", "n_gpus": 1, "steps": steps,
+                      "warmup": args.warmup, "ms_per_step": main["ms_per_step"], "higher_is_better": True,
+                      "data": "synthetic", "config": {"workload": w.name, "atoms": n}, "paths": res,
+                      "mixed_force_rel_err": err}), flush=True)
+
+
+def bench_batch(args, kind):
+    """Gradient evaluations per second of the 512-replica fitting batch (forces,
+    loss cotangent and adjoint replayed as one graph), with the oracle's
+    forward + adjoint timed on a sample of the replicas."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_1305_4196_amd import binding as B
+    from paper_1305_4196_amd import workloads as W
+    from paper_1305_4196_amd.fit import BatchedFit
+    from paper_1305_4196_amd.system import MDSystem
+
+    w = W.replica_batch(kind, 512)
+    n = w.n
+    log(f"workload {w.name}: {w.n_replicas} replicas, N={n}")
+    sysm = MDSystem.from_workload(w)
+    _tune(B, sysm, args)
+    F_star = sysm.forces(B.MD_FP64)[0]
+    start = W.perturb_params(w.pot)
+    if kind == "lj":
+        theta = torch.tensor([start.eps, start.sigma], dtype=torch.float64, device="cuda")
+    else:
+        theta = torch.tensor(np.concatenate([start.phi.coef.ravel(), start.rho.coef.ravel(),
+                                             start.embed.coef.ravel()]), dtype=torch.float64, device="cuda")
+    fit = BatchedFit(sysm, F_star, theta)
+    fit.capture()
+    for _ in range(max(args.warmup, 3)):
+        fit.gradient()
+    torch.cuda.synchronize()
+    reps = max(args.steps // 10, 20)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fit.gradient()
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / reps
+    if B.md_get_status(sysm.ctx)[0] != B.MD_OK:
+        raise RuntimeError("batch run ended with a device error")
+    log(f"graph replay {t * 1e3:.3f} ms per batch gradient, loss {fit.loss():.4e}")
+    line = {"metric": "batch gradients/s (forces + adjoint over the replica batch, one graph replay)",
+            "value": round(1.0 / t, 2), "unit": "batch-gradients/s", "n_gpus": 1,
+            "replica_gradients_per_s": round(w.n_replicas / t, 1), "atom_gradients_per_s": round(n / t, 1),
+            "ms_per_batch_gradient": round(t * 1e3, 4), "higher_is_better": True, "dtype": "f64",
+            "data": "synthetic", "config": {"workload": w.name, "replicas": w.n_replicas, "atoms": n,
+                                            "params": int(theta.numel())}}
+    if not args.no_cpu_baseline:
+        log("timing the CPU reference on 32 replicas ...")
+        F_np = F_star.cpu().numpy()
+        t0 = time.perf_counter()
+        for r in range(32):
+            lo, hi = int(w.offsets[r]), int(w.offsets[r + 1])
+            L = w.boxes[r]
+            x = oracle.wrap(w.pos[:, lo:hi], L)
+            Fr, _, _ = oracle.forces(x, L, start, skin=w.skin)
+            u = 2.0 * (Fr - F_np[:, lo:hi]) / (3.0 * n)
+            oracle.vjp(x, L, start, u, 0.0, skin=w.skin)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": round(32 / dt, 3), "unit": "replica-gradients/s", "cores": 1,
+                                "kind": "oracle", "sample": f"forward + adjoint of replicas 0..31 ({dt:.1f} s)"}
     print(json.dumps(line), flush=True)
 
 

@@ -101,6 +101,10 @@ struct md_ctx {
     int64_t B = 0, brec_alloc = 0;
     BrickDims bd{0, 0, 0};
     int32_t *brec = nullptr;
+    int32_t *bcost = nullptr;         // [B] brick costs of the last list build
+    int64_t *bwork = nullptr;         // [B+1] their prefix
+    int64_t bcost_alloc = 0;
+    TaskQueue *tq = nullptr;
 
     // atoms (cell-sorted)
     double4 *pos[2] = {nullptr, nullptr};
@@ -266,6 +270,9 @@ ListArgs list_args(md_ctx *c, const int32_t *pred, const double4 *src, int half)
     a.start = c->start;
     a.brec = c->brec;
     a.bd = c->bd;
+    a.tq = c->tq;
+    a.bcost = c->bcost;
+    a.bwork = c->bwork;
     a.src = src;
     a.n = c->n;
     a.nbr = c->nbr;
@@ -360,6 +367,11 @@ int plan_bricks(md_ctx *c, hipStream_t s)
         if (!dalloc(&c->brec, words)) return fail(c, MD_ERR_HIP, "brick records: out of device memory");
         c->brec_alloc = words;
     }
+    if (bricks > c->bcost_alloc) {
+        if (!dalloc(&c->bcost, bricks) || !dalloc(&c->bwork, bricks + 1))
+            return fail(c, MD_ERR_HIP, "brick costs: out of device memory");
+        c->bcost_alloc = bricks;
+    }
     c->B = bricks;
     if (hipMemcpyAsync(c->reps, c->reps_h.data(), sizeof(RepDesc) * c->R, hipMemcpyHostToDevice, s) !=
             hipSuccess ||
@@ -435,6 +447,7 @@ ForceArgs force_args(md_ctx *c, const md_potential *p)
     a.B = c->B;
     a.brec = c->brec;
     a.bd = c->bd;
+    a.bwork = c->bwork;
     a.cap = c->cap;
     a.rc2 = p->rc * p->rc;
     a.lj = p->lj_params;
@@ -559,7 +572,7 @@ int md_create(md_ctx **out, int64_t n, int32_t R, const int64_t *off)
           dalloc(&c->fpp, n) && dalloc(&c->rdot, n);
     ok &= dalloc(&c->u_s, 3 * n) && dalloc(&c->gx_s, 3 * n);
     ok &= dalloc(&c->partial, (size_t)c->max_grid() * 4 * 4) && dalloc(&c->zeros_R, R);
-    ok &= dalloc(&c->reps, R) && dalloc(&c->ctl, 1) && dalloc(&c->one, 1);
+    ok &= dalloc(&c->reps, R) && dalloc(&c->ctl, 1) && dalloc(&c->one, 1) && dalloc(&c->tq, 1);
     if (!ok) {
         md_destroy(c);
         return MD_ERR_HIP;
@@ -569,10 +582,12 @@ int md_create(md_ctx **out, int64_t n, int32_t R, const int64_t *off)
         for (int64_t i = off[r]; i < off[r + 1]; i++) rep[i] = r;
     const int32_t one = 1;
     DevCtl z{};
+    TaskQueue zq{};
     std::vector<double> zr(R, 0.0);
     ok = hipMemcpy(c->rep_of, rep.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(c->one, &one, sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(c->ctl, &z, sizeof(DevCtl), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(c->tq, &zq, sizeof(TaskQueue), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(c->zeros_R, zr.data(), sizeof(double) * R, hipMemcpyHostToDevice) == hipSuccess;
     if (!ok) {
         md_destroy(c);
@@ -589,7 +604,7 @@ void md_destroy(md_ctx *c)
     dfree(c->pos[0]); dfree(c->pos[1]); dfree(c->pos_t); dfree(c->xref);
     dfree(c->vel); dfree(c->vel_t); dfree(c->force);
     dfree(c->id); dfree(c->id_t); dfree(c->cell_of); dfree(c->slot); dfree(c->perm);
-    dfree(c->count); dfree(c->start); dfree(c->nbr); dfree(c->cnt); dfree(c->rep_of); dfree(c->brec);
+    dfree(c->count); dfree(c->start); dfree(c->nbr); dfree(c->cnt); dfree(c->rep_of); dfree(c->brec); dfree(c->bcost); dfree(c->bwork); dfree(c->tq);
     dfree(c->eatom); dfree(c->watom); dfree(c->rho); dfree(c->fp); dfree(c->fpp); dfree(c->rdot);
     dfree(c->u_s); dfree(c->gx_s); dfree(c->partial); dfree(c->zeros_R);
     dfree(c->tab64); dfree(c->tab32); dfree(c->reps); dfree(c->ctl); dfree(c->one);

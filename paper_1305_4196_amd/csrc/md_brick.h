@@ -31,7 +31,11 @@
 // atoms of a row group read 1 KiB contiguously.  M is a multiple of 8.
 #pragma once
 
+#include <mutex>
+#include <unordered_map>
+
 #include "md_internal.h"
+#include "md_reduce.h"
 
 constexpr int TASK_MAX_THREADS = 512;
 
@@ -52,12 +56,24 @@ __host__ __device__ inline int64_t ell_word(int64_t i, int64_t p, int32_t M)
     return (((i >> 6) * (M >> 2) + (p >> 2)) << 8) + ((i & 63) << 2) + (p & 3);
 }
 
-// allow a kernel to take `bytes` of dynamic LDS
+// allow a kernel to take `bytes` of dynamic LDS (the attribute is set only when a
+// kernel needs more than before, so launches recorded into a graph after a
+// first eager call make no attribute calls)
+inline void allow_lds_ptr(const void *kernel, size_t bytes)
+{
+    static std::mutex mu;
+    static std::unordered_map<const void *, size_t> done;
+    std::lock_guard<std::mutex> lock(mu);
+    size_t &have = done[kernel];
+    if (bytes <= have) return;
+    if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess)
+        have = bytes;
+}
+
 template <typename K>
 inline void allow_lds(K kernel, size_t bytes)
 {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    allow_lds_ptr(reinterpret_cast<const void *>(kernel), bytes);
 }
 
 // dynamic LDS of a task: staged (x, y, z) (binary64, interleaved) of `cap`
@@ -376,14 +392,111 @@ __device__ __forceinline__ void walk_list(const Stage &s, const BrickDims &d, co
     }
 
 // ---------------------------------------------------------------- brick-task loop
-// Persistent grid: each workgroup takes bricks from its XCD's range, loads the
-// record and stages the halo, then its lanes take the brick's atoms (la =
-// a0 + thread) in rounds of blockDim.x.  Defines for the body: st_rec-derived natoms,
-// rep_r, Lx/Ly/Lz, all_staged, has_img, valid, la, i (sorted index), mm (list
-// length, capped at M).
+// Next brick for this workgroup (-1 when none is left): the range of its XCD
+// (workgroups are dispatched round-robin over the eight XCDs, so block b runs
+// on XCD b % 8) first, so that an XCD's L2 works on one compact region, then
+// the other ranges, so that dense regions of an inhomogeneous system are
+// shared out.  Block-wide; starts and ends with a barrier.
+__device__ __forceinline__ int64_t next_brick(TaskQueue *q, int64_t nb, int32_t *slot)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int x = blockIdx.x & 7;
+        const int64_t per = (nb + 7) >> 3;
+        int64_t b = -1;
+        for (int d = 0; d < 8 && b < 0; d++) {
+            const int y = (x + d) & 7;
+            const int64_t lo = y * per, hi = lo + per < nb ? lo + per : nb;
+            if (lo >= hi) continue;
+            const uint32_t seen = __hip_atomic_load(&q->next[y], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((int64_t)seen >= hi - lo) continue;
+            const uint32_t t = atomicAdd(&q->next[y], 1u);
+            if (lo + (int64_t)t < hi) b = lo + t;
+        }
+        *slot = (int32_t)b;
+    }
+    __syncthreads();
+    return *slot;
+}
+
+// End of a queue-driven launch: returns true (in every thread) in the last
+// workgroup to finish, which has reset the queue for the next launch.
+__device__ __forceinline__ bool tasks_done(TaskQueue *q)
+{
+    __shared__ int last_;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t prev = atomicAdd(&q->done, 1u);
+        last_ = prev == gridDim.x - 1 ? 1 : 0;
+        if (last_) {
+            for (int k = 0; k < 8; k++) __hip_atomic_store(&q->next[k], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&q->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    __syncthreads();
+    if (last_) __threadfence();
+    return last_ != 0;
+}
+
+// first index b in [0, n] with w[b] >= t (w non-decreasing over [0, n], and
+// w[n] >= t); called by all 64 lanes of a wavefront, which probe 64 points per
+// round, so a prefix of up to 64^3 entries takes at most four dependent loads
+__device__ __forceinline__ int64_t lower_bound_wave(const int64_t *w, int64_t n, int64_t t)
+{
+    const int lane = threadIdx.x & 63;
+    int64_t lo = 0, hi = n;        // the answer lies in [lo, hi]
+    while (hi - lo > 63) {
+        const int64_t step = (hi - lo + 63) >> 6;
+        const int64_t p = lo + (int64_t)(lane + 1) * step;      // lane 63 probes >= hi
+        const bool ge = p >= hi || w[p] >= t;
+        const int first = __ffsll((long long)__ballot(ge)) - 1;
+        const int64_t nlo = first > 0 ? lo + (int64_t)first * step + 1 : lo;
+        const int64_t nhi = lo + (int64_t)(first + 1) * step < hi ? lo + (int64_t)(first + 1) * step : hi;
+        lo = nlo;
+        hi = nhi;
+    }
+    const int64_t p = lo + lane;
+    const bool ge = p >= hi || w[p] >= t;
+    return lo + (__ffsll((long long)__ballot(ge)) - 1);
+}
+
+// This workgroup's bricks: the cost prefix (from the list build) is cut into
+// eight parts of equal cost, one per XCD (block g runs on XCD g % 8), and the
+// workgroups of an XCD take the bricks of its part in turn (slot s takes
+// bricks first + s, first + s + G/8, ...), so the bricks in flight on an XCD
+// at any time are neighbours that share their halos in its L2, and every XCD
+// carries the same load even where the system is inhomogeneous.
+struct BrickRange {
+    int64_t first, end, stride;
+};
+
+__device__ __forceinline__ BrickRange balanced_bricks(const int64_t *w, int64_t nb)
+{
+    const int64_t G = gridDim.x;
+    BrickRange r;
+    if (G % 8 != 0) {
+        r.first = blockIdx.x;
+        r.end = nb;
+        r.stride = G;
+        return r;
+    }
+    const int64_t x = blockIdx.x & 7, W = w[nb];
+    const int64_t lo = lower_bound_wave(w, nb, W * x / 8);
+    r.end = x == 7 ? nb : lower_bound_wave(w, nb, W * (x + 1) / 8);
+    r.first = lo + (blockIdx.x >> 3);
+    r.stride = G >> 3;
+    return r;
+}
+
+// Brick-task loop of the force and adjoint kernels: the workgroup walks its
+// bricks (balanced_bricks), loads each record and stages the halo, then its
+// lanes take the brick's atoms (la = a0 + thread) in rounds of blockDim.x.
+// Defines for the body: natoms, rep_r, Lx/Ly/Lz, all_staged, has_img, valid,
+// la, i (sorted index), mm (list length, capped at M).
 #define BRICK_TASK_BEGIN(ST, POS, EXTRA0, EXTRA1)                                          \
-    const ItemRange it_ = xcd_items(a.B, 1, 0);                                           \
-    for (int64_t b_ = it_.first; b_ < it_.end; b_ += it_.stride) {                        \
+    const BrickRange br_ = balanced_bricks(a.bwork, a.B);                                 \
+    for (int64_t b_ = br_.first; b_ < br_.end; b_ += br_.stride) {                        \
         const int32_t *grec_ = a.brec + b_ * (int64_t)a.bd.stride;                        \
         const int32_t natoms = grec_[BR_ATOMS];                                           \
         if (natoms == 0) continue;                                                        \
@@ -394,7 +507,7 @@ __device__ __forceinline__ void walk_list(const Stage &s, const BrickDims &d, co
         const bool all_staged = ST.rec[BR_TOTAL] <= ST.cap;                               \
         const RepDesc &rep_ = a.reps[rep_r];                                              \
         const double Lx = rep_.L[0], Ly = rep_.L[1], Lz = rep_.L[2];                      \
-        for (int32_t a0_ = 0; a0_ < natoms; a0_ += (int32_t)blockDim.x) {                        \
+        for (int32_t a0_ = 0; a0_ < natoms; a0_ += (int32_t)blockDim.x) {                 \
             const int32_t la = a0_ + (int32_t)threadIdx.x;                                \
             const bool valid = la < natoms;                                               \
             const int64_t i = valid ? brick_atom(ST, a.bd, la) : 0;                       \

@@ -131,6 +131,9 @@ __device__ __forceinline__ void finish_atom(const ForceArgs &a, int64_t i, const
     }
 }
 
+// workgroup sums of E, W and 2 KE, then the launch totals in workgroup order
+// (the bricks of a workgroup are fixed by the cost prefix, so the totals are
+// bitwise repeatable for a given list and grid)
 __device__ __forceinline__ void finish_block(const ForceArgs &a, double accE, double accW,
                                              double accK, double *lds)
 {
@@ -243,12 +246,7 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_lj_half(ForceArgs a)
             atomicAdd(&a.force[2 * n + i], fz);
         }
     BRICK_TASK_END
-    double v[4] = {accE, accW, 0.0, 0.0};
-    if (a.outE == nullptr && a.outW == nullptr) return;
-    if (mdred::last_block_sum4(v, a.partial, a.done, lds) && threadIdx.x == 0) {
-        if (a.outE) *a.outE = v[0];
-        if (a.outW) *a.outW = v[1];
-    }
+    finish_block(a, accE, accW, 0.0, lds);
 }
 
 // velocity-Verlet pieces for forces already in a.force (half-list path); the

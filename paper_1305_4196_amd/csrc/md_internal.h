@@ -12,6 +12,8 @@
 //            01 = add L, 10 = subtract L) fixed when the list is built
 //   cnt      int32[N]    list length of each atom
 //   brec     int32[B*stride] one record per brick of cells (md_brick.h)
+//   bcost    int32[B]    cost of each brick in the last list build
+//   bwork    int64[B+1]  prefix of bcost: the force kernels' balanced schedule
 // Positions are wrapped into [0, L) when the cells are built; between builds they
 // move freely and each pair uses the image fixed at build time (exact as long as
 // no atom moves more than skin/2, which the rebuild trigger guarantees).
@@ -76,6 +78,16 @@ void launch_copy_back(hipStream_t s, int grid, const int32_t *pred, int64_t n,
                       const double4 *pos_t, const double *vel_t, const int32_t *id_t,
                       double4 *pos, double *vel, int32_t *id, double4 *xref);
 
+// Work queue of the brick tasks: the bricks are split into eight contiguous
+// ranges, one per XCD; a workgroup takes bricks from its XCD's range first and
+// then from the others' (next[x] counts the bricks handed out of range x).  The
+// last workgroup of a launch resets it.
+struct TaskQueue {
+    uint32_t next[8];
+    uint32_t done;
+    uint32_t pad[7];
+};
+
 // brick record sizes: halo cells and own cells of the largest brick, record stride
 struct BrickDims {
     int32_t Hm, Em, stride;
@@ -90,6 +102,9 @@ struct ListArgs {
     const int32_t *start;     // cell_start[C+1]
     int32_t *brec;            // brick records (written)
     BrickDims bd;
+    TaskQueue *tq;
+    int32_t *bcost;           // [B] cost of each brick (list entries + 8 atoms + 512), written
+    int64_t *bwork;           // [B+1] exclusive prefix of bcost, written by the last workgroup
     const double4 *src;       // sorted positions the list is built from
     int64_t n;
     uint32_t *nbr;
@@ -127,6 +142,7 @@ struct ForceArgs {
     int64_t B;                // bricks
     const int32_t *brec;      // brick records
     BrickDims bd;
+    const int64_t *bwork;     // [B+1] prefix of the bricks' costs (from the list build)
     int32_t cap;              // candidates staged in LDS per brick task
     double rc2;
     const double *lj;         // device {eps, sigma}

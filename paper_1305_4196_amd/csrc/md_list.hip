@@ -141,7 +141,8 @@ __device__ __forceinline__ double readlane_f64(double v, int l)
 
 template <bool HALF>
 __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, const BrickGeom &g,
-                                          int32_t e, int32_t na, int32_t *runs, int32_t &my_max)
+                                          int32_t e, int32_t na, int32_t *runs, int32_t &my_max,
+                                          int32_t *bpairs)
 {
     const int lane = threadIdx.x & 63;
     const int32_t *soff = st.rec + br_soff(a.bd);
@@ -296,14 +297,19 @@ __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, co
             else cnt1 = lane == l ? ni : cnt1;
         }
     }
+    int32_t tot = 0;
     if (lane < na) {
         a.cnt[i0 + lane] = cnt0;
         my_max = cnt0 > my_max ? cnt0 : my_max;
+        tot += cnt0;
     }
     if (lane + 64 < na) {
         a.cnt[i0 + 64 + lane] = cnt1;
         my_max = cnt1 > my_max ? cnt1 : my_max;
+        tot += cnt1;
     }
+    for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o, 64);
+    if (lane == 0) atomicAdd(bpairs, tot);
 }
 
 __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_build_list(ListArgs a)
@@ -315,17 +321,22 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_build_list(ListArgs a)
     const Stage st = stage_slice(lds_raw, a.cap, 0, a.half != 0);
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    const ItemRange it = xcd_items(a.B, 1, 0);
+    __shared__ int32_t slot, bpairs;
     int32_t my_max = 0, my_tot = 0, my_br = 0;
 
-    for (int64_t b = it.first; b < it.end; b += it.stride) {
+    for (;;) {
+        const int64_t b = next_brick(a.tq, a.B, &slot);
+        if (b < 0) break;
+        if (threadIdx.x == 0) bpairs = 0;
         const BrickGeom g = brick_geom(a.reps, a.R, b);
-        __syncthreads();
         brick_setup(st, a.bd, g, a.start);
         int32_t *grec = a.brec + b * (int64_t)a.bd.stride;
         for (int32_t t = threadIdx.x; t < a.bd.stride; t += blockDim.x) grec[t] = st.rec[t];
         const int32_t natoms = st.rec[BR_ATOMS];
-        if (natoms == 0) continue;
+        if (natoms == 0) {
+            if (threadIdx.x == 0) __hip_atomic_store(&a.bcost[b], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            continue;
+        }
         const int32_t total = st.rec[BR_TOTAL];
         my_tot = total > my_tot ? total : my_tot;
         my_br = natoms > my_br ? natoms : my_br;
@@ -348,8 +359,8 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_build_list(ListArgs a)
             const int32_t na = aoff[e + 1] - aoff[e];
             if (na == 0) continue;
             if (na <= 128) {
-                if (a.half) scan_cell<true>(a, st, g, e, na, runs_lds + 64 * w, my_max);
-                else scan_cell<false>(a, st, g, e, na, runs_lds + 64 * w, my_max);
+                if (a.half) scan_cell<true>(a, st, g, e, na, runs_lds + 64 * w, my_max, &bpairs);
+                else scan_cell<false>(a, st, g, e, na, runs_lds + 64 * w, my_max, &bpairs);
             } else {
                 for (int32_t at = lane; at < na; at += 64) {
                     const int64_t i = st.rec[br_abeg(a.bd) + e] + at;
@@ -361,6 +372,7 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_build_list(ListArgs a)
                     }
                     a.cnt[i] = ni;
                     my_max = ni > my_max ? ni : my_max;
+                    atomicAdd(&bpairs, ni);
                 }
             }
             // copy the freshly sorted state of the cell's atoms into the working buffers
@@ -379,6 +391,10 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_build_list(ListArgs a)
                 }
             }
         }
+        // the brick's cost for the balanced schedules of the force kernels
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_store(&a.bcost[b], bpairs + 8 * natoms + 512, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     // one atomic per workgroup (a per-atom atomic on one word would serialise in L2)
     for (int o = 32; o > 0; o >>= 1) {
@@ -404,6 +420,40 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_build_list(ListArgs a)
         atomicMax(&a.ctl->max_brick, q);
         if (m > a.M && a.M > 0) atomicOr(&a.ctl->err, MD_FLAG_OVERFLOW);
     }
+    // the last workgroup turns the bricks' costs into their prefix
+    if (!tasks_done(a.tq)) return;
+    __shared__ int64_t wsum[TASK_MAX_THREADS / 64];
+    const int nw = (int)(blockDim.x >> 6);
+    int64_t carry = 0;
+    for (int64_t c0 = 0; c0 < a.B; c0 += 4 * (int64_t)blockDim.x) {
+        const int64_t k0 = c0 + 4 * (int64_t)threadIdx.x;
+        int64_t v[4], s = 0;
+        for (int q = 0; q < 4; q++) {
+            v[q] = k0 + q < a.B ? (int64_t)__hip_atomic_load(&a.bcost[k0 + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+            s += v[q];
+        }
+        int64_t inc = s;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t y = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += y;
+        }
+        if (lane == 63) wsum[w] = inc;
+        __syncthreads();
+        int64_t before = 0, total = 0;
+        for (int k = 0; k < nw; k++) {
+            before += k < w ? wsum[k] : 0;
+            total += wsum[k];
+        }
+        int64_t run = carry + before + inc - s;
+        for (int q = 0; q < 4; q++)
+            if (k0 + q < a.B) {
+                a.bwork[k0 + q] = run;
+                run += v[q];
+            }
+        carry += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.bwork[a.B] = carry;
 }
 
 } // namespace
