@@ -84,6 +84,8 @@ def main():
     ap.add_argument("--brick", type=str, default="", help="brick shape bx,by,bz (cells per task)")
     ap.add_argument("--threads", type=int, default=0, help="threads per brick task")
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
+    ap.add_argument("--list", choices=["full", "half"], default="full",
+                    help="full list (each atom written by its own lane) or Newton-3 half list with atomics")
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None,
                     help="time one path only (for profiler runs)")
     ap.add_argument("--workload", default="lj_fcc_1048576",
@@ -132,6 +134,7 @@ def main():
     nreb = torch.zeros(1, dtype=torch.int32, device="cuda")
 
     results = {}
+    kind = B.MD_LIST_HALF if args.list == "half" else B.MD_LIST_FULL
     paths = [("mixed", B.MD_MIXED), ("fp64", B.MD_FP64)]
     if args.only:
         paths = [p for p in paths if p[0] == args.only]
@@ -140,7 +143,7 @@ def main():
         sysm.vel.copy_(vel0)
         B.md_build_cells(sysm.ctx, sysm.pos, sysm.boxes, w.pot.rc, w.skin)
         if args.warmup > 0:
-            B.md_verlet_step(sysm.ctx, sysm.dpot, prec, B.MD_LIST_FULL, sysm.pos, sysm.vel, F,
+            B.md_verlet_step(sysm.ctx, sysm.dpot, prec, kind, sysm.pos, sysm.vel, F,
                              w.dt, w.mass, args.warmup, None, None)
         code = B.md_get_status(sysm.ctx)[0]
         if code != B.MD_OK:
@@ -149,7 +152,7 @@ def main():
         B.md_profile(sysm.ctx, True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        B.md_verlet_step(sysm.ctx, sysm.dpot, prec, B.MD_LIST_FULL, sysm.pos, sysm.vel, F,
+        B.md_verlet_step(sysm.ctx, sysm.dpot, prec, kind, sysm.pos, sysm.vel, F,
                          w.dt, w.mass, args.steps, hist, nreb)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -237,7 +240,7 @@ def main():
         "dtype": "f32-pair/f64-accumulate" if main_name == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": "lj_fcc_1048576", "atoms": n, "cells": "64^3 fcc", "density": 0.8442,
-                   "rc": 2.5, "skin": 0.3, "T": 0.72, "dt": 0.005, "list": "full",
+                   "rc": 2.5, "skin": 0.3, "T": 0.72, "dt": 0.005, "list": args.list,
                    "parallelism": "single GPU"},
         "fp64_path": ({"value": round(results["fp64"]["atom_steps"], 1),
                        "ms_per_step": round(1e3 * results["fp64"]["seconds"] / args.steps, 4),

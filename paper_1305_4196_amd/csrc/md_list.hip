@@ -16,8 +16,7 @@
 // (or, on a grid of at most bx + 1 cells, wrap around it), so each of the 9
 // rows is one or two contiguous candidate ranges.  The cell's candidates are
 // held in registers, 9 x 64 at a time, and reused by all atoms of the cell.
-// Cells of more than 128 atoms fall back to one lane per atom, scanning the
-// candidates four at a time.
+// Cells of more than 128 atoms are taken in groups of 128 atoms.
 //
 // Interior cells: along an axis with at least 5 cells, a neighbour of a cell
 // that is not on the box face is at most 2 cell widths (< L/2) away, so the
@@ -27,105 +26,11 @@
 
 namespace {
 
-template <bool STAGED, bool IMG, bool HALF>
-__device__ __forceinline__ void scan_atom(const ListArgs &a, const Stage &st, const BrickGeom &g,
-                                          int64_t i, int32_t e, int32_t &ni_out)
-{
-    const int32_t *soff = st.rec + br_soff(a.bd), *sbeg = st.rec + br_sbeg(a.bd);
-    const int32_t lc[3] = {e % g.e[0], (e / g.e[0]) % g.e[1], e / (g.e[0] * g.e[1])};
-    int32_t np[3];
-    bool wrap[3];
-    for (int d = 0; d < 3; d++) {
-        const int32_t c = g.o[d] + lc[d];
-        np[d] = g.nc[d] >= 3 ? 3 : 2;
-        wrap[d] = IMG && !(g.nc[d] >= 5 && c >= 1 && c <= g.nc[d] - 2);
-    }
-    // halo position of stencil layer s (offset s - 1) along axis d: (lc + s) mod nc
-    const int32_t hown = (lc[0] + 1) % g.nc[0] + g.hn[0] * ((lc[1] + 1) % g.nc[1] + g.hn[1] * ((lc[2] + 1) % g.nc[2]));
-    const int32_t kself = soff[hown] + (int32_t)(i - sbeg[hown]);
-    const RepDesc &rep = a.reps[g.r];
-    const double Lx = rep.L[0], Ly = rep.L[1], Lz = rep.L[2];
-    const double hx = rep.hL[0], hy = rep.hL[1], hz = rep.hL[2];
-    const double rl2 = a.rl2;
-    const double4 xi = a.src[i];
-    // entry p of this atom is word base + (p / 4) * 256 + p % 4
-    uint32_t *base = a.nbr + (((i >> 6) * (int64_t)(a.M >> 2)) << 8) + ((i & 63) << 2);
-    const int32_t M = a.nbr == nullptr ? 0 : a.M;
-    const int32_t xa = lc[0] % g.nc[0];
-    const int32_t x1 = xa + np[0] < g.hn[0] ? xa + np[0] : g.hn[0];
-    const int32_t x2 = xa + np[0] - x1;   // wrapped part of the row: positions [0, x2)
-    int32_t ni = 0;
-    for (int sz = 0; sz < np[2]; sz++)
-        for (int sy = 0; sy < np[1]; sy++) {
-            const int32_t rowh = g.hn[0] * ((lc[1] + sy) % g.nc[1] + g.hn[1] * ((lc[2] + sz) % g.nc[2]));
-            for (int part = 0; part < 2; part++) {
-                const int32_t kb = part == 0 ? soff[rowh + xa] : soff[rowh];
-                const int32_t ke = part == 0 ? soff[rowh + x1] : soff[rowh + x2];
-                for (int32_t k0 = kb; k0 < ke; k0 += 4) {
-                    // phase 1: the four candidates' positions (and sorted indices)
-                    double px[4], py[4], pz[4];
-                    int64_t pj[4];
-                    _Pragma("unroll")
-                    for (int u = 0; u < 4; u++) {
-                        const int32_t kk = k0 + u < ke ? k0 + u : kb;
-                        pj[u] = 0;
-                        if (STAGED || kk < st.cap) {
-                            const double *q = st.xyz + 3 * kk;
-                            px[u] = q[0];
-                            py[u] = q[1];
-                            pz[u] = q[2];
-                            if (HALF) pj[u] = st.j[kk];
-                        } else {
-                            const int32_t j = candidate_index(st, a.bd, kk);
-                            const double4 p = a.src[j];
-                            px[u] = p.x;
-                            py[u] = p.y;
-                            pz[u] = p.z;
-                            pj[u] = j;
-                        }
-                    }
-                    // phase 2: distance test
-                    bool hit[4];
-                    uint32_t code[4];
-                    _Pragma("unroll")
-                    for (int u = 0; u < 4; u++) {
-                        double dx = xi.x - px[u], dy = xi.y - py[u], dz = xi.z - pz[u];
-                        code[u] = 0;
-                        if (IMG) {
-                            const bool gx = wrap[0] && dx > hx, lx = wrap[0] && dx < -hx;
-                            const bool gy = wrap[1] && dy > hy, ly = wrap[1] && dy < -hy;
-                            const bool gz = wrap[2] && dz > hz, lz = wrap[2] && dz < -hz;
-                            dx = gx ? dx - Lx : (lx ? dx + Lx : dx);
-                            dy = gy ? dy - Ly : (ly ? dy + Ly : dy);
-                            dz = gz ? dz - Lz : (lz ? dz + Lz : dz);
-                            code[u] = (gx ? 2u : (lx ? 1u : 0u)) | (gy ? 8u : (ly ? 4u : 0u)) |
-                                      (gz ? 32u : (lz ? 16u : 0u));
-                        }
-                        const double r2 = (dx * dx + dy * dy) + dz * dz;
-                        const int32_t k = k0 + u;
-                        hit[u] = (k < ke) && (r2 < rl2) && (k != kself) && (!HALF || pj[u] > i);
-                    }
-                    // phase 3: append the hits in candidate order
-                    _Pragma("unroll")
-                    for (int u = 0; u < 4; u++) {
-                        if (hit[u]) {
-                            if (ni < M)
-                                base[((int64_t)(ni >> 2) << 8) + (ni & 3)] =
-                                    (uint32_t)(k0 + u) | (code[u] << MD_IDX_BITS);
-                            ni++;
-                        }
-                    }
-                }
-            }
-        }
-    ni_out = ni;
-}
-
 // One wavefront, one own cell e of the brick: the cell's stencil rows are
 // concatenated into one candidate sequence, loaded into registers in tiles of
 // TILE x 64 (one candidate per lane and chunk), and every atom of the cell (a
 // uniform value per iteration) is tested against the tile.  The cell's atoms
-// (up to 128) are held one per lane and broadcast with readlane.  Hits are
+// (in groups of up to 128) are held two per lane and broadcast with readlane.  Hits are
 // compacted with a ballot, so atom a's entries keep the candidate order; the
 // running list length is a scalar while the atom is tested and is kept in lane
 // a between tiles.
@@ -141,7 +46,7 @@ __device__ __forceinline__ double readlane_f64(double v, int l)
 
 template <bool HALF>
 __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, const BrickGeom &g,
-                                          int32_t e, int32_t na, int32_t *runs, int32_t &my_max,
+                                          int32_t e, int32_t na_all, int32_t *runs, int32_t &my_max,
                                           int32_t *bpairs)
 {
     const int lane = threadIdx.x & 63;
@@ -157,7 +62,7 @@ __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, co
     }
     const int32_t hown = (lc[0] + 1) % g.nc[0] + g.hn[0] * ((lc[1] + 1) % g.nc[1] + g.hn[1] * ((lc[2] + 1) % g.nc[2]));
     const int32_t k_own = soff[hown];          // candidate index of the cell's first atom
-    const int64_t i0 = abeg[e];                // sorted index of the cell's first atom
+    const int64_t i0_all = abeg[e];            // sorted index of the cell's first atom
     // runs of the stencil rows in LDS: runs[0..nr) first candidates,
     // runs[32..32+nr] prefix of their lengths, runs[31] = nr
     if (lane == 0) {
@@ -190,10 +95,16 @@ __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, co
     const double hx = rep.hL[0], hy = rep.hL[1], hz = rep.hL[2];
     const double rl2 = a.rl2;
     const int32_t M = a.nbr == nullptr ? 0 : a.M;
+    int32_t tot = 0;
+    // the cell's atoms in groups of up to 128 (two per lane)
+    for (int32_t g0 = 0; g0 < na_all; g0 += 128) {
+    const int32_t na = na_all - g0 < 128 ? na_all - g0 : 128;
+    const int64_t i0 = i0_all + g0;
+    const int32_t k_grp = k_own + g0;
     int32_t cnt0 = 0, cnt1 = 0;                // list lengths of atoms lane and 64 + lane
     double ax0 = 0.0, ay0 = 0.0, az0 = 0.0, ax1 = 0.0, ay1 = 0.0, az1 = 0.0;
     {
-        const int32_t k0 = k_own + lane, k1 = k_own + 64 + lane;
+        const int32_t k0 = k_grp + lane, k1 = k_grp + 64 + lane;
         if (lane < na) {
             if (k0 < st.cap) {
                 ax0 = st.xyz[3 * k0];
@@ -253,51 +164,56 @@ __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, co
                 cj[c] = j;
             }
         }
-        for (int32_t at = 0; at < na; at++) {
-            const int64_t i = i0 + at;
-            const int32_t kself = k_own + at;
-            const bool lo_half = at < 64;
-            const int l = lo_half ? at : at - 64;
-            const double xi = readlane_f64(lo_half ? ax0 : ax1, l);
-            const double yi = readlane_f64(lo_half ? ay0 : ay1, l);
-            const double zi = readlane_f64(lo_half ? az0 : az1, l);
-            int32_t ni = t0 == 0 ? 0 : __builtin_amdgcn_readlane(lo_half ? cnt0 : cnt1, l);
-            uint32_t *base = a.nbr + (((i >> 6) * (int64_t)(a.M >> 2)) << 8) + ((i & 63) << 2);
-            _Pragma("unroll")
-            for (int c = 0; c < TILE; c++) {
-                if (c < nch) {
-                    double dx = xi - cx[c], dy = yi - cy[c], dz = zi - cz[c];
-                    uint32_t code = 0;
-                    if (wrap[0]) {
-                        const bool gt = dx > hx, lt = dx < -hx;
-                        dx = gt ? dx - Lx : (lt ? dx + Lx : dx);
-                        code |= gt ? 2u : (lt ? 1u : 0u);
-                    }
-                    if (wrap[1]) {
-                        const bool gt = dy > hy, lt = dy < -hy;
-                        dy = gt ? dy - Ly : (lt ? dy + Ly : dy);
-                        code |= gt ? 8u : (lt ? 4u : 0u);
-                    }
-                    if (wrap[2]) {
-                        const bool gt = dz > hz, lt = dz < -hz;
-                        dz = gt ? dz - Lz : (lt ? dz + Lz : dz);
-                        code |= gt ? 32u : (lt ? 16u : 0u);
-                    }
-                    const double r2 = (dx * dx + dy * dy) + dz * dz;
-                    const bool hit = (ck[c] >= 0) & (r2 < rl2) & (ck[c] != kself) & (!HALF | (cj[c] > i));
-                    const uint64_t mask = __ballot(hit);
-                    if (mask != 0) {
-                        const int32_t p = ni + (int32_t)lanes_below(mask);
-                        if (hit && p < M) base[((int64_t)(p >> 2) << 8) + (p & 3)] = (uint32_t)ck[c] | (code << MD_IDX_BITS);
-                        ni += (int32_t)__popcll(mask);
+        // atoms 0..63 of the group from the first register set, 64..127 from the second
+        for (int half = 0; half < 2; half++) {
+            const int32_t at_end = half == 0 ? (na < 64 ? na : 64) : na;
+            const double ax = half == 0 ? ax0 : ax1, ay = half == 0 ? ay0 : ay1, az = half == 0 ? az0 : az1;
+            int32_t cnt = half == 0 ? cnt0 : cnt1;
+            for (int32_t at = 64 * half; at < at_end; at++) {
+                const int64_t i = i0 + at;
+                const int32_t kself = k_grp + at;
+                const int l = at - 64 * half;
+                const double xi = readlane_f64(ax, l);
+                const double yi = readlane_f64(ay, l);
+                const double zi = readlane_f64(az, l);
+                int32_t ni = t0 == 0 ? 0 : __builtin_amdgcn_readlane(cnt, l);
+                uint32_t *base = a.nbr + (((i >> 6) * (int64_t)(a.M >> 2)) << 8) + ((i & 63) << 2);
+                _Pragma("unroll")
+                for (int c = 0; c < TILE; c++) {
+                    if (c < nch) {
+                        double dx = xi - cx[c], dy = yi - cy[c], dz = zi - cz[c];
+                        uint32_t code = 0;
+                        if (wrap[0]) {
+                            const bool gt = dx > hx, lt = dx < -hx;
+                            dx = gt ? dx - Lx : (lt ? dx + Lx : dx);
+                            code |= gt ? 2u : (lt ? 1u : 0u);
+                        }
+                        if (wrap[1]) {
+                            const bool gt = dy > hy, lt = dy < -hy;
+                            dy = gt ? dy - Ly : (lt ? dy + Ly : dy);
+                            code |= gt ? 8u : (lt ? 4u : 0u);
+                        }
+                        if (wrap[2]) {
+                            const bool gt = dz > hz, lt = dz < -hz;
+                            dz = gt ? dz - Lz : (lt ? dz + Lz : dz);
+                            code |= gt ? 32u : (lt ? 16u : 0u);
+                        }
+                        const double r2 = (dx * dx + dy * dy) + dz * dz;
+                        const bool hit = (ck[c] >= 0) & (r2 < rl2) & (ck[c] != kself) & (!HALF | (cj[c] > i));
+                        const uint64_t mask = __ballot(hit);
+                        if (mask != 0) {
+                            const int32_t p = ni + (int32_t)lanes_below(mask);
+                            if (hit && p < M) base[((int64_t)(p >> 2) << 8) + (p & 3)] = (uint32_t)ck[c] | (code << MD_IDX_BITS);
+                            ni += (int32_t)__popcll(mask);
+                        }
                     }
                 }
+                cnt = lane == l ? ni : cnt;
             }
-            if (lo_half) cnt0 = lane == l ? ni : cnt0;
-            else cnt1 = lane == l ? ni : cnt1;
+            if (half == 0) cnt0 = cnt;
+            else cnt1 = cnt;
         }
     }
-    int32_t tot = 0;
     if (lane < na) {
         a.cnt[i0 + lane] = cnt0;
         my_max = cnt0 > my_max ? cnt0 : my_max;
@@ -308,19 +224,22 @@ __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, co
         my_max = cnt1 > my_max ? cnt1 : my_max;
         tot += cnt1;
     }
+    }
     for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o, 64);
     if (lane == 0) atomicAdd(bpairs, tot);
 }
 
+template <bool HALF>
 __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_build_list(ListArgs a)
 {
     if (*a.pred == 0) return;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ int32_t smax[TASK_MAX_THREADS / 64], stot[TASK_MAX_THREADS / 64], sbr[TASK_MAX_THREADS / 64];
     __shared__ int32_t runs_lds[64 * (TASK_MAX_THREADS / 64)];
-    const Stage st = stage_slice(lds_raw, a.cap, 0, a.half != 0);
+    const Stage st = stage_slice(lds_raw, a.cap, 0, HALF);
     const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
+    // the wavefront index as a scalar, so that everything derived per cell is uniform
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     __shared__ int32_t slot, bpairs;
     int32_t my_max = 0, my_tot = 0, my_br = 0;
 
@@ -350,31 +269,13 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_build_list(ListArgs a)
             if (st.j != nullptr) st.j[k] = jj;
         }
         __syncthreads();
-        const bool all_staged = total <= st.cap;
-        const bool has_img = st.rec[BR_IMG] != 0;
         const int32_t E = st.rec[BR_E];
         const int32_t *aoff = st.rec + br_aoff(a.bd);
-        // own cells: one wavefront per cell (cells of more than 128 atoms: one lane per atom)
+        // own cells: one wavefront per cell
         for (int32_t e = w; e < E; e += (int32_t)(blockDim.x >> 6)) {
             const int32_t na = aoff[e + 1] - aoff[e];
             if (na == 0) continue;
-            if (na <= 128) {
-                if (a.half) scan_cell<true>(a, st, g, e, na, runs_lds + 64 * w, my_max, &bpairs);
-                else scan_cell<false>(a, st, g, e, na, runs_lds + 64 * w, my_max, &bpairs);
-            } else {
-                for (int32_t at = lane; at < na; at += 64) {
-                    const int64_t i = st.rec[br_abeg(a.bd) + e] + at;
-                    int32_t ni = 0;
-                    if (a.half) {
-                        STAGE_IMG_SPLIT(all_staged, has_img, scan_atom<STAGED, IMG, true>(a, st, g, i, e, ni);)
-                    } else {
-                        STAGE_IMG_SPLIT(all_staged, has_img, scan_atom<STAGED, IMG, false>(a, st, g, i, e, ni);)
-                    }
-                    a.cnt[i] = ni;
-                    my_max = ni > my_max ? ni : my_max;
-                    atomicAdd(&bpairs, ni);
-                }
-            }
+            scan_cell<HALF>(a, st, g, e, na, runs_lds + 64 * w, my_max, &bpairs);
             // copy the freshly sorted state of the cell's atoms into the working buffers
             if (a.pos_dst != nullptr) {
                 for (int32_t at = lane; at < na; at += 64) {
@@ -461,6 +362,11 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_build_list(ListArgs a)
 void launch_build_list(hipStream_t s, int grid, int threads, const ListArgs &a)
 {
     const size_t lds = stage_bytes(a.cap, 0, a.half != 0, a.bd.stride);
-    allow_lds(k_build_list, lds);
-    hipLaunchKernelGGL(k_build_list, dim3(grid), dim3(threads), lds, s, a);
+    if (a.half) {
+        allow_lds(k_build_list<true>, lds);
+        hipLaunchKernelGGL(k_build_list<true>, dim3(grid), dim3(threads), lds, s, a);
+    } else {
+        allow_lds(k_build_list<false>, lds);
+        hipLaunchKernelGGL(k_build_list<false>, dim3(grid), dim3(threads), lds, s, a);
+    }
 }
