@@ -84,6 +84,8 @@ def main():
     ap.add_argument("--brick", type=str, default="", help="brick shape bx,by,bz (cells per task)")
     ap.add_argument("--threads", type=int, default=0, help="threads per brick task")
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
+    ap.add_argument("--thermo", type=int, default=100,
+                    help="record E_pot, KE, W every this many steps (and after the last)")
     ap.add_argument("--list", choices=["full", "half"], default="full",
                     help="full list (each atom written by its own lane) or Newton-3 half list with atomics")
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None,
@@ -130,7 +132,7 @@ def main():
     pos0 = torch.tensor(w.pos, dtype=torch.float64, device="cuda")
     vel0 = torch.tensor(w.vel, dtype=torch.float64, device="cuda")
     F = torch.empty_like(pos0)
-    hist = torch.zeros((args.steps, 3), dtype=torch.float64, device="cuda")
+    hist = torch.zeros(((args.steps + args.thermo - 1) // args.thermo, 3), dtype=torch.float64, device="cuda")
     nreb = torch.zeros(1, dtype=torch.int32, device="cuda")
 
     results = {}
@@ -153,7 +155,7 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         B.md_verlet_step(sysm.ctx, sysm.dpot, prec, kind, sysm.pos, sysm.vel, F,
-                         w.dt, w.mass, args.steps, hist, nreb)
+                         w.dt, w.mass, args.steps, hist, nreb, hist_every=args.thermo)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         fms, fn, lms, ln = B.md_profile(sysm.ctx, False)
@@ -240,7 +242,7 @@ def main():
         "dtype": "f32-pair/f64-accumulate" if main_name == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": "lj_fcc_1048576", "atoms": n, "cells": "64^3 fcc", "density": 0.8442,
-                   "rc": 2.5, "skin": 0.3, "T": 0.72, "dt": 0.005, "list": args.list,
+                   "rc": 2.5, "skin": 0.3, "T": 0.72, "dt": 0.005, "list": args.list, "thermo_every": args.thermo,
                    "parallelism": "single GPU"},
         "fp64_path": ({"value": round(results["fp64"]["atom_steps"], 1),
                        "ms_per_step": round(1e3 * results["fp64"]["seconds"] / args.steps, 4),
@@ -304,7 +306,7 @@ def bench_other(args, name):
     pos0 = torch.tensor(w.pos, dtype=torch.float64, device="cuda")
     vel0 = torch.tensor(w.vel, dtype=torch.float64, device="cuda")
     F = torch.empty_like(pos0)
-    hist = torch.zeros((steps, 3), dtype=torch.float64, device="cuda")
+    hist = torch.zeros(((steps + args.thermo - 1) // args.thermo, 3), dtype=torch.float64, device="cuda")
     nreb = torch.zeros(1, dtype=torch.int32, device="cuda")
     res = {}
     for pname, prec in (("mixed", B.MD_MIXED), ("fp64", B.MD_FP64)):
@@ -323,7 +325,7 @@ def bench_other(args, name):
             B.md_profile(sysm.ctx, True)
             t0 = time.perf_counter()
             B.md_verlet_step(sysm.ctx, sysm.dpot, prec, B.MD_LIST_FULL, sysm.pos, sysm.vel, F, w.dt, w.mass,
-                             steps, hist, nreb)
+                             steps, hist, nreb, hist_every=args.thermo)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             fms, fn, lms, ln = B.md_profile(sysm.ctx, False)
@@ -359,7 +361,8 @@ def bench_other(args, name):
     print(json.dumps({"metric": "atom-steps/s (forces+neighbor rebuild), FP32-mixed vs FP64 path at stated error",
                       "value": main["atom_steps_per_s"], "unit": "atom-steps/s", "n_gpus": 1, "steps": steps,
                       "warmup": args.warmup, "ms_per_step": main["ms_per_step"], "higher_is_better": True,
-                      "data": "synthetic", "config": {"workload": w.name, "atoms": n}, "paths": res,
+                      "data": "synthetic", "config": {"workload": w.name, "atoms": n, "thermo_every": args.thermo},
+                      "paths": res,
                       "mixed_force_rel_err": err}), flush=True)
 
 

@@ -135,17 +135,21 @@ int md_compute_forces(md_ctx *ctx, const md_potential *pot, int32_t precision, d
  * v += dt/(2m) F; x += dt v; wrap; if max_i |minimage(x_i - x_i^ref)|^2 >
  * (skin/2)^2 rebuild cells and list (decided on the device, no host sync);
  * F <- F(x); v += dt/(2m) F.  pos, vel: [3][N] in/out; forces: [3][N] out
- * (forces at the final positions).  energy_hist: n_steps x 3 doubles (E_pot,
- * KE, W) per step, summed over replicas, or NULL.  rebuilds: 1 int32 out
+ * (forces at the final positions).  energy_hist: ceil(n_steps / hist_every)
+ * x 3 doubles (E_pot, KE, W), summed over replicas, after steps hist_every,
+ * 2 hist_every, ... and after the last step (row r: step min((r+1) hist_every,
+ * n_steps)), or NULL; the steps in between skip the energy terms of the pair
+ * loops.  hist_every >= 1 (ignored when energy_hist is NULL).  rebuilds: 1 int32 out
  * (DEVICE, number of rebuilds after the initial one) or NULL.  Uses the rc and
  * skin of the last md_build_cells.  If md_get_status then reports
  * MD_ERR_CAPACITY, the outputs are invalid: the context has grown its
  * capacity and the caller repeats the call from its saved inputs.
- * Errors: MD_ERR_ARG (n_steps < 1, dt or mass not finite/positive),
- * MD_ERR_STATE, MD_ERR_BOX, MD_ERR_HIP. */
+ * Errors: MD_ERR_ARG (n_steps < 1, dt or mass not finite/positive,
+ * hist_every < 1), MD_ERR_STATE, MD_ERR_BOX, MD_ERR_HIP. */
 int md_verlet_step(md_ctx *ctx, const md_potential *pot, int32_t precision, int32_t list_kind,
                    double *pos, double *vel, double *forces, double dt, double mass,
-                   int32_t n_steps, double *energy_hist, int32_t *rebuilds, void *stream);
+                   int32_t n_steps, double *energy_hist, int32_t hist_every,
+                   int32_t *rebuilds, void *stream);
 
 /* Adjoint (vector-Jacobian product) of (F, E) at positions pos with the
  * current cells/list (pos must lie within skin/2 of the positions the list was
@@ -183,7 +187,7 @@ int md_get_cells(md_ctx *ctx, int32_t *cell_start, int32_t *order, int64_t *n_ce
  * key 0 = candidates staged in LDS per brick task (64..4096, a multiple of 64,
  *   within the device's LDS; by default the first list build picks one from
  *   the largest brick halo, and candidates beyond it are read from global
- *   memory);
+ *   memory); drops the current list;
  * key 1 = most workgroups per CU in the brick-task grids (1..8);
  * key 2 = fixed per-atom list capacity (1..4096, rounded up to a multiple of 8;
  *   reallocates, synchronises the device and drops the current list -- a small

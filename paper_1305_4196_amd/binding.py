@@ -64,7 +64,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     L.md_build_cells.argtypes = [vp, vp, P(d), d, d, vp]
     L.md_build_neighbor_list.argtypes = [vp, i32, vp]
     L.md_compute_forces.argtypes = [vp, P(md_potential), i32, vp, vp, vp, vp]
-    L.md_verlet_step.argtypes = [vp, P(md_potential), i32, i32, vp, vp, vp, d, d, i32, vp, vp, vp]
+    L.md_verlet_step.argtypes = [vp, P(md_potential), i32, i32, vp, vp, vp, d, d, i32, vp, i32, vp, vp]
     L.md_force_vjp.argtypes = [vp, P(md_potential), i32, vp, vp, vp, vp, vp, vp]
     L.md_get_status.argtypes = [vp, P(i32), P(i64)]
     L.md_get_neighbor_list.argtypes = [vp, P(i64), P(i32), i64]
@@ -192,10 +192,11 @@ def md_compute_forces(ctx: Context, pot: DevicePotential, precision: int, forces
 
 
 def md_verlet_step(ctx: Context, pot: DevicePotential, precision: int, kind: int, pos, vel, forces,
-                   dt: float, mass: float, n_steps: int, hist=None, rebuilds=None, stream=None):
+                   dt: float, mass: float, n_steps: int, hist=None, rebuilds=None, stream=None,
+                   hist_every: int = 1):
     _check(ctx.h, load().md_verlet_step(ctx.h, C.byref(pot.s), int(precision), int(kind), _ptr(pos),
                                         _ptr(vel), _ptr(forces), float(dt), float(mass), int(n_steps),
-                                        _ptr(hist), _ptr(rebuilds), _stream(stream)))
+                                        _ptr(hist), int(hist_every), _ptr(rebuilds), _stream(stream)))
 
 
 def md_force_vjp(ctx: Context, pot: DevicePotential, precision: int, pos, u, vE, g_pos=None,

@@ -666,7 +666,7 @@ int md_compute_forces(md_ctx *c, const md_potential *p, int32_t precision, doubl
     if (c->R == 1) {
         a.outE = energy;
         a.outW = virial;
-    } else {
+    } else if (energy != nullptr || virial != nullptr) {
         a.eatom = c->eatom;
         a.watom = c->watom;
     }
@@ -688,11 +688,12 @@ int md_compute_forces(md_ctx *c, const md_potential *p, int32_t precision, doubl
 
 int md_verlet_step(md_ctx *c, const md_potential *p, int32_t precision, int32_t kind, double *pos,
                    double *vel, double *forces, double dt, double mass, int32_t n_steps,
-                   double *hist, int32_t *rebuilds, void *stream)
+                   double *hist, int32_t hist_every, int32_t *rebuilds, void *stream)
 {
     if (c == nullptr) return MD_ERR_ARG;
     if (pos == nullptr || vel == nullptr || forces == nullptr) return fail(c, MD_ERR_ARG, "null argument");
     if (n_steps < 1 || !finite_pos(dt) || !finite_pos(mass)) return fail(c, MD_ERR_ARG, "need n_steps >= 1, dt > 0, mass > 0");
+    if (hist != nullptr && hist_every < 1) return fail(c, MD_ERR_ARG, "hist_every must be >= 1");
     if (precision != MD_FP64 && precision != MD_MIXED) return fail(c, MD_ERR_ARG, "unknown precision");
     if (kind != MD_LIST_FULL && kind != MD_LIST_HALF) return fail(c, MD_ERR_ARG, "unknown list kind");
     if (!c->have_cells) return fail(c, MD_ERR_STATE, "md_build_cells first (sets boxes, rc, skin)");
@@ -789,8 +790,10 @@ int md_verlet_step(md_ctx *c, const md_potential *p, int32_t precision, int32_t 
         la.xref = c->xref;
         timed(c, s, c->ev_list, [&] { launch_build_list(s, half ? gh : gf, c->threads, la); });
         const int mode = st < n_steps ? 2 : 3;
+        // energies of every hist_every-th step and of the last one
+        const bool rec = hist != nullptr && (st % hist_every == 0 || st == n_steps);
         forces_and_step(mode, pred, &c->ctl->rebuild[(st + 1) & 1],
-                        hist != nullptr ? hist + 3 * (int64_t)(st - 1) : nullptr);
+                        rec ? hist + 3 * (int64_t)((st + hist_every - 1) / hist_every - 1) : nullptr);
         if (mode == 2) c->cur = 1 - c->cur;
     }
     launch_pos_to_user(s, ga, c->n, c->R, c->reps, c->rep_of, c->id, c->pos[c->cur], pos);
@@ -926,8 +929,10 @@ int md_set_tuning(md_ctx *c, int32_t key, int32_t value)
     // the largest record a brick of at most 64 cells can need
     const int64_t cap_max = (c->lds_max - 4096 - 4 * (int64_t)br_stride(512, 64)) / (int64_t)(4 * sizeof(double));
     if (key == 0 && value >= 64 && value <= 4096 && value % 64 == 0 && value <= cap_max) {
+        // the list's entry format depends on which halos fit the stage
         c->cap = value;
         c->cap_user = true;
+        c->have_list = false;
         return MD_OK;
     }
     if (key == 1 && value >= 1 && value <= 8) {

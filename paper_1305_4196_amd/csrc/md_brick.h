@@ -13,6 +13,21 @@
 // neighbours from there.  A list entry holds the candidate index (low 26 bits)
 // and the image code (high 6 bits) fixed when the list was built.
 //
+// Image of a halo cell: along an axis of n >= 4 cells whose halo does not wrap
+// onto itself (e + 2 <= n), the layer below a brick at the low face is cell n-1
+// seen through -L, the layer above one at the high face cell 0 seen through +L,
+// and every other halo cell is seen directly.  A listed pair is closer than
+// r_c + skin <= one cell width along each axis, while the cell image puts its
+// atoms at most two cell widths (plus rounding) apart; a different image would
+// move them by L >= 4 cell widths, so the list's minimum-image code of every
+// entry equals the image of its candidate's halo cell.  Such bricks, when
+// their whole halo fits the LDS stage (BR_SHIFT = 1), stage their candidates
+// already shifted by the cell image, their list entries carry no code and the
+// pair loops apply none; the others (an axis of fewer than 4 cells, a halo
+// that covers its axis, or one only partly staged) keep the per-entry codes.
+// The stage capacity is fixed when the list is built (changing it drops the
+// list), so the flag the list build records holds for every later task.
+//
 // Each lane owns one atom of its brick (lane t of a workgroup of T threads
 // takes the brick's atoms t, t + T, ...; T is a multiple of 64 up to 512), so
 // the atom's sums stay in registers and no atom is written by two lanes: the
@@ -21,9 +36,11 @@
 // Brick record (int32, one per brick, written by the list build, read by the
 // force and adjoint tasks so that they skip the setup):
 //   [BR_TOTAL] candidates  [BR_ATOMS] atoms  [BR_REP] replica  [BR_H] halo cells
-//   [BR_E] own cells  [BR_IMG] 1 if a pair of the brick may cross the box
-//   soff[Hm+1]  sbeg[Hm]  aoff[Em+1]  abeg[Em]
-// (aoff/abeg: the same for the brick's own cells, in x-fastest order.)
+//   [BR_E] own cells  [BR_IMG] 1 if pairs need the per-entry image codes
+//   [BR_SHIFT] 1 if the halo is staged through the cell images (entries carry no code)
+//   soff[Hm+1]  sbeg[Hm]  aoff[Em+1]  abeg[Em]  himg[Hm]
+// (aoff/abeg: the same for the brick's own cells, in x-fastest order; himg:
+// the image code of each halo cell, in the list-entry encoding.)
 //
 // List layout (interleaved rows): entry p of sorted atom i is word
 //   ((i/64) * M/4 + p/4) * 256 + (i%64) * 4 + p%4
@@ -39,15 +56,16 @@
 
 constexpr int TASK_MAX_THREADS = 512;
 
-enum { BR_TOTAL = 0, BR_ATOMS = 1, BR_REP = 2, BR_H = 3, BR_E = 4, BR_IMG = 5, BR_HDR = 8 };
+enum { BR_TOTAL = 0, BR_ATOMS = 1, BR_REP = 2, BR_H = 3, BR_E = 4, BR_IMG = 5, BR_SHIFT = 6, BR_HDR = 8 };
 
 __host__ __device__ inline int32_t br_soff(const BrickDims &d) { (void)d; return BR_HDR; }
 __host__ __device__ inline int32_t br_sbeg(const BrickDims &d) { return BR_HDR + d.Hm + 1; }
 __host__ __device__ inline int32_t br_aoff(const BrickDims &d) { return BR_HDR + 2 * d.Hm + 1; }
 __host__ __device__ inline int32_t br_abeg(const BrickDims &d) { return BR_HDR + 2 * d.Hm + d.Em + 2; }
+__host__ __device__ inline int32_t br_himg(const BrickDims &d) { return BR_HDR + 2 * d.Hm + 2 * d.Em + 2; }
 __host__ __device__ inline int32_t br_stride(int32_t Hm, int32_t Em)
 {
-    return (BR_HDR + 2 * Hm + 2 * Em + 2 + 3) / 4 * 4;
+    return (BR_HDR + 3 * Hm + 2 * Em + 2 + 3) / 4 * 4;
 }
 
 // word index of entry p of sorted atom i in the interleaved list
@@ -176,7 +194,7 @@ __device__ __forceinline__ void brick_setup(const Stage &s, const BrickDims &d, 
 {
     int32_t *rec = s.rec;
     int32_t *soff = rec + br_soff(d), *sbeg = rec + br_sbeg(d);
-    int32_t *aoff = rec + br_aoff(d), *abeg = rec + br_abeg(d);
+    int32_t *aoff = rec + br_aoff(d), *abeg = rec + br_abeg(d), *himg = rec + br_himg(d);
     const int32_t H = g.hn[0] * g.hn[1] * g.hn[2];
     const int32_t E = g.e[0] * g.e[1] * g.e[2];
     const int64_t nx = g.nc[0], nxy = (int64_t)g.nc[0] * g.nc[1];
@@ -190,6 +208,14 @@ __device__ __forceinline__ void brick_setup(const Stage &s, const BrickDims &d, 
         const int32_t b0 = start[cell];
         soff[h] = start[cell + 1] - b0;
         sbeg[h] = b0;
+        // image code (bit 0: d + L, bit 1: d - L per axis) of the halo cell
+        const int32_t q[3] = {g.o[0] - 1 + px, g.o[1] - 1 + py, g.o[2] - 1 + pz};
+        int32_t code = 0;
+        for (int k = 0; k < 3; k++) {
+            if (q[k] < 0) code |= 1 << (2 * k);
+            else if (q[k] >= g.nc[k]) code |= 2 << (2 * k);
+        }
+        himg[h] = code;
     }
     for (int32_t e = threadIdx.x; e < E; e += blockDim.x) {
         const int32_t ex = e % g.e[0], t = e / g.e[0];
@@ -212,9 +238,9 @@ __device__ __forceinline__ void brick_setup(const Stage &s, const BrickDims &d, 
         rec[BR_H] = H;
         rec[BR_E] = E;
         bool img = false;
-        for (int k = 0; k < 3; k++)
-            img |= g.nc[k] < 5 || g.o[k] == 0 || g.o[k] + g.e[k] == g.nc[k];
+        for (int k = 0; k < 3; k++) img |= g.nc[k] < 4 || g.e[k] + 2 > g.nc[k];
         rec[BR_IMG] = img ? 1 : 0;
+        rec[BR_SHIFT] = !img && soff[H] <= s.cap ? 1 : 0;
     }
     __syncthreads();
 }
@@ -251,23 +277,43 @@ __device__ __forceinline__ int64_t brick_atom(const Stage &s, const BrickDims &d
     return s.rec[br_abeg(d) + lo] + (la - aoff[lo]);
 }
 
+// the image shift of a list entry, as an addition: bit 0 adds L, bit 1
+// subtracts it (d + 0 leaves every non-zero d unchanged)
+__device__ __forceinline__ double image_shift(uint32_t code, uint32_t add_bit, double L)
+{
+    return (code & add_bit) ? L : ((code & (add_bit << 1)) ? -L : 0.0);
+}
+
 // Copies the record of brick b into LDS and stages its first `cap` candidates
 // (block-wide; ends with a barrier).  extra0/extra1 (may be null) are staged
-// as extras 0 and 1.
+// as extras 0 and 1.  A brick with BR_SHIFT = 1 has its candidates staged
+// through their halo cell's image (x_j - shift, so that x_i - x_j' is the
+// shifted difference); pairs of it take no image code.
 __device__ __forceinline__ void brick_load(const Stage &s, const BrickDims &d, const int32_t *grec,
-                                           const double4 *pos, const double *extra0,
-                                           const double *extra1)
+                                           const RepDesc *reps, const double4 *pos,
+                                           const double *extra0, const double *extra1)
 {
     for (int32_t t = threadIdx.x; t < d.stride; t += blockDim.x) s.rec[t] = grec[t];
     __syncthreads();
     const int32_t total = s.rec[BR_TOTAL];
     const int32_t lim = total < s.cap ? total : s.cap;
+    const bool shifted = s.rec[BR_SHIFT] != 0;
+    const RepDesc &rep = reps[s.rec[BR_REP]];
+    const double Lx = rep.L[0], Ly = rep.L[1], Lz = rep.L[2];
     for (int32_t k = threadIdx.x; k < lim; k += blockDim.x) {
-        const int32_t g = candidate_index(s, d, k);
+        const int32_t h = halo_cell(s, k);
+        const int32_t g = s.rec[br_sbeg(d) + h] + (k - s.rec[BR_HDR + h]);
         const double4 p = pos[g];
-        s.xyz[3 * k] = p.x;
-        s.xyz[3 * k + 1] = p.y;
-        s.xyz[3 * k + 2] = p.z;
+        if (shifted) {
+            const uint32_t c = (uint32_t)s.rec[br_himg(d) + h];
+            s.xyz[3 * k] = p.x - image_shift(c, 1u, Lx);
+            s.xyz[3 * k + 1] = p.y - image_shift(c, 4u, Ly);
+            s.xyz[3 * k + 2] = p.z - image_shift(c, 16u, Lz);
+        } else {
+            s.xyz[3 * k] = p.x;
+            s.xyz[3 * k + 1] = p.y;
+            s.xyz[3 * k + 2] = p.z;
+        }
         if (s.j != nullptr) s.j[k] = g;
         if (extra0 != nullptr) s.ex[k] = extra0[g];
         if (extra1 != nullptr) s.ex[s.cap + k] = extra1[g];
@@ -284,13 +330,6 @@ __device__ __forceinline__ double rcp64(double x)
     r = fma(r, e, r);
     e = fma(-x, r, 1.0);
     return fma(r, e, r);
-}
-
-// the image shift of a list entry, as an addition: bit 0 adds L, bit 1
-// subtracts it (d + 0 leaves every non-zero d unchanged)
-__device__ __forceinline__ double image_shift(uint32_t code, uint32_t add_bit, double L)
-{
-    return (code & add_bit) ? L : ((code & (add_bit << 1)) ? -L : 0.0);
 }
 
 // Position of candidate k.  STAGED = true: the whole halo is in LDS (pure LDS
@@ -346,12 +385,13 @@ __device__ __forceinline__ void walk_list(const Stage &s, const BrickDims &d, co
         double px[4], py[4], pz[4];
         _Pragma("unroll")
         for (int u = 0; u < 4; u++)
-            candidate_pos<STAGED>(s, d, (int32_t)((u < rem ? es[u] : 0u) & MD_IDX_MASK), pos, px[u], py[u], pz[u]);
+            candidate_pos<STAGED>(s, d, (int32_t)(IMG ? ((u < rem ? es[u] : 0u) & MD_IDX_MASK) : (u < rem ? es[u] : 0u)),
+                                  pos, px[u], py[u], pz[u]);
         _Pragma("unroll")
         for (int u = 0; u < 4; u++) {
             const bool ok = u < rem;
             const uint32_t en = ok ? es[u] : 0u;
-            const int32_t k = (int32_t)(en & MD_IDX_MASK);
+            const int32_t k = (int32_t)(IMG ? en & MD_IDX_MASK : en);
             double dx = xi.x - px[u], dy = xi.y - py[u], dz = xi.z - pz[u];
             if (IMG) {
                 const uint32_t c = en >> MD_IDX_BITS;
@@ -365,7 +405,9 @@ __device__ __forceinline__ void walk_list(const Stage &s, const BrickDims &d, co
     }
 }
 
-// runs the block once per (STAGED, IMG) combination (both uniform per brick)
+// runs the block once per (STAGED, IMG) combination (both uniform per brick):
+// IMG = false exactly for the bricks whose staging applied the cell images
+// (BR_SHIFT = 1, which implies a wholly staged halo)
 #define STAGE_IMG_SPLIT(ALL_STAGED, HAS_IMG, ...)                                         \
     if (ALL_STAGED) {                                                                     \
         constexpr bool STAGED = true;                                                     \
@@ -379,15 +421,6 @@ __device__ __forceinline__ void walk_list(const Stage &s, const BrickDims &d, co
     } else {                                                                              \
         constexpr bool STAGED = false;                                                    \
         constexpr bool IMG = true;                                                        \
-        __VA_ARGS__                                                                       \
-    }
-
-#define STAGED_SPLIT(ALL_STAGED, ...)                                                     \
-    if (ALL_STAGED) {                                                                     \
-        constexpr bool STAGED = true;                                                     \
-        __VA_ARGS__                                                                       \
-    } else {                                                                              \
-        constexpr bool STAGED = false;                                                    \
         __VA_ARGS__                                                                       \
     }
 
@@ -501,9 +534,9 @@ __device__ __forceinline__ BrickRange balanced_bricks(const int64_t *w, int64_t 
         const int32_t natoms = grec_[BR_ATOMS];                                           \
         if (natoms == 0) continue;                                                        \
         __syncthreads();                                                                  \
-        brick_load(ST, a.bd, grec_, POS, EXTRA0, EXTRA1);                                 \
+        brick_load(ST, a.bd, grec_, a.reps, POS, EXTRA0, EXTRA1);                         \
         const int32_t rep_r = ST.rec[BR_REP];                                             \
-        const bool has_img = ST.rec[BR_IMG] != 0;                                         \
+        const bool has_img = ST.rec[BR_SHIFT] == 0;                                       \
         const bool all_staged = ST.rec[BR_TOTAL] <= ST.cap;                               \
         const RepDesc &rep_ = a.reps[rep_r];                                              \
         const double Lx = rep_.L[0], Ly = rep_.L[1], Lz = rep_.L[2];                      \

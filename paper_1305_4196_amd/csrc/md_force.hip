@@ -149,8 +149,9 @@ __device__ __forceinline__ void finish_block(const ForceArgs &a, double accE, do
 // ---------------------------------------------------------------- LJ pair scalar
 // f_s = 24 eps (2 q12 - q6) / r2 and V = 4 eps (q12 - q6), q6 = (sigma^2/r2)^3.
 // Outside the cutoff (or for an empty slot) 1/r2 is replaced by 0, which makes
-// both exactly zero without further selects.
-template <bool MIXED>
+// both exactly zero without further selects.  V only if EN (the force does not
+// depend on it).
+template <bool MIXED, bool EN = true>
 __device__ __forceinline__ void lj_pair(bool in, double r2, double s2, double e4, double e24, float s2f,
                                         float e4f, float e24f, double &fs, double &V)
 {
@@ -159,8 +160,8 @@ __device__ __forceinline__ void lj_pair(bool in, double r2, double s2, double e4
         const float q2 = s2f * ir2;
         const float q6 = q2 * q2 * q2;
         const float q12 = q6 * q6;
-        fs = (double)(e24f * (2.0f * q12 - q6) * ir2);
-        V = (double)(e4f * (q12 - q6));
+        fs = (double)(e24f * __builtin_fmaf(2.0f, q12, -q6) * ir2);
+        V = EN ? (double)(e4f * (q12 - q6)) : 0.0;
     } else {
         const double ir2 = in ? rcp64(r2) : 0.0;
         const double q2 = s2 * ir2;
@@ -172,7 +173,9 @@ __device__ __forceinline__ void lj_pair(bool in, double r2, double s2, double e4
 }
 
 // ---------------------------------------------------------------- LJ, full list
-template <bool MIXED>
+// EN: the launch returns energy or virial (steps that record no energy skip
+// their per-pair terms)
+template <bool MIXED, bool EN>
 __global__ __launch_bounds__(TASK_MAX_THREADS) void k_lj_full(ForceArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -191,12 +194,14 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_lj_full(ForceArgs a)
             walk_list<STAGED, IMG>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
                 [&](bool ok, int32_t, double dx, double dy, double dz, double r2) {
                     double fs, V;
-                    lj_pair<MIXED>(ok && r2 < rc2, r2, s2, e4, e24, s2f, e4f, e24f, fs, V);
+                    lj_pair<MIXED, EN>(ok && r2 < rc2, r2, s2, e4, e24, s2f, e4f, e24f, fs, V);
                     fx = fma(fs, dx, fx);
                     fy = fma(fs, dy, fy);
                     fz = fma(fs, dz, fz);
-                    e += V;
-                    w += fs * r2;
+                    if (EN) {
+                        e += V;
+                        w += fs * r2;
+                    }
                 });
         )
         if (valid) finish_atom(a, i, xi, fx, fy, fz, 0.5 * e, 0.5 * w, accE, accW, accK);
@@ -468,7 +473,19 @@ __global__ __launch_bounds__(256) void k_replica_sums(const RepDesc *__restrict_
 
 void launch_lj_full(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a)
 {
-    MD_LAUNCH_TASKS(k_lj_full, 0, false)
+    const size_t lds = stage_bytes(a.cap, 0, false, a.bd.stride);
+    const bool en = a.outE != nullptr || a.outW != nullptr || a.eatom != nullptr;
+    auto go = [&](auto kernel) {
+        allow_lds(kernel, lds);
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), lds, s, a);
+    };
+    if (mixed) {
+        if (en) go(k_lj_full<true, true>);
+        else go(k_lj_full<true, false>);
+    } else {
+        if (en) go(k_lj_full<false, true>);
+        else go(k_lj_full<false, false>);
+    }
 }
 
 void launch_lj_half(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a)

@@ -10,7 +10,10 @@
 // in binary64 with contraction off, keeping j iff r2 < (rc + skin)^2 and j != i
 // (and, for the half list, j after i in the sorted order).  Only the wavefront
 // of atom i's cell appends to i's list, so every list has exactly one writer
-// and no atomics are needed (each task owns its lists, Sec. II.C).
+// and no atomics are needed (each task owns its lists, Sec. II.C).  An entry
+// holds the candidate index and the pair's image code, except in bricks that
+// stage their halo through the cell images (BR_SHIFT), where the code equals
+// the candidate's halo-cell image and is left out.
 //
 // The three cells of a stencil row along x are consecutive in the halo order
 // (or, on a grid of at most bx + 1 cells, wrap around it), so each of the 9
@@ -95,6 +98,8 @@ __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, co
     const double hx = rep.hL[0], hy = rep.hL[1], hz = rep.hL[2];
     const double rl2 = a.rl2;
     const int32_t M = a.nbr == nullptr ? 0 : a.M;
+    // bricks staged through their cell images store bare candidate indices
+    const uint32_t cmask = st.rec[BR_SHIFT] != 0 ? 0u : ~0u;
     int32_t tot = 0;
     // the cell's atoms in groups of up to 128 (two per lane)
     for (int32_t g0 = 0; g0 < na_all; g0 += 128) {
@@ -203,7 +208,7 @@ __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, co
                         const uint64_t mask = __ballot(hit);
                         if (mask != 0) {
                             const int32_t p = ni + (int32_t)lanes_below(mask);
-                            if (hit && p < M) base[((int64_t)(p >> 2) << 8) + (p & 3)] = (uint32_t)ck[c] | (code << MD_IDX_BITS);
+                            if (hit && p < M) base[((int64_t)(p >> 2) << 8) + (p & 3)] = (uint32_t)ck[c] | ((code << MD_IDX_BITS) & cmask);
                             ni += (int32_t)__popcll(mask);
                         }
                     }

@@ -82,8 +82,8 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_lj_vjp(VjpArgs v)
         const double vE = v.vE[rep_r];
         const double4 xi = a.pos[i];
         const double ui[3] = {v.u[i], v.u[n + i], v.u[2 * n + i]};
-        STAGED_SPLIT(all_staged,
-            walk_list<STAGED, true>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
+        STAGE_IMG_SPLIT(all_staged, has_img,
+            walk_list<STAGED, IMG>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
                 [&](bool ok, int32_t k, double dx, double dy, double dz, double r2) {
                     if (!ok || !(r2 < rc2)) return;
                     const int32_t j = candidate_j<STAGED>(st, a.bd, k);
@@ -133,8 +133,8 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_vjp_a(VjpArgs v)
         double rho = 0.0, rdot = 0.0;
         const double4 xi = a.pos[i];
         const double ui[3] = {v.u[i], v.u[n + i], v.u[2 * n + i]};
-        STAGED_SPLIT(all_staged,
-            walk_list<STAGED, true>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
+        STAGE_IMG_SPLIT(all_staged, has_img,
+            walk_list<STAGED, IMG>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
                 [&](bool ok, int32_t k, double dx, double dy, double dz, double r2) {
                     if (!ok || !(r2 < rrho2)) return;
                     const int32_t j = candidate_j<STAGED>(st, a.bd, k);
@@ -180,8 +180,8 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_vjp_b(VjpArgs v)
         const double ui[3] = {v.u[i], v.u[n + i], v.u[2 * n + i]};
         const double fpi = a.fp[i];
         const double qi = v.fpp[i] * v.rdot[i];
-        STAGED_SPLIT(all_staged,
-            walk_list<STAGED, true>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
+        STAGE_IMG_SPLIT(all_staged, has_img,
+            walk_list<STAGED, IMG>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
                 [&](bool ok, int32_t k, double dx, double dy, double dz, double r2) {
                     const bool in_phi = r2 < rphi2, in_rho = r2 < rrho2;
                     if (!ok || (!in_phi && !in_rho)) return;

@@ -59,18 +59,20 @@ class MDSystem:
         return F, E, W
 
     def run(self, n_steps: int, dt: float, mass: float = 1.0, precision: int = B.MD_FP64,
-            kind: int = B.MD_LIST_FULL, record: bool = True, max_retries: int = 3):
-        """Velocity Verlet in place on self.pos / self.vel.
-        Returns (forces, hist [n_steps][3] or None, rebuild count)."""
+            kind: int = B.MD_LIST_FULL, record: bool = True, max_retries: int = 3, every: int = 1):
+        """Velocity Verlet in place on self.pos / self.vel.  Returns (forces,
+        hist [ceil(n_steps / every)][3] (E_pot, KE, W after steps every,
+        2 every, ... and the last) or None, rebuild count)."""
         if self._built is None:
             B.md_build_cells(self.ctx, self.pos, self.boxes, self.pot.rc, self.skin)
         x0, v0 = self.pos.clone(), self.vel.clone()
         F = torch.empty_like(self.pos)
-        hist = torch.zeros((n_steps, 3), dtype=torch.float64, device=self.device) if record else None
+        rows = (n_steps + every - 1) // every
+        hist = torch.zeros((rows, 3), dtype=torch.float64, device=self.device) if record else None
         nreb = torch.zeros(1, dtype=torch.int32, device=self.device)
         for _ in range(max_retries + 1):
             B.md_verlet_step(self.ctx, self.dpot, precision, kind, self.pos, self.vel, F, dt, mass,
-                             n_steps, hist, nreb)
+                             n_steps, hist, nreb, hist_every=every)
             code, flags, cap = B.md_get_status(self.ctx)
             if code == B.MD_OK:
                 self._built = None

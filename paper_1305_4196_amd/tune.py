@@ -28,7 +28,7 @@ LDS_PER_CU = 160 * 1024
 
 
 def record_stride(halo: int, cells: int) -> int:
-    return (8 + 2 * halo + 2 * cells + 2 + 3) // 4 * 4
+    return (8 + 3 * halo + 2 * cells + 2 + 3) // 4 * 4
 
 
 def score(shape: Tuple[int, int, int], threads: int, occ: float, wgpc: int = 8,

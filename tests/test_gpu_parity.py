@@ -310,6 +310,21 @@ def test_verlet_mixed_tracks_fp64():
     assert np.max(np.abs(e - eo)) / abs(eo[0]) < 1e-5
 
 
+@pytest.mark.parametrize("prec", [B.MD_FP64, B.MD_MIXED])
+def test_verlet_energy_interval(prec):
+    """Recording every 7th step skips the pair loops' energy terms in between
+    without touching the trajectory: the recorded rows, the positions and the
+    forces equal those of the run that records every step, bit for bit."""
+    w = W.lj_small()
+    s1 = MDSystem.from_workload(w)
+    F1, h1, n1 = s1.run(40, w.dt, w.mass, prec)
+    s7 = MDSystem.from_workload(w)
+    F7, h7, n7 = s7.run(40, w.dt, w.mass, prec, every=7)
+    assert h7.shape == (6, 3)
+    assert torch.equal(h7, h1[[6, 13, 20, 27, 34, 39]])
+    assert torch.equal(s7.pos, s1.pos) and torch.equal(F7, F1) and n7 == n1
+
+
 def test_verlet_eam_fp64():
     w = eam_case(5, 6, sd=0.08)
     L = w.boxes[0]
