@@ -47,50 +47,67 @@ __device__ __forceinline__ double readlane_f64(double v, int l)
     return __longlong_as_double((int64_t)(((uint64_t)hi << 32) | lo));
 }
 
-template <bool HALF>
+// Runs of the stencil rows of own cell lc, built by the wavefront's lanes in
+// parallel (lane t: layer sz = t / (2 np_y), row sy = (t / 2) % np_y, part t & 1,
+// the order of a plain loop over sz, sy, part) and stored in LDS:
+// runs[0..nr) first candidates, runs[32..32+nr] prefix of their lengths,
+// runs[31] = nr.  Along an axis the stencil's halo coordinate is lc + s
+// (s = 0..np-1), reduced by n when the halo covers the axis (lc + s < 2 n).
+__device__ __forceinline__ void build_runs(const Stage &st, const BrickGeom &g, const int32_t lc[3],
+                                           const int32_t np[3], int32_t *runs)
+{
+    const int lane = threadIdx.x & 63;
+    const int32_t *soff = st.rec + BR_HDR;
+    const int32_t nt = 2 * np[1] * np[2];
+    int32_t kb = 0, len = 0;
+    if (lane < nt) {
+        const int32_t part = lane & 1, sy = (lane >> 1) % np[1], sz = (lane >> 1) / np[1];
+        int32_t hy = lc[1] + sy, hz = lc[2] + sz;
+        hy = hy >= g.nc[1] ? hy - g.nc[1] : hy;
+        hz = hz >= g.nc[2] ? hz - g.nc[2] : hz;
+        const int32_t rowh = g.hn[0] * (hy + g.hn[1] * hz);
+        const int32_t xa = lc[0];
+        const int32_t x1 = xa + np[0] < g.hn[0] ? xa + np[0] : g.hn[0];
+        const int32_t x2 = xa + np[0] - x1;
+        kb = part == 0 ? soff[rowh + xa] : soff[rowh];
+        const int32_t ke = part == 0 ? soff[rowh + x1] : soff[rowh + x2];
+        len = ke > kb ? ke - kb : 0;
+    }
+    // exclusive prefix of the lengths over the lanes, then the non-empty runs compacted
+    int32_t inc = len;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    const uint64_t nonempty = __builtin_amdgcn_ballot_w64(len > 0);
+    if (len > 0) {
+        const int32_t r = (int32_t)lanes_below(nonempty);
+        runs[r] = kb;
+        runs[32 + r] = inc - len;
+    }
+    const int32_t nr = (int32_t)__popcll(nonempty);
+    const int32_t total = __shfl(inc, 63, 64);     // with every lane active
+    if (lane == 0) {
+        runs[32 + nr] = total;
+        runs[31] = nr;
+    }
+    wave_sync();
+}
+
+// WRAP: some axis of the cell needs the minimum-image test; otherwise the
+// test and the image code are compiled out.
+template <bool HALF, bool WRAP>
 __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, const BrickGeom &g,
-                                          int32_t e, int32_t na_all, int32_t *runs, int32_t &my_max,
+                                          int32_t e, int32_t na_all, const int32_t lc[3],
+                                          const bool wrap[3], int32_t *runs, int32_t &my_max,
                                           int32_t *bpairs)
 {
     const int lane = threadIdx.x & 63;
     const int32_t *soff = st.rec + br_soff(a.bd);
     const int32_t *abeg = st.rec + br_abeg(a.bd);
-    const int32_t lc[3] = {e % g.e[0], (e / g.e[0]) % g.e[1], e / (g.e[0] * g.e[1])};
-    int32_t np[3];
-    bool wrap[3];
-    for (int d = 0; d < 3; d++) {
-        const int32_t c = g.o[d] + lc[d];
-        np[d] = g.nc[d] >= 3 ? 3 : 2;
-        wrap[d] = !(g.nc[d] >= 5 && c >= 1 && c <= g.nc[d] - 2);
-    }
     const int32_t hown = (lc[0] + 1) % g.nc[0] + g.hn[0] * ((lc[1] + 1) % g.nc[1] + g.hn[1] * ((lc[2] + 1) % g.nc[2]));
     const int32_t k_own = soff[hown];          // candidate index of the cell's first atom
     const int64_t i0_all = abeg[e];            // sorted index of the cell's first atom
-    // runs of the stencil rows in LDS: runs[0..nr) first candidates,
-    // runs[32..32+nr] prefix of their lengths, runs[31] = nr
-    if (lane == 0) {
-        const int32_t xa = lc[0] % g.nc[0];
-        const int32_t x1 = xa + np[0] < g.hn[0] ? xa + np[0] : g.hn[0];
-        const int32_t x2 = xa + np[0] - x1;
-        int32_t nr = 0, tot = 0;
-        for (int sz = 0; sz < np[2]; sz++)
-            for (int sy = 0; sy < np[1]; sy++) {
-                const int32_t rowh = g.hn[0] * ((lc[1] + sy) % g.nc[1] + g.hn[1] * ((lc[2] + sz) % g.nc[2]));
-                for (int part = 0; part < 2; part++) {
-                    const int32_t kb = part == 0 ? soff[rowh + xa] : soff[rowh];
-                    const int32_t ke = part == 0 ? soff[rowh + x1] : soff[rowh + x2];
-                    if (ke > kb) {
-                        runs[nr] = kb;
-                        runs[32 + nr] = tot;
-                        tot += ke - kb;
-                        nr++;
-                    }
-                }
-            }
-        runs[32 + nr] = tot;
-        runs[31] = nr;
-    }
-    wave_sync();
     const int32_t nr = runs[31];
     const int32_t ncand = runs[32 + nr];
     const RepDesc &rep = a.reps[g.r];
@@ -169,6 +186,9 @@ __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, co
                 cj[c] = j;
             }
         }
+        uint64_t valid[TILE];
+        _Pragma("unroll")
+        for (int c = 0; c < TILE; c++) valid[c] = __builtin_amdgcn_ballot_w64(ck[c] >= 0);
         // atoms 0..63 of the group from the first register set, 64..127 from the second
         for (int half = 0; half < 2; half++) {
             const int32_t at_end = half == 0 ? (na < 64 ? na : 64) : na;
@@ -182,33 +202,41 @@ __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, co
                 const double yi = readlane_f64(ay, l);
                 const double zi = readlane_f64(az, l);
                 int32_t ni = t0 == 0 ? 0 : __builtin_amdgcn_readlane(cnt, l);
+                // the atom's row (uniform); entry p at word (p/4) * 256 + p%4 of it
                 uint32_t *base = a.nbr + (((i >> 6) * (int64_t)(a.M >> 2)) << 8) + ((i & 63) << 2);
                 _Pragma("unroll")
                 for (int c = 0; c < TILE; c++) {
                     if (c < nch) {
                         double dx = xi - cx[c], dy = yi - cy[c], dz = zi - cz[c];
                         uint32_t code = 0;
-                        if (wrap[0]) {
-                            const bool gt = dx > hx, lt = dx < -hx;
-                            dx = gt ? dx - Lx : (lt ? dx + Lx : dx);
-                            code |= gt ? 2u : (lt ? 1u : 0u);
-                        }
-                        if (wrap[1]) {
-                            const bool gt = dy > hy, lt = dy < -hy;
-                            dy = gt ? dy - Ly : (lt ? dy + Ly : dy);
-                            code |= gt ? 8u : (lt ? 4u : 0u);
-                        }
-                        if (wrap[2]) {
-                            const bool gt = dz > hz, lt = dz < -hz;
-                            dz = gt ? dz - Lz : (lt ? dz + Lz : dz);
-                            code |= gt ? 32u : (lt ? 16u : 0u);
+                        if (WRAP) {
+                            if (wrap[0]) {
+                                const bool gt = dx > hx, lt = dx < -hx;
+                                dx = gt ? dx - Lx : (lt ? dx + Lx : dx);
+                                code |= gt ? 2u : (lt ? 1u : 0u);
+                            }
+                            if (wrap[1]) {
+                                const bool gt = dy > hy, lt = dy < -hy;
+                                dy = gt ? dy - Ly : (lt ? dy + Ly : dy);
+                                code |= gt ? 8u : (lt ? 4u : 0u);
+                            }
+                            if (wrap[2]) {
+                                const bool gt = dz > hz, lt = dz < -hz;
+                                dz = gt ? dz - Lz : (lt ? dz + Lz : dz);
+                                code |= gt ? 32u : (lt ? 16u : 0u);
+                            }
                         }
                         const double r2 = (dx * dx + dy * dy) + dz * dz;
+                        // one ballot per comparison (each is a plain compare mask), ANDed as scalars
                         const bool hit = (ck[c] >= 0) & (r2 < rl2) & (ck[c] != kself) & (!HALF | (cj[c] > i));
-                        const uint64_t mask = __ballot(hit);
+                        uint64_t mask = valid[c] & __builtin_amdgcn_ballot_w64(r2 < rl2) &
+                                        __builtin_amdgcn_ballot_w64(ck[c] != kself);
+                        if (HALF) mask &= __builtin_amdgcn_ballot_w64(cj[c] > i);
                         if (mask != 0) {
                             const int32_t p = ni + (int32_t)lanes_below(mask);
-                            if (hit && p < M) base[((int64_t)(p >> 2) << 8) + (p & 3)] = (uint32_t)ck[c] | ((code << MD_IDX_BITS) & cmask);
+                            const uint32_t off = ((uint32_t)p >> 2 << 8) | ((uint32_t)p & 3u);
+                            const uint32_t word = WRAP ? (uint32_t)ck[c] | ((code << MD_IDX_BITS) & cmask) : (uint32_t)ck[c];
+                            if (hit && p < M) base[off] = word;
                             ni += (int32_t)__popcll(mask);
                         }
                     }
@@ -280,20 +308,33 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_build_list(ListArgs a)
         for (int32_t e = w; e < E; e += (int32_t)(blockDim.x >> 6)) {
             const int32_t na = aoff[e + 1] - aoff[e];
             if (na == 0) continue;
-            scan_cell<HALF>(a, st, g, e, na, runs_lds + 64 * w, my_max, &bpairs);
-            // copy the freshly sorted state of the cell's atoms into the working buffers
-            if (a.pos_dst != nullptr) {
-                for (int32_t at = lane; at < na; at += 64) {
-                    const int64_t i = st.rec[br_abeg(a.bd) + e] + at;
-                    const double4 p = a.src[i];
-                    a.pos_dst[i] = p;
-                    a.xref[i] = p;
-                    a.id_dst[i] = a.id_src[i];
-                    if (a.vel_dst != nullptr) {
-                        a.vel_dst[i] = a.vel_src[i];
-                        a.vel_dst[a.n + i] = a.vel_src[a.n + i];
-                        a.vel_dst[2 * a.n + i] = a.vel_src[2 * a.n + i];
-                    }
+            const int32_t lc[3] = {e % g.e[0], (e / g.e[0]) % g.e[1], e / (g.e[0] * g.e[1])};
+            int32_t np[3];
+            bool wrap[3];
+            for (int d = 0; d < 3; d++) {
+                const int32_t c = g.o[d] + lc[d];
+                np[d] = g.nc[d] >= 3 ? 3 : 2;
+                wrap[d] = !(g.nc[d] >= 5 && c >= 1 && c <= g.nc[d] - 2);
+            }
+            int32_t *runs = runs_lds + 64 * w;
+            build_runs(st, g, lc, np, runs);
+            if (wrap[0] || wrap[1] || wrap[2])
+                scan_cell<HALF, true>(a, st, g, e, na, lc, wrap, runs, my_max, &bpairs);
+            else
+                scan_cell<HALF, false>(a, st, g, e, na, lc, wrap, runs, my_max, &bpairs);
+        }
+        // copy the freshly sorted state of the brick's atoms into the working buffers
+        if (a.pos_dst != nullptr) {
+            for (int32_t la = threadIdx.x; la < natoms; la += blockDim.x) {
+                const int64_t i = brick_atom(st, a.bd, la);
+                const double4 p = a.src[i];
+                a.pos_dst[i] = p;
+                a.xref[i] = p;
+                a.id_dst[i] = a.id_src[i];
+                if (a.vel_dst != nullptr) {
+                    a.vel_dst[i] = a.vel_src[i];
+                    a.vel_dst[a.n + i] = a.vel_src[a.n + i];
+                    a.vel_dst[2 * a.n + i] = a.vel_src[2 * a.n + i];
                 }
             }
         }
