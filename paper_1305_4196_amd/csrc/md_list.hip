@@ -38,6 +38,8 @@ namespace {
 // running list length is a scalar while the atom is tested and is kept in lane
 // a between tiles.
 constexpr int TILE = 4;
+// candidates per cell whose run starts are flagged in LDS (more: binary search)
+constexpr int CRUN = 768;
 
 __device__ __forceinline__ double readlane_f64(double v, int l)
 {
@@ -50,11 +52,13 @@ __device__ __forceinline__ double readlane_f64(double v, int l)
 // Runs of the stencil rows of own cell lc, built by the wavefront's lanes in
 // parallel (lane t: layer sz = t / (2 np_y), row sy = (t / 2) % np_y, part t & 1,
 // the order of a plain loop over sz, sy, part) and stored in LDS:
-// runs[0..nr) first candidates, runs[32..32+nr] prefix of their lengths,
+// runs[0..nr) candidate index minus position (the cell's v-th candidate, v in
+// run r, is v + runs[r]), runs[32..32+nr] prefix of the run lengths,
 // runs[31] = nr.  Along an axis the stencil's halo coordinate is lc + s
 // (s = 0..np-1), reduced by n when the halo covers the axis (lc + s < 2 n).
+// With at most CRUN candidates, crun[v] = 1 exactly where a run starts.
 __device__ __forceinline__ void build_runs(const Stage &st, const BrickGeom &g, const int32_t lc[3],
-                                           const int32_t np[3], int32_t *runs)
+                                           const int32_t np[3], int32_t *runs, uint8_t *crun)
 {
     const int lane = threadIdx.x & 63;
     const int32_t *soff = st.rec + BR_HDR;
@@ -80,16 +84,23 @@ __device__ __forceinline__ void build_runs(const Stage &st, const BrickGeom &g, 
         if (lane >= o) inc += y;
     }
     const uint64_t nonempty = __builtin_amdgcn_ballot_w64(len > 0);
+    const int32_t pex = inc - len;
     if (len > 0) {
         const int32_t r = (int32_t)lanes_below(nonempty);
-        runs[r] = kb;
-        runs[32 + r] = inc - len;
+        runs[r] = kb - pex;
+        runs[32 + r] = pex;
     }
     const int32_t nr = (int32_t)__popcll(nonempty);
     const int32_t total = __shfl(inc, 63, 64);     // with every lane active
     if (lane == 0) {
         runs[32 + nr] = total;
         runs[31] = nr;
+    }
+    if (total <= CRUN) {
+        uint32_t *w32 = reinterpret_cast<uint32_t *>(crun);
+        for (int32_t q = lane; q < (total + 3) >> 2; q += 64) w32[q] = 0u;
+        wave_sync();
+        if (len > 0) crun[pex] = 1;
     }
     wave_sync();
 }
@@ -99,8 +110,8 @@ __device__ __forceinline__ void build_runs(const Stage &st, const BrickGeom &g, 
 template <bool HALF, bool WRAP>
 __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, const BrickGeom &g,
                                           int32_t e, int32_t na_all, const int32_t lc[3],
-                                          const bool wrap[3], int32_t *runs, int32_t &my_max,
-                                          int32_t *bpairs)
+                                          const bool wrap[3], const int32_t *runs, const uint8_t *crun,
+                                          int32_t &my_max, int32_t *bpairs)
 {
     const int lane = threadIdx.x & 63;
     const int32_t *soff = st.rec + br_soff(a.bd);
@@ -152,6 +163,7 @@ __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, co
             }
         }
     }
+    int32_t rbase = 0;                         // runs started before the current chunk
     for (int32_t t0 = 0; t0 < ncand; t0 += 64 * TILE) {
         const int32_t nch = min(TILE, (ncand - t0 + 63) >> 6);
         double cx[TILE], cy[TILE], cz[TILE];
@@ -161,13 +173,23 @@ __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, co
         for (int c = 0; c < TILE; c++) {
             const int32_t v = t0 + 64 * c + lane;
             int32_t k = k_own;
-            if (c < nch && v < ncand) {
+            if (ncand <= CRUN) {
+                // run of candidate v: the runs started before this chunk plus
+                // the starts flagged up to v within it
+                if (c < nch) {
+                    const bool st0 = v < ncand && crun[v] != 0;
+                    const uint64_t sm = __builtin_amdgcn_ballot_w64(st0);
+                    const int32_t r = rbase + (int32_t)lanes_below(sm) + (st0 ? 1 : 0) - 1;
+                    rbase += (int32_t)__popcll(sm);
+                    if (v < ncand) k = v + runs[r];
+                }
+            } else if (c < nch && v < ncand) {
                 int32_t lo = 0, hi = nr - 1;
                 while (lo < hi) {
                     const int32_t mid = (lo + hi + 1) >> 1;
                     if (runs[32 + mid] <= v) lo = mid; else hi = mid - 1;
                 }
-                k = runs[lo] + (v - runs[32 + lo]);
+                k = v + runs[lo];
             }
             ck[c] = (c < nch && v < ncand) ? k : -1;
             cj[c] = 0;
@@ -262,6 +284,14 @@ __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, co
     if (lane == 0) atomicAdd(bpairs, tot);
 }
 
+// next own cell for this wavefront (uniform)
+__device__ __forceinline__ int32_t take_cell(int32_t *next_cell)
+{
+    int32_t v = 0;
+    if ((threadIdx.x & 63) == 0) v = atomicAdd(next_cell, 1);
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
 template <bool HALF>
 __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_build_list(ListArgs a)
 {
@@ -269,17 +299,22 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_build_list(ListArgs a)
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ int32_t smax[TASK_MAX_THREADS / 64], stot[TASK_MAX_THREADS / 64], sbr[TASK_MAX_THREADS / 64];
     __shared__ int32_t runs_lds[64 * (TASK_MAX_THREADS / 64)];
+    __shared__ uint8_t crun_lds[CRUN * (TASK_MAX_THREADS / 64)];
+    __shared__ int32_t order[64];
     const Stage st = stage_slice(lds_raw, a.cap, 0, HALF);
     const int lane = threadIdx.x & 63;
     // the wavefront index as a scalar, so that everything derived per cell is uniform
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    __shared__ int32_t slot, bpairs;
+    __shared__ int32_t slot, bpairs, next_cell;
     int32_t my_max = 0, my_tot = 0, my_br = 0;
 
     for (;;) {
         const int64_t b = next_brick(a.tq, a.B, &slot);
         if (b < 0) break;
-        if (threadIdx.x == 0) bpairs = 0;
+        if (threadIdx.x == 0) {
+            bpairs = 0;
+            next_cell = (int32_t)(blockDim.x >> 6);
+        }
         const BrickGeom g = brick_geom(a.reps, a.R, b);
         brick_setup(st, a.bd, g, a.start);
         int32_t *grec = a.brec + b * (int64_t)a.bd.stride;
@@ -304,10 +339,24 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_build_list(ListArgs a)
         __syncthreads();
         const int32_t E = st.rec[BR_E];
         const int32_t *aoff = st.rec + br_aoff(a.bd);
-        // own cells: one wavefront per cell
-        for (int32_t e = w; e < E; e += (int32_t)(blockDim.x >> 6)) {
+        // cells by decreasing atom count (ties by index): the cheap ones come
+        // last, so the wavefronts finish the brick close together
+        if (w == 0) {
+            const int32_t my = lane < E ? aoff[lane + 1] - aoff[lane] : -1;
+            int32_t rank = 0;
+            for (int32_t q = 0; q < E; q++) {
+                const int32_t o = __shfl(my, q, 64);
+                rank += (o > my || (o == my && q < lane)) ? 1 : 0;
+            }
+            if (lane < E) order[rank] = lane;
+        }
+        __syncthreads();
+        // own cells in that order, one wavefront per cell: the first one per
+        // wavefront fixed, the others taken from a counter as wavefronts finish
+        for (int32_t t = w; t < E;) {
+            const int32_t e = order[t];
             const int32_t na = aoff[e + 1] - aoff[e];
-            if (na == 0) continue;
+            if (na == 0) break;                      // the rest are empty too
             const int32_t lc[3] = {e % g.e[0], (e / g.e[0]) % g.e[1], e / (g.e[0] * g.e[1])};
             int32_t np[3];
             bool wrap[3];
@@ -317,11 +366,13 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_build_list(ListArgs a)
                 wrap[d] = !(g.nc[d] >= 5 && c >= 1 && c <= g.nc[d] - 2);
             }
             int32_t *runs = runs_lds + 64 * w;
-            build_runs(st, g, lc, np, runs);
+            uint8_t *crun = crun_lds + CRUN * w;
+            build_runs(st, g, lc, np, runs, crun);
             if (wrap[0] || wrap[1] || wrap[2])
-                scan_cell<HALF, true>(a, st, g, e, na, lc, wrap, runs, my_max, &bpairs);
+                scan_cell<HALF, true>(a, st, g, e, na, lc, wrap, runs, crun, my_max, &bpairs);
             else
-                scan_cell<HALF, false>(a, st, g, e, na, lc, wrap, runs, my_max, &bpairs);
+                scan_cell<HALF, false>(a, st, g, e, na, lc, wrap, runs, crun, my_max, &bpairs);
+            t = take_cell(&next_cell);
         }
         // copy the freshly sorted state of the brick's atoms into the working buffers
         if (a.pos_dst != nullptr) {
