@@ -30,7 +30,7 @@ ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # algorithmic lane-ops of the LJ pair loop: every listed pair 9 (displacement 3,
 # r^2 5, cutoff test 1); a pair inside rc 17 more (1/r^2 1, q2 1, q6 2, q12 1,
 # 2 q12 - q6 2, f_s 2, V 2, force accumulation 3, energy 1, virial 2)
-OPS_LISTED, OPS_INSIDE = 9, 17
+OPS_LISTED, OPS_INSIDE, OPS_ENERGY = 9, 12, 5
 FORCE_SOURCES = ["paper_1305_4196_amd/csrc/md_force.hip", "paper_1305_4196_amd/csrc/md_brick.h",
                  "paper_1305_4196_amd/csrc/md_internal.h", "paper_1305_4196_amd/csrc/md_reduce.h"]
 
@@ -208,11 +208,12 @@ def main():
     r = results[main_name]
     # The fused LJ force kernel is bound by vector ALU issue, not HBM: its
     # algorithmic lane-ops per atom-step are OPS_LISTED per listed pair plus
-    # OPS_INSIDE per pair inside rc; its algorithmic bytes per atom-step are
+    # OPS_INSIDE per pair inside rc, plus OPS_ENERGY per pair inside rc on the
+    # steps that record energies; its algorithmic bytes per atom-step are
     # list 4 nbar + x read 24 + v read/write 48 + x' write 24 + x_ref read 24.
     t_s = r["force_ms_avg"] * 1e-3
     nbar = r["nbar"]
-    ops_per_atom = OPS_LISTED * nbar + OPS_INSIDE * nbar * inside_frac
+    ops_per_atom = OPS_LISTED * nbar + (OPS_INSIDE + OPS_ENERGY / args.thermo) * nbar * inside_frac
     bytes_per_atom = 4.0 * nbar + 120.0
     achieved_alu = n * ops_per_atom / t_s / 1e12
     achieved_hbm = n * bytes_per_atom / t_s / 1e9
