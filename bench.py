@@ -86,8 +86,9 @@ def main():
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
     ap.add_argument("--thermo", type=int, default=100,
                     help="record E_pot, KE, W every this many steps (and after the last)")
-    ap.add_argument("--list", choices=["full", "half"], default="full",
-                    help="full list (each atom written by its own lane) or Newton-3 half list with atomics")
+    ap.add_argument("--list", choices=["full", "half", "waves"], default="full",
+                    help="full list (each atom written by its own lane), Newton-3 half list with atomics, "
+                         "or the half list run in waves of non-overlapping brick tasks")
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None,
                     help="time one path only (for profiler runs)")
     ap.add_argument("--workload", default="lj_fcc_1048576",
@@ -136,7 +137,7 @@ def main():
     nreb = torch.zeros(1, dtype=torch.int32, device="cuda")
 
     results = {}
-    kind = B.MD_LIST_HALF if args.list == "half" else B.MD_LIST_FULL
+    kind = {"full": B.MD_LIST_FULL, "half": B.MD_LIST_HALF, "waves": B.MD_LIST_WAVES}[args.list]
     paths = [("mixed", B.MD_MIXED), ("fp64", B.MD_FP64)]
     if args.only:
         paths = [p for p in paths if p[0] == args.only]

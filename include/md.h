@@ -55,12 +55,20 @@ typedef enum { MD_FP64 = 0, MD_MIXED = 1 } md_precision;
  *           pair arithmetic (potential, force magnitude, tables) in binary32;
  *           per-atom accumulation, integration and global sums in binary64. */
 
-typedef enum { MD_LIST_FULL = 0, MD_LIST_HALF = 1 } md_list_kind;
+typedef enum { MD_LIST_FULL = 0, MD_LIST_HALF = 1, MD_LIST_WAVES = 2 } md_list_kind;
 /* MD_LIST_FULL: every pair is stored with both atoms; each atom's force is
  *               written only by the worker that owns the atom (no atomics).
  * MD_LIST_HALF: Newton-3 list, each pair once (Sec. II.D.3), held by the atom
  *               that comes first in the cell-sorted order; the partner's force
- *               is accumulated with binary64 atomics (order not deterministic). */
+ *               is accumulated with binary64 atomics (order not deterministic).
+ * MD_LIST_WAVES: the same half list, its brick tasks run in waves of tasks
+ *               whose write sets (a brick and one cell around it) are disjoint
+ *               (Sec. II.B and the appendix: index sets per axis, Cartesian
+ *               products, inner loops not reset), one launch per wave.  A task
+ *               sums partner forces in on-chip memory and adds them to the
+ *               partners with plain stores: no global atomics while the halo
+ *               fits the LDS stage.  LJ only; the order of the on-chip sums
+ *               is not deterministic. */
 
 typedef enum { MD_POT_LJ = 0, MD_POT_EAM = 1 } md_pot_kind;
 
@@ -182,6 +190,14 @@ int64_t md_get_neighbor_list(md_ctx *ctx, int64_t *start, int32_t *nbr, int64_t 
  * Pass NULL arrays to query n_cells_total only.  Synchronises. */
 int md_get_cells(md_ctx *ctx, int32_t *cell_start, int32_t *order, int64_t *n_cells_total);
 
+/* The wave schedule of the last MD_LIST_WAVES build (for checking) [host]:
+ * colour (n_bricks int32 out, capacity entries available): the wave of each
+ * brick, bricks numbered replica by replica, x fastest within a replica's brick
+ * grid; n_bricks (1 int64 out, may be NULL).  Pass colour = NULL to query the
+ * size.  Returns the number of waves (>= 1), or MD_ERR_STATE (no schedule),
+ * MD_ERR_ARG (capacity too small). */
+int md_get_waves(md_ctx *ctx, int32_t *colour, int64_t capacity, int64_t *n_bricks);
+
 /* Tuning knobs (used by the autotuner).  The kernels run one workgroup per
  * brick of bx x by x bz cells (the cell-task blocking of Sec. II.D.2).
  * key 0 = candidates staged in LDS per brick task (64..4096, a multiple of 64,
@@ -205,7 +221,8 @@ int md_set_tuning(md_ctx *ctx, int32_t key, int32_t value);
  * replica 0), 4 threads per brick task, 5 bricks in total, 6 largest brick halo
  * (candidates) and 7 largest brick (atoms) seen by the list builds since the
  * sizing pass (both synchronise), 8 LDS bytes a workgroup may use, 9 workgroups
- * of the LJ force grid, 10 entries of the current list (synchronises).
+ * of the LJ force grid, 10 entries of the current list (synchronises), 11
+ * waves of the current wave schedule (0 if none).
  * Returns MD_OK, MD_ERR_ARG, MD_ERR_STATE (key 10 without a list) or MD_ERR_HIP. */
 int md_query(md_ctx *ctx, int32_t key, int64_t *value);
 

@@ -19,13 +19,14 @@ LIB_PATH = os.path.join(HERE, "libmd.so")
 MD_OK, MD_ERR_ARG, MD_ERR_BOX, MD_ERR_CAPACITY, MD_ERR_NONFINITE, MD_ERR_HIP, MD_ERR_STATE = \
     0, -1, -2, -3, -4, -5, -6
 MD_FP64, MD_MIXED = 0, 1
-MD_LIST_FULL, MD_LIST_HALF = 0, 1
+MD_LIST_FULL, MD_LIST_HALF, MD_LIST_WAVES = 0, 1, 2
 MD_POT_LJ, MD_POT_EAM = 0, 1
 FLAG_OVERFLOW, FLAG_NONFINITE = 1, 2
 
 EXPORTS = ["md_create", "md_destroy", "md_build_cells", "md_build_neighbor_list",
            "md_compute_forces", "md_verlet_step", "md_force_vjp", "md_get_status",
-           "md_get_neighbor_list", "md_get_cells", "md_set_tuning", "md_query", "md_profile", "md_last_error"]
+           "md_get_neighbor_list", "md_get_cells", "md_get_waves", "md_set_tuning", "md_query", "md_profile",
+           "md_last_error"]
 
 
 class MDError(RuntimeError):
@@ -70,6 +71,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     L.md_get_neighbor_list.argtypes = [vp, P(i64), P(i32), i64]
     L.md_get_neighbor_list.restype = i64
     L.md_get_cells.argtypes = [vp, P(i32), P(i32), P(i64)]
+    L.md_get_waves.argtypes = [vp, P(i32), i64, P(i64)]
     L.md_set_tuning.argtypes = [vp, i32, i32]
     L.md_query.argtypes = [vp, i32, P(i64)]
     L.md_profile.argtypes = [vp, i32, P(d), P(i64), P(d), P(i64)]
@@ -238,6 +240,17 @@ def md_get_cells(ctx: Context) -> Tuple[np.ndarray, np.ndarray]:
     _check(ctx.h, L.md_get_cells(ctx.h, cs.ctypes.data_as(C.POINTER(C.c_int32)),
                                  order.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(nc)))
     return cs, order
+
+
+def md_get_waves(ctx: Context) -> Tuple[np.ndarray, int]:
+    """(colour[B], number of waves) of the current wave schedule."""
+    L = load()
+    nb = C.c_int64()
+    _check(ctx.h, min(0, L.md_get_waves(ctx.h, None, 0, C.byref(nb))))
+    col = np.zeros(nb.value, dtype=np.int32)
+    nw = L.md_get_waves(ctx.h, col.ctypes.data_as(C.POINTER(C.c_int32)), nb.value, None)
+    _check(ctx.h, min(0, nw))
+    return col, int(nw)
 
 
 def md_set_tuning(ctx: Context, key: int, value: int):

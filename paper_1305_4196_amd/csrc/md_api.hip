@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "md_brick.h"
+#include "md_waves.h"
 
 namespace {
 
@@ -105,6 +106,13 @@ struct md_ctx {
     int64_t *bwork = nullptr;         // [B+1] their prefix
     int64_t bcost_alloc = 0;
     TaskQueue *tq = nullptr;
+    // waves of bricks with disjoint write sets (MD_LIST_WAVES)
+    bool waves_valid = false;
+    int32_t ncol = 0;
+    std::vector<int64_t> wave_off;        // [ncol+1] offsets into wave_br
+    std::vector<int32_t> brick_colour;    // [B] colour of each brick (host copy)
+    int32_t *wave_br = nullptr;           // [B] bricks ordered by colour, then index
+    int64_t wave_alloc = 0;
 
     // atoms (cell-sorted)
     double4 *pos[2] = {nullptr, nullptr};
@@ -378,7 +386,69 @@ int plan_bricks(md_ctx *c, hipStream_t s)
         hipStreamSynchronize(s) != hipSuccess)
         return fail(c, MD_ERR_HIP, "replica descriptors: copy");
     c->bricks_valid = true;
+    c->waves_valid = false;
     return MD_OK;
+}
+
+// Colours the bricks of every replica (md_waves.h); colour k of all replicas
+// runs in one launch (replicas never interact).
+int plan_waves(md_ctx *c, hipStream_t s)
+{
+    if (c->waves_valid) return MD_OK;
+    c->brick_colour.assign((size_t)c->B, 0);
+    int32_t ncol = 0;
+    for (int32_t r = 0; r < c->R; r++) {
+        const RepDesc &d = c->reps_h[r];
+        int sep[3];
+        for (int k = 0; k < 3; k++) sep[k] = mdwaves::axis_separation(d.nc[k], d.bd[k]);
+        std::vector<int32_t> col;
+        ncol = std::max(ncol, (int32_t)mdwaves::colour_bricks(d.nb, sep, col));
+        std::copy(col.begin(), col.end(), c->brick_colour.begin() + d.brick_off);
+    }
+    std::vector<int64_t> cnt((size_t)ncol + 1, 0);
+    for (int64_t b = 0; b < c->B; b++) cnt[(size_t)c->brick_colour[b] + 1]++;
+    for (int32_t k = 0; k < ncol; k++) cnt[(size_t)k + 1] += cnt[k];
+    std::vector<int32_t> order((size_t)c->B);
+    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int64_t b = 0; b < c->B; b++) order[(size_t)fill[c->brick_colour[b]]++] = (int32_t)b;
+    if (c->B > c->wave_alloc) {
+        if (!dalloc(&c->wave_br, c->B)) return fail(c, MD_ERR_HIP, "waves: out of device memory");
+        c->wave_alloc = c->B;
+    }
+    if (hipMemcpyAsync(c->wave_br, order.data(), sizeof(int32_t) * c->B, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(c, MD_ERR_HIP, "waves: copy");
+    c->ncol = ncol;
+    c->wave_off = cnt;
+    c->waves_valid = true;
+    return MD_OK;
+}
+
+// The wave kernel stages three more binary64 values (partner force sums) and
+// the sorted index per candidate: a chosen stage shrinks to fit, a stage set
+// by the caller that does not fit is an error.  Runs before the list build,
+// whose records depend on the stage capacity.
+int fit_wave_stage(md_ctx *c)
+{
+    if (stage_bytes(c->cap, 3, true, c->bd.stride) <= (size_t)c->lds_max) return MD_OK;
+    if (c->cap_user) return fail(c, MD_ERR_ARG, "wave-scheduled list: the LDS stage set with md_set_tuning is too large");
+    const int64_t fit = ((int64_t)c->lds_max - 4 * (int64_t)c->bd.stride) / (6 * 8 + 4) / 64 * 64;
+    if (fit < 64) return fail(c, MD_ERR_STATE, "wave-scheduled list: brick record leaves no LDS stage");
+    c->cap = (int32_t)fit;
+    return MD_OK;
+}
+
+// the wave launches of one force evaluation (forces accumulate into c->force,
+// which the caller has cleared)
+void launch_waves(md_ctx *c, hipStream_t s, bool mixed, ForceArgs a)
+{
+    for (int32_t k = 0; k < c->ncol; k++) {
+        const int64_t nb = c->wave_off[(size_t)k + 1] - c->wave_off[k];
+        if (nb == 0) continue;
+        a.wbr = c->wave_br + c->wave_off[k];
+        a.nwb = (int32_t)nb;
+        launch_lj_wave(s, (int)std::min<int64_t>(nb, c->max_grid()), c->threads, mixed, a);
+    }
 }
 
 // first build: count pass, then size the lists (1.25 x the longest + margin)
@@ -604,7 +674,7 @@ void md_destroy(md_ctx *c)
     dfree(c->pos[0]); dfree(c->pos[1]); dfree(c->pos_t); dfree(c->xref);
     dfree(c->vel); dfree(c->vel_t); dfree(c->force);
     dfree(c->id); dfree(c->id_t); dfree(c->cell_of); dfree(c->slot); dfree(c->perm);
-    dfree(c->count); dfree(c->start); dfree(c->nbr); dfree(c->cnt); dfree(c->rep_of); dfree(c->brec); dfree(c->bcost); dfree(c->bwork); dfree(c->tq);
+    dfree(c->count); dfree(c->start); dfree(c->nbr); dfree(c->cnt); dfree(c->rep_of); dfree(c->brec); dfree(c->bcost); dfree(c->bwork); dfree(c->tq); dfree(c->wave_br);
     dfree(c->eatom); dfree(c->watom); dfree(c->rho); dfree(c->fp); dfree(c->fpp); dfree(c->rdot);
     dfree(c->u_s); dfree(c->gx_s); dfree(c->partial); dfree(c->zeros_R);
     dfree(c->tab64); dfree(c->tab32); dfree(c->reps); dfree(c->ctl); dfree(c->one);
@@ -633,13 +703,16 @@ int md_build_cells(md_ctx *c, const double *pos, const double *boxes, double rc,
 int md_build_neighbor_list(md_ctx *c, int32_t kind, void *stream)
 {
     if (c == nullptr) return MD_ERR_ARG;
-    if (kind != MD_LIST_FULL && kind != MD_LIST_HALF) return fail(c, MD_ERR_ARG, "unknown list kind");
+    if (kind != MD_LIST_FULL && kind != MD_LIST_HALF && kind != MD_LIST_WAVES)
+        return fail(c, MD_ERR_ARG, "unknown list kind");
     if (!c->have_cells) return fail(c, MD_ERR_STATE, "md_build_cells first");
     hipStream_t s = (hipStream_t)stream;
     c->last = s;
-    const int half = kind == MD_LIST_HALF;
+    const int half = kind != MD_LIST_FULL;
     int rcode = ensure_list_capacity(c, c->pos[c->cur], half, s);
     if (rcode != MD_OK) return rcode;
+    if (kind == MD_LIST_WAVES && ((rcode = fit_wave_stage(c)) != MD_OK || (rcode = plan_waves(c, s)) != MD_OK))
+        return rcode;
     launch_build_list(s, c->grid_tasks(0, half != 0), c->threads, list_args(c, c->one, c->pos[c->cur], half));
     c->have_list = true;
     c->list_kind = kind;
@@ -657,12 +730,27 @@ int md_compute_forces(md_ctx *c, const md_potential *p, int32_t precision, doubl
     if (rcode != MD_OK) return rcode;
     if (c->list_kind == MD_LIST_HALF && (p->kind != MD_POT_LJ || c->R > 1))
         return fail(c, MD_ERR_STATE, "the half list serves LJ on one replica; build a full list");
+    if (c->list_kind == MD_LIST_WAVES && p->kind != MD_POT_LJ)
+        return fail(c, MD_ERR_STATE, "the wave-scheduled half list serves LJ; build a full list");
     hipStream_t s = (hipStream_t)stream;
     c->last = s;
     if ((rcode = stage_tables(c, p, s)) != MD_OK) return rcode;
     const bool mixed = precision == MD_MIXED;
     ForceArgs a = force_args(c, p);
     a.mode = 0;
+    if (c->list_kind == MD_LIST_WAVES) {
+        // per-atom energies summed per replica in a fixed order
+        if (energy != nullptr || virial != nullptr) {
+            a.eatom = c->eatom;
+            a.watom = c->watom;
+        }
+        launch_zero(s, c->grid_atoms(256), c->force, 3 * c->n);
+        launch_waves(c, s, mixed, a);
+        if (energy != nullptr || virial != nullptr)
+            launch_replica_sums(s, c->R, c->reps, c->eatom, c->watom, energy, virial);
+        launch_to_user(s, c->grid_atoms(256), c->n, c->id, c->force, forces);
+        return check_hip(c, "md_compute_forces");
+    }
     if (c->R == 1) {
         a.outE = energy;
         a.outW = virial;
@@ -695,16 +783,18 @@ int md_verlet_step(md_ctx *c, const md_potential *p, int32_t precision, int32_t 
     if (n_steps < 1 || !finite_pos(dt) || !finite_pos(mass)) return fail(c, MD_ERR_ARG, "need n_steps >= 1, dt > 0, mass > 0");
     if (hist != nullptr && hist_every < 1) return fail(c, MD_ERR_ARG, "hist_every must be >= 1");
     if (precision != MD_FP64 && precision != MD_MIXED) return fail(c, MD_ERR_ARG, "unknown precision");
-    if (kind != MD_LIST_FULL && kind != MD_LIST_HALF) return fail(c, MD_ERR_ARG, "unknown list kind");
+    if (kind != MD_LIST_FULL && kind != MD_LIST_HALF && kind != MD_LIST_WAVES)
+        return fail(c, MD_ERR_ARG, "unknown list kind");
     if (!c->have_cells) return fail(c, MD_ERR_STATE, "md_build_cells first (sets boxes, rc, skin)");
     int rcode = check_pot(c, p);
     if (rcode != MD_OK) return rcode;
-    if (kind == MD_LIST_HALF && p->kind != MD_POT_LJ) return fail(c, MD_ERR_STATE, "the half list serves LJ only");
+    if (kind != MD_LIST_FULL && p->kind != MD_POT_LJ) return fail(c, MD_ERR_STATE, "the half lists serve LJ only");
     hipStream_t s = (hipStream_t)stream;
     c->last = s;
     if ((rcode = stage_tables(c, p, s)) != MD_OK) return rcode;
     const bool mixed = precision == MD_MIXED;
-    const int half = kind == MD_LIST_HALF;
+    const int half = kind != MD_LIST_FULL;
+    const bool waves = kind == MD_LIST_WAVES;
     const int ga = c->grid_atoms(256);
 
     // initial state: user order -> sorted, cells and list from scratch
@@ -712,6 +802,7 @@ int md_verlet_step(md_ctx *c, const md_potential *p, int32_t precision, int32_t 
     launch_load_user(s, ga, c->n, pos, vel, c->pos[c->cur], c->vel, c->id);
     sort_into_tmp(c, c->one, true, s);
     if ((rcode = ensure_list_capacity(c, c->pos_t, half, s)) != MD_OK) return rcode;
+    if (waves && ((rcode = fit_wave_stage(c)) != MD_OK || (rcode = plan_waves(c, s)) != MD_OK)) return rcode;
     {
         ListArgs la = list_args(c, c->one, c->pos_t, half);
         la.vel_src = c->vel_t;
@@ -741,7 +832,32 @@ int md_verlet_step(md_ctx *c, const md_potential *p, int32_t precision, int32_t 
             a.outK = h + 1;
             a.outW = h + 2;
         }
-        if (p->kind == MD_POT_LJ && half) {
+        if (waves) {
+            // the wave launches, the energies of a recorded step from the
+            // per-atom sums, then the velocity-Verlet pass
+            ForceArgs f = a;
+            f.mode = 0;
+            f.force = c->force;
+            f.outE = f.outK = f.outW = nullptr;
+            f.flag_clear = nullptr;
+            f.flag_set = nullptr;
+            const bool en = mode >= 2 && a.outE != nullptr;
+            f.eatom = en ? c->eatom : nullptr;
+            f.watom = en ? c->watom : nullptr;
+            ForceArgs g = a;
+            g.outE = nullptr;
+            g.outW = nullptr;
+            g.outK = mode >= 2 ? a.outK : nullptr;
+            g.done = &c->ctl->done[2];
+            g.partial = c->partial + (size_t)c->max_grid() * 8;
+            timed(c, s, c->ev_force, [&] {
+                launch_waves(c, s, mixed, f);
+                if (en)
+                    launch_atom_sums(s, c->grid_atoms(1024), c->n, c->eatom, c->watom, a.outE, a.outW,
+                                     c->partial, &c->ctl->done[0]);
+                launch_integrate(s, ga, g);
+            });
+        } else if (p->kind == MD_POT_LJ && half) {
             ForceArgs f = a;
             f.mode = 0;
             f.force = c->force;
@@ -1011,8 +1127,21 @@ int md_query(md_ctx *c, int32_t key, int64_t *value)
         *value = t;
         return MD_OK;
     }
-    default: return fail(c, MD_ERR_ARG, "query: key 0..10");
+    case 11: *value = c->waves_valid ? c->ncol : 0; return MD_OK;
+    default: return fail(c, MD_ERR_ARG, "query: key 0..11");
     }
+}
+
+int md_get_waves(md_ctx *c, int32_t *colour, int64_t capacity, int64_t *n_bricks)
+{
+    if (c == nullptr) return MD_ERR_ARG;
+    if (!c->waves_valid) return fail(c, MD_ERR_STATE, "no wave schedule (build an MD_LIST_WAVES list)");
+    if (n_bricks != nullptr) *n_bricks = c->B;
+    if (colour != nullptr) {
+        if (capacity < c->B) return fail(c, MD_ERR_ARG, "colour array too small");
+        std::copy(c->brick_colour.begin(), c->brick_colour.end(), colour);
+    }
+    return c->ncol;
 }
 
 int md_profile(md_ctx *c, int32_t enable, double *force_ms, int64_t *force_n, double *list_ms,

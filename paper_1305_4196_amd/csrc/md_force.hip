@@ -254,6 +254,124 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_lj_half(ForceArgs a)
     finish_block(a, accE, accW, 0.0, lds);
 }
 
+// ---------------------------------------------------------------- LJ, half list in waves
+// One launch per wave of bricks whose write sets (own cells plus one layer)
+// are disjoint (the appendix's construction on the brick grid).  A task sums
+// its atoms' forces and its pairs' partner forces per halo candidate in LDS
+// (binary64 LDS atomics between the lanes of the workgroup), then adds the
+// sums to the candidates' forces in HBM with plain loads and stores: no other
+// task of the launch writes those atoms.  Candidates past the LDS stage (a
+// halo larger than the stage) are updated with global atomics, which then meet
+// no other task of the wave either.  Energy and virial are per atom (the
+// pairs an atom holds) and summed later in a fixed order.
+template <bool MIXED>
+__global__ __launch_bounds__(TASK_MAX_THREADS) void k_lj_wave(ForceArgs a)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const Stage st = stage_slice(lds_raw, a.cap, 3, true);    // extras: partner sums x, y, z
+    const double eps = a.lj[0], sig = a.lj[1];
+    const double s2 = sig * sig, e4 = 4.0 * eps, e24 = 24.0 * eps;
+    const float s2f = (float)s2, e4f = (float)e4, e24f = (float)e24;
+    const double rc2 = a.rc2;
+    const int64_t n = a.n;
+    const int32_t cap = a.cap;
+    double *sx = st.ex, *sy = st.ex + cap, *sz = st.ex + 2 * (size_t)cap;
+    for (int32_t t = blockIdx.x; t < a.nwb; t += gridDim.x) {
+        const int64_t b = a.wbr[t];
+        const int32_t *grec = a.brec + b * (int64_t)a.bd.stride;
+        const int32_t natoms = grec[BR_ATOMS];
+        if (natoms == 0) continue;
+        __syncthreads();
+        brick_load(st, a.bd, grec, a.reps, a.pos, nullptr, nullptr);
+        const int32_t total = st.rec[BR_TOTAL];
+        const int32_t lim = total < cap ? total : cap;
+        for (int32_t k = threadIdx.x; k < lim; k += blockDim.x) {
+            sx[k] = 0.0;
+            sy[k] = 0.0;
+            sz[k] = 0.0;
+        }
+        __syncthreads();
+        const bool all_staged = total <= cap;
+        const bool has_img = st.rec[BR_SHIFT] == 0;
+        const RepDesc &rep = a.reps[st.rec[BR_REP]];
+        const double Lx = rep.L[0], Ly = rep.L[1], Lz = rep.L[2];
+        const BrickGeom g = brick_geom(a.reps, a.R, b);
+        const int32_t *soff = st.rec + br_soff(a.bd), *aoff = st.rec + br_aoff(a.bd);
+        auto add_to = [&](int32_t k, double fx, double fy, double fz) {
+            if (k < cap) {
+                atomicAdd(&sx[k], fx);
+                atomicAdd(&sy[k], fy);
+                atomicAdd(&sz[k], fz);
+            } else {
+                const int32_t j = candidate_index(st, a.bd, k);
+                atomicAdd(&a.force[j], fx);
+                atomicAdd(&a.force[n + j], fy);
+                atomicAdd(&a.force[2 * n + j], fz);
+            }
+        };
+        for (int32_t a0 = 0; a0 < natoms; a0 += (int32_t)blockDim.x) {
+            const int32_t la = a0 + (int32_t)threadIdx.x;
+            const bool valid = la < natoms;
+            int32_t e = 0;
+            const int64_t i = valid ? brick_atom(st, a.bd, la, &e) : 0;
+            const int32_t mm = valid ? min(a.cnt[i], a.M) : 0;
+            double fx = 0.0, fy = 0.0, fz = 0.0, en = 0.0, w = 0.0;
+            const double4 xi = a.pos[i];
+            STAGE_IMG_SPLIT(all_staged, has_img,
+                walk_list<STAGED, IMG>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
+                    [&](bool ok, int32_t k, double dx, double dy, double dz, double r2) {
+                        const bool in = ok && r2 < rc2;
+                        double fs, V;
+                        lj_pair<MIXED>(in, r2, s2, e4, e24, s2f, e4f, e24f, fs, V);
+                        const double px = fs * dx, py = fs * dy, pz = fs * dz;
+                        fx += px;
+                        fy += py;
+                        fz += pz;
+                        if (in) add_to(k, -px, -py, -pz);
+                        en += V;
+                        w += fs * r2;
+                    });
+            )
+            if (valid) {
+                // the atom's own candidate slot: its cell's first candidate plus its rank in the cell
+                const int32_t lc0 = e % g.e[0], lc1 = (e / g.e[0]) % g.e[1], lc2 = e / (g.e[0] * g.e[1]);
+                const int32_t hown = (lc0 + 1) % g.nc[0] + g.hn[0] * ((lc1 + 1) % g.nc[1] + g.hn[1] * ((lc2 + 1) % g.nc[2]));
+                add_to(soff[hown] + (la - aoff[e]), fx, fy, fz);
+                if (a.eatom != nullptr) {
+                    a.eatom[i] = en;
+                    a.watom[i] = w;
+                }
+            }
+        }
+        __syncthreads();
+        for (int32_t k = threadIdx.x; k < lim; k += blockDim.x) {
+            const int32_t j = st.j[k];
+            a.force[j] += sx[k];
+            a.force[n + j] += sy[k];
+            a.force[2 * n + j] += sz[k];
+        }
+    }
+}
+
+// E and W summed over all atoms: per-workgroup partials over fixed strided
+// ranges, added in workgroup order by the last workgroup (fixed grid, so the
+// sums are bitwise repeatable)
+__global__ __launch_bounds__(256) void k_atom_sums(int64_t n, const double *__restrict__ eatom,
+                                                   const double *__restrict__ watom, double *energy,
+                                                   double *virial, double *partial, uint32_t *done)
+{
+    __shared__ double lds[4 * 256 / 64];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        v[0] += eatom[i];
+        v[1] += watom[i];
+    }
+    if (mdred::last_block_sum4(v, partial, done, lds) && threadIdx.x == 0) {
+        if (energy) *energy = v[0];
+        if (virial) *virial = v[1];
+    }
+}
+
 // velocity-Verlet pieces for forces already in a.force (half-list path); the
 // consumed forces are cleared for the next atomic accumulation
 __global__ __launch_bounds__(256) void k_integrate(ForceArgs a)
@@ -501,6 +619,17 @@ void launch_eam_density(hipStream_t s, int grid, int threads, bool mixed, const 
 void launch_eam_force(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a)
 {
     MD_LAUNCH_TASKS(k_eam_force, 1, false)
+}
+
+void launch_lj_wave(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a)
+{
+    MD_LAUNCH_TASKS(k_lj_wave, 3, true)
+}
+
+void launch_atom_sums(hipStream_t s, int grid, int64_t n, const double *eatom, const double *watom,
+                      double *energy, double *virial, double *partial, uint32_t *done)
+{
+    hipLaunchKernelGGL(k_atom_sums, dim3(grid), dim3(256), 0, s, n, eatom, watom, energy, virial, partial, done);
 }
 
 void launch_integrate(hipStream_t s, int grid, const ForceArgs &a)

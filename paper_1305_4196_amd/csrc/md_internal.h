@@ -171,9 +171,15 @@ struct ForceArgs {
     double *eatom;            // per-atom energy (multi-replica outputs), or null
     double *watom;            // per-atom virial, or null
     DevCtl *ctl;
+    // waves of bricks (half list without global atomics)
+    const int32_t *wbr;       // the bricks of this launch's wave
+    int32_t nwb;
 };
 void launch_lj_full(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a);
 void launch_lj_half(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a);
+void launch_lj_wave(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a);
+void launch_atom_sums(hipStream_t s, int grid, int64_t n, const double *eatom, const double *watom,
+                      double *energy, double *virial, double *partial, uint32_t *done);
 void launch_eam_density(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a);
 void launch_eam_force(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a);
 void launch_integrate(hipStream_t s, int grid, const ForceArgs &a);
