@@ -438,8 +438,12 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_density(ForceArgs a)
 }
 
 // ---------------------------------------------------------------- EAM pass 2: forces
-template <bool MIXED>
-__global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_force(ForceArgs a)
+// EN: the launch returns energy or virial (steps that record no energy skip
+// their per-pair terms).  At most 128 VGPRs, so that two 512-thread
+// workgroups share a CU (the few spills this costs are per atom, outside the
+// pair loop).
+template <bool MIXED, bool EN>
+__global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_eam_force(ForceArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ double lds[4 * TASK_MAX_THREADS / 64];
@@ -459,15 +463,17 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_force(ForceArgs a)
                     const bool in_phi = ok && r2 < rphi2, in_rho = ok && r2 < rrho2;
                     const double fpj = (STAGED || k < st.cap) ? st.ex[k] : a.fp[candidate_index(st, a.bd, k)];
                     const double r = sqrt(r2);
-                    const double ir = rcp64(r);
-                    double gsc, ep;
+                    double gsc, grr, ep;
                     if (MIXED) {
+                        // pair scalar in binary32: dV/dr / r with the binary32 reciprocal
                         float f, fu, g, h;
                         spl32(a.tabf[0], (r - x0p) * ihp, nkp, f, fu);
                         spl32(a.tabf[1], (r - x0r) * ihr, nkr, g, h);
                         const float gp = in_phi ? fu * (float)ihp : 0.0f;
                         const float gr = in_rho ? (float)(fpi + fpj) * h * (float)ihr : 0.0f;
-                        gsc = (double)(gp + gr);
+                        const float gsf = gp + gr;
+                        gsc = (double)gsf;
+                        grr = (double)(gsf * __builtin_amdgcn_rcpf((float)r));
                         ep = in_phi ? (double)f : 0.0;
                     } else {
                         double f, fu, g, h;
@@ -476,14 +482,16 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_force(ForceArgs a)
                         const double gp = in_phi ? fu * ihp : 0.0;
                         const double gr = in_rho ? (fpi + fpj) * (h * ihr) : 0.0;
                         gsc = gp + gr;
+                        grr = (in_phi || in_rho) ? gsc * rcp64(r) : 0.0;
                         ep = in_phi ? f : 0.0;
                     }
-                    const double grr = (in_phi || in_rho) ? gsc * ir : 0.0;
                     fx = fma(-grr, dx, fx);
                     fy = fma(-grr, dy, fy);
                     fz = fma(-grr, dz, fz);
-                    e += ep;
-                    w -= (in_phi || in_rho) ? gsc * r : 0.0;
+                    if (EN) {
+                        e += ep;
+                        w -= (in_phi || in_rho) ? gsc * r : 0.0;
+                    }
                 });
         )
         if (valid) {
@@ -618,7 +626,19 @@ void launch_eam_density(hipStream_t s, int grid, int threads, bool mixed, const 
 
 void launch_eam_force(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a)
 {
-    MD_LAUNCH_TASKS(k_eam_force, 1, false)
+    const size_t lds = stage_bytes(a.cap, 1, false, a.bd.stride);
+    const bool en = a.outE != nullptr || a.outW != nullptr || a.eatom != nullptr;
+    auto go = [&](auto kernel) {
+        allow_lds(kernel, lds);
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), lds, s, a);
+    };
+    if (mixed) {
+        if (en) go(k_eam_force<true, true>);
+        else go(k_eam_force<true, false>);
+    } else {
+        if (en) go(k_eam_force<false, true>);
+        else go(k_eam_force<false, false>);
+    }
 }
 
 void launch_lj_wave(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a)
