@@ -86,9 +86,10 @@ def main():
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
     ap.add_argument("--thermo", type=int, default=100,
                     help="record E_pot, KE, W every this many steps (and after the last)")
-    ap.add_argument("--list", choices=["full", "half", "waves"], default="full",
+    ap.add_argument("--list", choices=["full", "half", "waves", "deps"], default="full",
                     help="full list (each atom written by its own lane), Newton-3 half list with atomics, "
-                         "or the half list run in waves of non-overlapping brick tasks")
+                         "the half list run in waves of non-overlapping brick tasks, "
+                         "or the same tasks in dependence order in one persistent launch")
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None,
                     help="time one path only (for profiler runs)")
     ap.add_argument("--workload", default="lj_fcc_1048576",
@@ -137,7 +138,8 @@ def main():
     nreb = torch.zeros(1, dtype=torch.int32, device="cuda")
 
     results = {}
-    kind = {"full": B.MD_LIST_FULL, "half": B.MD_LIST_HALF, "waves": B.MD_LIST_WAVES}[args.list]
+    kind = {"full": B.MD_LIST_FULL, "half": B.MD_LIST_HALF, "waves": B.MD_LIST_WAVES,
+            "deps": B.MD_LIST_DEPS}[args.list]
     paths = [("mixed", B.MD_MIXED), ("fp64", B.MD_FP64)]
     if args.only:
         paths = [p for p in paths if p[0] == args.only]

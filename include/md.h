@@ -46,7 +46,8 @@ typedef enum {
     MD_ERR_CAPACITY = -3,   /* neighbor list overflowed its per-atom capacity (see md_get_status) */
     MD_ERR_NONFINITE = -4,  /* a force or position became NaN/Inf on the device */
     MD_ERR_HIP = -5,        /* a HIP runtime call failed */
-    MD_ERR_STATE = -6       /* call out of order (e.g. forces before cells/list) */
+    MD_ERR_STATE = -6,      /* call out of order (e.g. forces before cells/list) */
+    MD_ERR_TIMEOUT = -7     /* a task of the dependent schedule waited past its limit (see md_get_status) */
 } md_status;
 
 typedef enum { MD_FP64 = 0, MD_MIXED = 1 } md_precision;
@@ -55,7 +56,7 @@ typedef enum { MD_FP64 = 0, MD_MIXED = 1 } md_precision;
  *           pair arithmetic (potential, force magnitude, tables) in binary32;
  *           per-atom accumulation, integration and global sums in binary64. */
 
-typedef enum { MD_LIST_FULL = 0, MD_LIST_HALF = 1, MD_LIST_WAVES = 2 } md_list_kind;
+typedef enum { MD_LIST_FULL = 0, MD_LIST_HALF = 1, MD_LIST_WAVES = 2, MD_LIST_DEPS = 3 } md_list_kind;
 /* MD_LIST_FULL: every pair is stored with both atoms; each atom's force is
  *               written only by the worker that owns the atom (no atomics).
  * MD_LIST_HALF: Newton-3 list, each pair once (Sec. II.D.3), held by the atom
@@ -68,7 +69,16 @@ typedef enum { MD_LIST_FULL = 0, MD_LIST_HALF = 1, MD_LIST_WAVES = 2 } md_list_k
  *               sums partner forces in on-chip memory and adds them to the
  *               partners with plain stores: no global atomics while the halo
  *               fits the LDS stage.  LJ only; the order of the on-chip sums
- *               is not deterministic. */
+ *               is not deterministic.
+ * MD_LIST_DEPS: the same tasks in one persistent launch that runs them in
+ *               dependence order instead of wave by wave (Sec. II.B): a task
+ *               starts as soon as the last earlier task, in wave order, that
+ *               writes each of its cells has finished (its direct
+ *               predecessors, found by the backward method).  Workgroups take
+ *               ready tasks from a device queue; finished tasks count their
+ *               successors down.  Each wait for a ready task is bounded
+ *               (md_set_tuning key 5); past the bound the launch ends early
+ *               and md_get_status reports MD_ERR_TIMEOUT.  LJ only. */
 
 typedef enum { MD_POT_LJ = 0, MD_POT_EAM = 1 } md_pot_kind;
 
@@ -174,9 +184,11 @@ int md_force_vjp(md_ctx *ctx, const md_potential *pot, int32_t precision, const 
                  double *g_params, void *stream);
 
 /* Device status (synchronises the context's last stream).  device_flags
- * [host]: bit 0 list overflow, bit 1 non-finite force; cleared after reading.
+ * [host]: bit 0 list overflow, bit 1 non-finite force, bit 2 a dependent-
+ * schedule wait past its limit; cleared after reading.
  * required_capacity [host]: per-atom list capacity now allocated or required.
- * Returns MD_ERR_CAPACITY / MD_ERR_NONFINITE if the flag is set, else MD_OK. */
+ * Returns MD_ERR_CAPACITY / MD_ERR_NONFINITE / MD_ERR_TIMEOUT if the flag is
+ * set, else MD_OK. */
 int md_get_status(md_ctx *ctx, int32_t *device_flags, int64_t *required_capacity);
 
 /* Export the current neighbor list as CSR over user indices (for checking).
@@ -198,6 +210,14 @@ int md_get_cells(md_ctx *ctx, int32_t *cell_start, int32_t *order, int64_t *n_ce
  * MD_ERR_ARG (capacity too small). */
 int md_get_waves(md_ctx *ctx, int32_t *colour, int64_t capacity, int64_t *n_bricks);
 
+/* The task graph of the last MD_LIST_DEPS build (for checking) [host], tasks
+ * numbered as the bricks of md_get_waves: succ_off (n_bricks + 1 int32 out,
+ * may be NULL) and succ (capacity int32 out, may be NULL): the direct
+ * successors of task t are succ[succ_off[t] .. succ_off[t+1]), ascending.
+ * Returns the number of edges, or MD_ERR_STATE (no graph), MD_ERR_ARG
+ * (capacity too small). */
+int64_t md_get_task_graph(md_ctx *ctx, int32_t *succ_off, int32_t *succ, int64_t capacity);
+
 /* Tuning knobs (used by the autotuner).  The kernels run one workgroup per
  * brick of bx x by x bz cells (the cell-task blocking of Sec. II.D.2).
  * key 0 = candidates staged in LDS per brick task (64..4096, a multiple of 64,
@@ -212,7 +232,10 @@ int md_get_waves(md_ctx *ctx, int32_t *colour, int64_t capacity, int64_t *n_bric
  *   cells, (bx+2)(by+2)(bz+2) <= 512), or 0 to choose it from the mean
  *   occupancy of the non-empty cells; drops the current list;
  * key 4 = threads per brick task (128..512, a multiple of 64), or 0 to choose
- *   them with the shape; drops the current list.
+ *   them with the shape; drops the current list;
+ * key 5 = longest wait of a dependent-schedule workgroup for a ready task, in
+ *   microseconds (default 2,000,000; 0 ends a launch at the first wait, the
+ *   way the failure path is tested).
  * Returns MD_OK or MD_ERR_ARG. */
 int md_set_tuning(md_ctx *ctx, int32_t key, int32_t value);
 
@@ -222,7 +245,8 @@ int md_set_tuning(md_ctx *ctx, int32_t key, int32_t value);
  * (candidates) and 7 largest brick (atoms) seen by the list builds since the
  * sizing pass (both synchronise), 8 LDS bytes a workgroup may use, 9 workgroups
  * of the LJ force grid, 10 entries of the current list (synchronises), 11
- * waves of the current wave schedule (0 if none).
+ * waves of the current wave schedule (0 if none), 12 edges of the current
+ * task graph (0 if none).
  * Returns MD_OK, MD_ERR_ARG, MD_ERR_STATE (key 10 without a list) or MD_ERR_HIP. */
 int md_query(md_ctx *ctx, int32_t key, int64_t *value);
 

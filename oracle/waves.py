@@ -18,6 +18,14 @@ position once per pass (the reading of the appendix used here; the appendix's
 figure of the sixth wave of the 14 x 6 example is garbled, the text's rule --
 further steps of s along the walk -- is followed).
 
+Dependent schedule (Sec. II.B): instead of a barrier after every wave, a task
+waits only for its direct predecessors -- for each cell it writes, the last
+earlier task (in wave order) that writes the same cell.  Two ways to find them,
+both as the paper describes: the forward method keeps, per cell, the last task
+seen so far while walking the tasks first to last (predecessor lists); the
+backward method keeps, per cell, the next task while walking last to first
+(successor lists).
+
 Brick colouring (this design's GPU tasks are bricks of cells): a brick writes
 the cells of its halo (its cells and one layer around them, the same
 coordinates the brick record uses); two bricks may share a wave only if their
@@ -148,3 +156,55 @@ def brick_colours(nc: Sequence[int], bshape: Sequence[int]) -> Tuple[List[int], 
         for (x, y, z) in cells:
             colour[x + nb[0] * (y + nb[1] * z)] = w
     return colour, len(ws)
+
+
+# ---------------------------------------------------------------- dependences
+def brick_write_cells(nc: Sequence[int], bshape: Sequence[int], b: int) -> List[Tuple[int, int, int]]:
+    """Cells (x, y, z) written by brick b (numbered x fastest) of a grid nc cut into bshape bricks."""
+    nb = [len(brick_ranges(nc[d], bshape[d])) for d in range(3)]
+    idx = (b % nb[0], (b // nb[0]) % nb[1], b // (nb[0] * nb[1]))
+    sets = []
+    for d in range(3):
+        o, e = brick_ranges(nc[d], bshape[d])[idx[d]]
+        sets.append(sorted(write_set(o, e, nc[d])))
+    return [(x, y, z) for z in sets[2] for y in sets[1] for x in sets[0]]
+
+
+def wave_order(colour: Sequence[int]) -> List[int]:
+    """Tasks wave by wave, by index within a wave."""
+    return sorted(range(len(colour)), key=lambda t: (colour[t], t))
+
+
+def predecessors_forward(order: Sequence[int], cells) -> dict:
+    """Forward method: {task: set of direct predecessors}."""
+    last = {}
+    pred = {}
+    for t in order:
+        pred[t] = set()
+        for c in cells(t):
+            if c in last:
+                pred[t].add(last[c])
+            last[c] = t
+    return pred
+
+
+def successors_backward(order: Sequence[int], cells) -> dict:
+    """Backward method: {task: set of direct successors}."""
+    nxt = {}
+    succ = {}
+    for t in reversed(order):
+        succ[t] = set()
+        for c in cells(t):
+            if c in nxt:
+                succ[t].add(nxt[c])
+            nxt[c] = t
+    return succ
+
+
+def brick_task_graph(nc: Sequence[int], bshape: Sequence[int]) -> Tuple[dict, List[int]]:
+    """Successor sets of the bricks of one grid (backward method over the wave
+    order of brick_colours) and that order."""
+    colour, _ = brick_colours(nc, bshape)
+    order = wave_order(colour)
+    succ = successors_backward(order, lambda t: brick_write_cells(nc, bshape, t))
+    return succ, order

@@ -16,16 +16,16 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmd.so")
 
-MD_OK, MD_ERR_ARG, MD_ERR_BOX, MD_ERR_CAPACITY, MD_ERR_NONFINITE, MD_ERR_HIP, MD_ERR_STATE = \
-    0, -1, -2, -3, -4, -5, -6
+MD_OK, MD_ERR_ARG, MD_ERR_BOX, MD_ERR_CAPACITY, MD_ERR_NONFINITE, MD_ERR_HIP, MD_ERR_STATE, MD_ERR_TIMEOUT = \
+    0, -1, -2, -3, -4, -5, -6, -7
 MD_FP64, MD_MIXED = 0, 1
-MD_LIST_FULL, MD_LIST_HALF, MD_LIST_WAVES = 0, 1, 2
+MD_LIST_FULL, MD_LIST_HALF, MD_LIST_WAVES, MD_LIST_DEPS = 0, 1, 2, 3
 MD_POT_LJ, MD_POT_EAM = 0, 1
-FLAG_OVERFLOW, FLAG_NONFINITE = 1, 2
+FLAG_OVERFLOW, FLAG_NONFINITE, FLAG_SCHEDULE = 1, 2, 4
 
 EXPORTS = ["md_create", "md_destroy", "md_build_cells", "md_build_neighbor_list",
            "md_compute_forces", "md_verlet_step", "md_force_vjp", "md_get_status",
-           "md_get_neighbor_list", "md_get_cells", "md_get_waves", "md_set_tuning", "md_query", "md_profile",
+           "md_get_neighbor_list", "md_get_cells", "md_get_waves", "md_get_task_graph", "md_set_tuning", "md_query", "md_profile",
            "md_last_error"]
 
 
@@ -72,6 +72,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     L.md_get_neighbor_list.restype = i64
     L.md_get_cells.argtypes = [vp, P(i32), P(i32), P(i64)]
     L.md_get_waves.argtypes = [vp, P(i32), i64, P(i64)]
+    L.md_get_task_graph.argtypes = [vp, P(i32), P(i32), i64]
+    L.md_get_task_graph.restype = i64
     L.md_set_tuning.argtypes = [vp, i32, i32]
     L.md_query.argtypes = [vp, i32, P(i64)]
     L.md_profile.argtypes = [vp, i32, P(d), P(i64), P(d), P(i64)]
@@ -251,6 +253,20 @@ def md_get_waves(ctx: Context) -> Tuple[np.ndarray, int]:
     nw = L.md_get_waves(ctx.h, col.ctypes.data_as(C.POINTER(C.c_int32)), nb.value, None)
     _check(ctx.h, min(0, nw))
     return col, int(nw)
+
+
+def md_get_task_graph(ctx: Context) -> Tuple[np.ndarray, np.ndarray]:
+    """(succ_off[B+1], succ[E]) of the current dependent schedule."""
+    L = load()
+    ne = L.md_get_task_graph(ctx.h, None, None, 0)
+    _check(ctx.h, int(min(0, ne)))
+    nb = C.c_int64()
+    _check(ctx.h, min(0, L.md_get_waves(ctx.h, None, 0, C.byref(nb))))
+    off = np.zeros(nb.value + 1, dtype=np.int32)
+    succ = np.zeros(max(int(ne), 1), dtype=np.int32)
+    P = C.POINTER(C.c_int32)
+    _check(ctx.h, int(min(0, L.md_get_task_graph(ctx.h, off.ctypes.data_as(P), succ.ctypes.data_as(P), int(ne)))))
+    return off, succ[:int(ne)]
 
 
 def md_set_tuning(ctx: Context, key: int, value: int):

@@ -113,6 +113,16 @@ struct md_ctx {
     std::vector<int32_t> brick_colour;    // [B] colour of each brick (host copy)
     int32_t *wave_br = nullptr;           // [B] bricks ordered by colour, then index
     int64_t wave_alloc = 0;
+    std::vector<int32_t> wave_order;      // host copy of wave_br
+    // the same tasks in dependence order (MD_LIST_DEPS): the task graph of the wave order
+    bool deps_valid = false;
+    std::vector<int32_t> dag_off_h, dag_succ_h, dag_npred_h;
+    int32_t *dag_off = nullptr, *dag_succ = nullptr, *dag_npred = nullptr, *dag_init = nullptr;
+    int32_t *dag_ref = nullptr, *dag_queue = nullptr;
+    int64_t dag_alloc_t = 0, dag_alloc_e = 0;
+    int32_t dag_roots = 0;
+    int64_t wait_us = 2000000;            // longest wait for a queue slot (microseconds)
+    int64_t wall_khz = 100000;            // device wall clock (kHz)
 
     // atoms (cell-sorted)
     double4 *pos[2] = {nullptr, nullptr};
@@ -387,6 +397,7 @@ int plan_bricks(md_ctx *c, hipStream_t s)
         return fail(c, MD_ERR_HIP, "replica descriptors: copy");
     c->bricks_valid = true;
     c->waves_valid = false;
+    c->deps_valid = false;
     return MD_OK;
 }
 
@@ -420,7 +431,65 @@ int plan_waves(md_ctx *c, hipStream_t s)
         return fail(c, MD_ERR_HIP, "waves: copy");
     c->ncol = ncol;
     c->wave_off = cnt;
+    c->wave_order = order;
     c->waves_valid = true;
+    c->deps_valid = false;
+    return MD_OK;
+}
+
+// Task graph of the wave order (md_waves.h, backward method) for the
+// dependent schedule; a brick's write set is its halo cells.
+int plan_deps(md_ctx *c, hipStream_t s)
+{
+    int rc = plan_waves(c, s);
+    if (rc != MD_OK) return rc;
+    if (c->deps_valid) return MD_OK;
+    const int64_t T = c->B;
+    int64_t cells_total = 0;
+    for (int32_t r = 0; r < c->R; r++) {
+        const RepDesc &d = c->reps_h[r];
+        cells_total = std::max<int64_t>(cells_total, d.cell_off + (int64_t)d.nc[0] * d.nc[1] * d.nc[2]);
+    }
+    std::vector<int> ax[3];
+    auto cells = [&](int32_t b, std::vector<int64_t> &out) {
+        int32_t r = 0;
+        while (r + 1 < c->R && c->reps_h[r + 1].brick_off <= b) r++;
+        const RepDesc &d = c->reps_h[r];
+        int64_t lb = b - d.brick_off;
+        const int bi[3] = {(int)(lb % d.nb[0]), (int)(lb / d.nb[0] % d.nb[1]), (int)(lb / ((int64_t)d.nb[0] * d.nb[1]))};
+        for (int k = 0; k < 3; k++) {
+            const int o = bi[k] * d.bd[k];
+            mdwaves::axis_write_set(o, std::min(d.bd[k], d.nc[k] - o), d.nc[k], ax[k]);
+        }
+        for (int z : ax[2])
+            for (int y : ax[1])
+                for (int x : ax[0]) out.push_back(d.cell_off + x + (int64_t)d.nc[0] * (y + (int64_t)d.nc[1] * z));
+    };
+    mdwaves::task_graph(c->wave_order, cells, cells_total, T, c->dag_off_h, c->dag_succ_h, c->dag_npred_h);
+    std::vector<int32_t> init((size_t)T, -1);
+    int32_t nroots = 0;
+    for (int32_t t : c->wave_order)
+        if (c->dag_npred_h[(size_t)t] == 0) init[(size_t)nroots++] = t;
+    const int64_t E = (int64_t)c->dag_succ_h.size();
+    bool ok = true;
+    if (T > c->dag_alloc_t) {
+        ok &= dalloc(&c->dag_off, (size_t)T + 1) && dalloc(&c->dag_npred, (size_t)T) && dalloc(&c->dag_init, (size_t)T) &&
+              dalloc(&c->dag_ref, (size_t)T) && dalloc(&c->dag_queue, (size_t)T);
+        c->dag_alloc_t = ok ? T : 0;
+    }
+    if (ok && E > c->dag_alloc_e) {
+        ok &= dalloc(&c->dag_succ, (size_t)E);
+        c->dag_alloc_e = ok ? E : 0;
+    }
+    if (!ok) return fail(c, MD_ERR_HIP, "dependent schedule: out of device memory");
+    if (hipMemcpyAsync(c->dag_off, c->dag_off_h.data(), sizeof(int32_t) * (T + 1), hipMemcpyHostToDevice, s) != hipSuccess ||
+        (E > 0 && hipMemcpyAsync(c->dag_succ, c->dag_succ_h.data(), sizeof(int32_t) * E, hipMemcpyHostToDevice, s) != hipSuccess) ||
+        hipMemcpyAsync(c->dag_npred, c->dag_npred_h.data(), sizeof(int32_t) * T, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(c->dag_init, init.data(), sizeof(int32_t) * T, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(c, MD_ERR_HIP, "dependent schedule: copy");
+    c->dag_roots = nroots;
+    c->deps_valid = true;
     return MD_OK;
 }
 
@@ -430,9 +499,11 @@ int plan_waves(md_ctx *c, hipStream_t s)
 // whose records depend on the stage capacity.
 int fit_wave_stage(md_ctx *c)
 {
-    if (stage_bytes(c->cap, 3, true, c->bd.stride) <= (size_t)c->lds_max) return MD_OK;
+    // 256 bytes stay free for the kernels' static LDS
+    const int64_t room = (int64_t)c->lds_max - 256;
+    if ((int64_t)stage_bytes(c->cap, 3, true, c->bd.stride) <= room) return MD_OK;
     if (c->cap_user) return fail(c, MD_ERR_ARG, "wave-scheduled list: the LDS stage set with md_set_tuning is too large");
-    const int64_t fit = ((int64_t)c->lds_max - 4 * (int64_t)c->bd.stride) / (6 * 8 + 4) / 64 * 64;
+    const int64_t fit = (room - 4 * (int64_t)c->bd.stride) / (6 * 8 + 4) / 64 * 64;
     if (fit < 64) return fail(c, MD_ERR_STATE, "wave-scheduled list: brick record leaves no LDS stage");
     c->cap = (int32_t)fit;
     return MD_OK;
@@ -442,6 +513,18 @@ int fit_wave_stage(md_ctx *c)
 // which the caller has cleared)
 void launch_waves(md_ctx *c, hipStream_t s, bool mixed, ForceArgs a)
 {
+    if (c->list_kind == MD_LIST_DEPS) {
+        DepArgs d{};
+        d.off = c->dag_off;
+        d.succ = c->dag_succ;
+        d.ref = c->dag_ref;
+        d.queue = c->dag_queue;
+        d.sched = c->ctl->sched;
+        d.T = (int32_t)c->B;
+        d.limit = (uint64_t)(c->wait_us * c->wall_khz / 1000);
+        launch_lj_deps(s, c->grid_tasks(3, true), c->threads, mixed, a, d, c->dag_npred, c->dag_init, c->dag_roots);
+        return;
+    }
     for (int32_t k = 0; k < c->ncol; k++) {
         const int64_t nb = c->wave_off[(size_t)k + 1] - c->wave_off[k];
         if (nb == 0) continue;
@@ -633,6 +716,9 @@ int md_create(md_ctx **out, int64_t n, int32_t R, const int64_t *off)
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) == hipSuccess &&
         lds > 0)
         c->lds_max = lds;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device) == hipSuccess && khz > 0)
+        c->wall_khz = khz;
     bool ok = true;
     ok &= dalloc(&c->pos[0], n) && dalloc(&c->pos[1], n) && dalloc(&c->pos_t, n) && dalloc(&c->xref, n);
     ok &= dalloc(&c->vel, 3 * n) && dalloc(&c->vel_t, 3 * n) && dalloc(&c->force, 3 * n);
@@ -675,6 +761,7 @@ void md_destroy(md_ctx *c)
     dfree(c->vel); dfree(c->vel_t); dfree(c->force);
     dfree(c->id); dfree(c->id_t); dfree(c->cell_of); dfree(c->slot); dfree(c->perm);
     dfree(c->count); dfree(c->start); dfree(c->nbr); dfree(c->cnt); dfree(c->rep_of); dfree(c->brec); dfree(c->bcost); dfree(c->bwork); dfree(c->tq); dfree(c->wave_br);
+    dfree(c->dag_off); dfree(c->dag_succ); dfree(c->dag_npred); dfree(c->dag_init); dfree(c->dag_ref); dfree(c->dag_queue);
     dfree(c->eatom); dfree(c->watom); dfree(c->rho); dfree(c->fp); dfree(c->fpp); dfree(c->rdot);
     dfree(c->u_s); dfree(c->gx_s); dfree(c->partial); dfree(c->zeros_R);
     dfree(c->tab64); dfree(c->tab32); dfree(c->reps); dfree(c->ctl); dfree(c->one);
@@ -703,7 +790,7 @@ int md_build_cells(md_ctx *c, const double *pos, const double *boxes, double rc,
 int md_build_neighbor_list(md_ctx *c, int32_t kind, void *stream)
 {
     if (c == nullptr) return MD_ERR_ARG;
-    if (kind != MD_LIST_FULL && kind != MD_LIST_HALF && kind != MD_LIST_WAVES)
+    if (kind != MD_LIST_FULL && kind != MD_LIST_HALF && kind != MD_LIST_WAVES && kind != MD_LIST_DEPS)
         return fail(c, MD_ERR_ARG, "unknown list kind");
     if (!c->have_cells) return fail(c, MD_ERR_STATE, "md_build_cells first");
     hipStream_t s = (hipStream_t)stream;
@@ -712,6 +799,8 @@ int md_build_neighbor_list(md_ctx *c, int32_t kind, void *stream)
     int rcode = ensure_list_capacity(c, c->pos[c->cur], half, s);
     if (rcode != MD_OK) return rcode;
     if (kind == MD_LIST_WAVES && ((rcode = fit_wave_stage(c)) != MD_OK || (rcode = plan_waves(c, s)) != MD_OK))
+        return rcode;
+    if (kind == MD_LIST_DEPS && ((rcode = fit_wave_stage(c)) != MD_OK || (rcode = plan_deps(c, s)) != MD_OK))
         return rcode;
     launch_build_list(s, c->grid_tasks(0, half != 0), c->threads, list_args(c, c->one, c->pos[c->cur], half));
     c->have_list = true;
@@ -730,15 +819,16 @@ int md_compute_forces(md_ctx *c, const md_potential *p, int32_t precision, doubl
     if (rcode != MD_OK) return rcode;
     if (c->list_kind == MD_LIST_HALF && (p->kind != MD_POT_LJ || c->R > 1))
         return fail(c, MD_ERR_STATE, "the half list serves LJ on one replica; build a full list");
-    if (c->list_kind == MD_LIST_WAVES && p->kind != MD_POT_LJ)
-        return fail(c, MD_ERR_STATE, "the wave-scheduled half list serves LJ; build a full list");
+    const bool scheduled = c->list_kind == MD_LIST_WAVES || c->list_kind == MD_LIST_DEPS;
+    if (scheduled && p->kind != MD_POT_LJ)
+        return fail(c, MD_ERR_STATE, "the scheduled half lists serve LJ; build a full list");
     hipStream_t s = (hipStream_t)stream;
     c->last = s;
     if ((rcode = stage_tables(c, p, s)) != MD_OK) return rcode;
     const bool mixed = precision == MD_MIXED;
     ForceArgs a = force_args(c, p);
     a.mode = 0;
-    if (c->list_kind == MD_LIST_WAVES) {
+    if (scheduled) {
         // per-atom energies summed per replica in a fixed order
         if (energy != nullptr || virial != nullptr) {
             a.eatom = c->eatom;
@@ -783,7 +873,7 @@ int md_verlet_step(md_ctx *c, const md_potential *p, int32_t precision, int32_t 
     if (n_steps < 1 || !finite_pos(dt) || !finite_pos(mass)) return fail(c, MD_ERR_ARG, "need n_steps >= 1, dt > 0, mass > 0");
     if (hist != nullptr && hist_every < 1) return fail(c, MD_ERR_ARG, "hist_every must be >= 1");
     if (precision != MD_FP64 && precision != MD_MIXED) return fail(c, MD_ERR_ARG, "unknown precision");
-    if (kind != MD_LIST_FULL && kind != MD_LIST_HALF && kind != MD_LIST_WAVES)
+    if (kind != MD_LIST_FULL && kind != MD_LIST_HALF && kind != MD_LIST_WAVES && kind != MD_LIST_DEPS)
         return fail(c, MD_ERR_ARG, "unknown list kind");
     if (!c->have_cells) return fail(c, MD_ERR_STATE, "md_build_cells first (sets boxes, rc, skin)");
     int rcode = check_pot(c, p);
@@ -794,7 +884,7 @@ int md_verlet_step(md_ctx *c, const md_potential *p, int32_t precision, int32_t 
     if ((rcode = stage_tables(c, p, s)) != MD_OK) return rcode;
     const bool mixed = precision == MD_MIXED;
     const int half = kind != MD_LIST_FULL;
-    const bool waves = kind == MD_LIST_WAVES;
+    const bool waves = kind == MD_LIST_WAVES || kind == MD_LIST_DEPS;
     const int ga = c->grid_atoms(256);
 
     // initial state: user order -> sorted, cells and list from scratch
@@ -802,7 +892,9 @@ int md_verlet_step(md_ctx *c, const md_potential *p, int32_t precision, int32_t 
     launch_load_user(s, ga, c->n, pos, vel, c->pos[c->cur], c->vel, c->id);
     sort_into_tmp(c, c->one, true, s);
     if ((rcode = ensure_list_capacity(c, c->pos_t, half, s)) != MD_OK) return rcode;
-    if (waves && ((rcode = fit_wave_stage(c)) != MD_OK || (rcode = plan_waves(c, s)) != MD_OK)) return rcode;
+    if (waves && ((rcode = fit_wave_stage(c)) != MD_OK ||
+                  (rcode = kind == MD_LIST_DEPS ? plan_deps(c, s) : plan_waves(c, s)) != MD_OK))
+        return rcode;
     {
         ListArgs la = list_args(c, c->one, c->pos_t, half);
         la.vel_src = c->vel_t;
@@ -982,6 +1074,7 @@ int md_get_status(md_ctx *c, int32_t *flags, int64_t *required)
     }
     if (h.err & MD_FLAG_OVERFLOW) return fail(c, MD_ERR_CAPACITY, "neighbour list overflow");
     if (h.err & MD_FLAG_NONFINITE) return fail(c, MD_ERR_NONFINITE, "non-finite force");
+    if (h.err & MD_FLAG_SCHEDULE) return fail(c, MD_ERR_TIMEOUT, "dependent schedule: a wait ran past its limit");
     return MD_OK;
 }
 
@@ -1087,8 +1180,13 @@ int md_set_tuning(md_ctx *c, int32_t key, int32_t value)
         c->have_list = false;
         return MD_OK;
     }
+    if (key == 5 && value >= 0) {
+        c->wait_us = value;
+        return MD_OK;
+    }
     return fail(c, MD_ERR_ARG, "tuning: key 0 in 64..4096 (multiple of 64, within the LDS), key 1 in 1..8, key 2 in 1..4096, "
-                               "key 3 a brick shape, key 4 threads per task (0 or 128..512, multiple of 64)");
+                               "key 3 a brick shape, key 4 threads per task (0 or 128..512, multiple of 64), "
+                               "key 5 a wait limit >= 0 (microseconds)");
 }
 
 int md_query(md_ctx *c, int32_t key, int64_t *value)
@@ -1128,6 +1226,7 @@ int md_query(md_ctx *c, int32_t key, int64_t *value)
         return MD_OK;
     }
     case 11: *value = c->waves_valid ? c->ncol : 0; return MD_OK;
+    case 12: *value = c->deps_valid ? (int64_t)c->dag_succ_h.size() : 0; return MD_OK;
     default: return fail(c, MD_ERR_ARG, "query: key 0..11");
     }
 }
@@ -1135,13 +1234,26 @@ int md_query(md_ctx *c, int32_t key, int64_t *value)
 int md_get_waves(md_ctx *c, int32_t *colour, int64_t capacity, int64_t *n_bricks)
 {
     if (c == nullptr) return MD_ERR_ARG;
-    if (!c->waves_valid) return fail(c, MD_ERR_STATE, "no wave schedule (build an MD_LIST_WAVES list)");
+    if (!c->waves_valid) return fail(c, MD_ERR_STATE, "no wave schedule (build an MD_LIST_WAVES or MD_LIST_DEPS list)");
     if (n_bricks != nullptr) *n_bricks = c->B;
     if (colour != nullptr) {
         if (capacity < c->B) return fail(c, MD_ERR_ARG, "colour array too small");
         std::copy(c->brick_colour.begin(), c->brick_colour.end(), colour);
     }
     return c->ncol;
+}
+
+int64_t md_get_task_graph(md_ctx *c, int32_t *succ_off, int32_t *succ, int64_t capacity)
+{
+    if (c == nullptr) return MD_ERR_ARG;
+    if (!c->deps_valid) return fail(c, MD_ERR_STATE, "no dependent schedule (build an MD_LIST_DEPS list)");
+    const int64_t E = (int64_t)c->dag_succ_h.size();
+    if (succ_off != nullptr) std::copy(c->dag_off_h.begin(), c->dag_off_h.end(), succ_off);
+    if (succ != nullptr) {
+        if (capacity < E) return fail(c, MD_ERR_ARG, "successor array too small");
+        std::copy(c->dag_succ_h.begin(), c->dag_succ_h.end(), succ);
+    }
+    return E;
 }
 
 int md_profile(md_ctx *c, int32_t enable, double *force_ms, int64_t *force_n, double *list_ms,

@@ -254,21 +254,18 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_lj_half(ForceArgs a)
     finish_block(a, accE, accW, 0.0, lds);
 }
 
-// ---------------------------------------------------------------- LJ, half list in waves
-// One launch per wave of bricks whose write sets (own cells plus one layer)
-// are disjoint (the appendix's construction on the brick grid).  A task sums
-// its atoms' forces and its pairs' partner forces per halo candidate in LDS
-// (binary64 LDS atomics between the lanes of the workgroup), then adds the
-// sums to the candidates' forces in HBM with plain loads and stores: no other
-// task of the launch writes those atoms.  Candidates past the LDS stage (a
-// halo larger than the stage) are updated with global atomics, which then meet
-// no other task of the wave either.  Energy and virial are per atom (the
-// pairs an atom holds) and summed later in a fixed order.
+// One half-list brick task: stages the halo with a sorted index and three
+// binary64 partner-force sums per candidate, walks the brick's lists (own force
+// in registers, -f of each pair added to the partner's LDS sums with binary64
+// LDS atomics between the lanes of the workgroup), then adds every sum to its
+// atom's force in HBM with plain loads and stores.  Correct only while no
+// other task that writes the same atoms runs at the same time (the callers'
+// schedules guarantee it).  Candidates past the LDS stage take global atomics.
+// Energy and virial are per atom (the pairs an atom holds).  Begins with a
+// barrier, so consecutive calls may reuse the stage.
 template <bool MIXED>
-__global__ __launch_bounds__(TASK_MAX_THREADS) void k_lj_wave(ForceArgs a)
+__device__ __forceinline__ void lj_half_task(const ForceArgs &a, const Stage &st, int64_t b)
 {
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    const Stage st = stage_slice(lds_raw, a.cap, 3, true);    // extras: partner sums x, y, z
     const double eps = a.lj[0], sig = a.lj[1];
     const double s2 = sig * sig, e4 = 4.0 * eps, e24 = 24.0 * eps;
     const float s2f = (float)s2, e4f = (float)e4, e24f = (float)e24;
@@ -276,80 +273,194 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_lj_wave(ForceArgs a)
     const int64_t n = a.n;
     const int32_t cap = a.cap;
     double *sx = st.ex, *sy = st.ex + cap, *sz = st.ex + 2 * (size_t)cap;
-    for (int32_t t = blockIdx.x; t < a.nwb; t += gridDim.x) {
-        const int64_t b = a.wbr[t];
-        const int32_t *grec = a.brec + b * (int64_t)a.bd.stride;
-        const int32_t natoms = grec[BR_ATOMS];
-        if (natoms == 0) continue;
-        __syncthreads();
-        brick_load(st, a.bd, grec, a.reps, a.pos, nullptr, nullptr);
-        const int32_t total = st.rec[BR_TOTAL];
-        const int32_t lim = total < cap ? total : cap;
-        for (int32_t k = threadIdx.x; k < lim; k += blockDim.x) {
-            sx[k] = 0.0;
-            sy[k] = 0.0;
-            sz[k] = 0.0;
+    const int32_t *grec = a.brec + b * (int64_t)a.bd.stride;
+    const int32_t natoms = __builtin_amdgcn_readfirstlane(grec[BR_ATOMS]);
+    if (natoms == 0) return;
+    __syncthreads();
+    brick_load(st, a.bd, grec, a.reps, a.pos, nullptr, nullptr);
+    const int32_t total = st.rec[BR_TOTAL];
+    const int32_t lim = total < cap ? total : cap;
+    for (int32_t k = threadIdx.x; k < lim; k += blockDim.x) {
+        sx[k] = 0.0;
+        sy[k] = 0.0;
+        sz[k] = 0.0;
+    }
+    __syncthreads();
+    const bool all_staged = total <= cap;
+    const bool has_img = st.rec[BR_SHIFT] == 0;
+    const RepDesc &rep = a.reps[st.rec[BR_REP]];
+    const double Lx = rep.L[0], Ly = rep.L[1], Lz = rep.L[2];
+    const BrickGeom g = brick_geom(a.reps, a.R, b);
+    const int32_t *soff = st.rec + br_soff(a.bd), *aoff = st.rec + br_aoff(a.bd);
+    auto add_to = [&](int32_t k, double fx, double fy, double fz) {
+        if (k < cap) {
+            atomicAdd(&sx[k], fx);
+            atomicAdd(&sy[k], fy);
+            atomicAdd(&sz[k], fz);
+        } else {
+            const int32_t j = candidate_index(st, a.bd, k);
+            atomicAdd(&a.force[j], fx);
+            atomicAdd(&a.force[n + j], fy);
+            atomicAdd(&a.force[2 * n + j], fz);
         }
-        __syncthreads();
-        const bool all_staged = total <= cap;
-        const bool has_img = st.rec[BR_SHIFT] == 0;
-        const RepDesc &rep = a.reps[st.rec[BR_REP]];
-        const double Lx = rep.L[0], Ly = rep.L[1], Lz = rep.L[2];
-        const BrickGeom g = brick_geom(a.reps, a.R, b);
-        const int32_t *soff = st.rec + br_soff(a.bd), *aoff = st.rec + br_aoff(a.bd);
-        auto add_to = [&](int32_t k, double fx, double fy, double fz) {
-            if (k < cap) {
-                atomicAdd(&sx[k], fx);
-                atomicAdd(&sy[k], fy);
-                atomicAdd(&sz[k], fz);
-            } else {
-                const int32_t j = candidate_index(st, a.bd, k);
-                atomicAdd(&a.force[j], fx);
-                atomicAdd(&a.force[n + j], fy);
-                atomicAdd(&a.force[2 * n + j], fz);
-            }
-        };
-        for (int32_t a0 = 0; a0 < natoms; a0 += (int32_t)blockDim.x) {
-            const int32_t la = a0 + (int32_t)threadIdx.x;
-            const bool valid = la < natoms;
-            int32_t e = 0;
-            const int64_t i = valid ? brick_atom(st, a.bd, la, &e) : 0;
-            const int32_t mm = valid ? min(a.cnt[i], a.M) : 0;
-            double fx = 0.0, fy = 0.0, fz = 0.0, en = 0.0, w = 0.0;
-            const double4 xi = a.pos[i];
-            STAGE_IMG_SPLIT(all_staged, has_img,
-                walk_list<STAGED, IMG>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
-                    [&](bool ok, int32_t k, double dx, double dy, double dz, double r2) {
-                        const bool in = ok && r2 < rc2;
-                        double fs, V;
-                        lj_pair<MIXED>(in, r2, s2, e4, e24, s2f, e4f, e24f, fs, V);
-                        const double px = fs * dx, py = fs * dy, pz = fs * dz;
-                        fx += px;
-                        fy += py;
-                        fz += pz;
-                        if (in) add_to(k, -px, -py, -pz);
-                        en += V;
-                        w += fs * r2;
-                    });
-            )
-            if (valid) {
-                // the atom's own candidate slot: its cell's first candidate plus its rank in the cell
-                const int32_t lc0 = e % g.e[0], lc1 = (e / g.e[0]) % g.e[1], lc2 = e / (g.e[0] * g.e[1]);
-                const int32_t hown = (lc0 + 1) % g.nc[0] + g.hn[0] * ((lc1 + 1) % g.nc[1] + g.hn[1] * ((lc2 + 1) % g.nc[2]));
-                add_to(soff[hown] + (la - aoff[e]), fx, fy, fz);
-                if (a.eatom != nullptr) {
-                    a.eatom[i] = en;
-                    a.watom[i] = w;
-                }
+    };
+    for (int32_t a0 = 0; a0 < natoms; a0 += (int32_t)blockDim.x) {
+        const int32_t la = a0 + (int32_t)threadIdx.x;
+        const bool valid = la < natoms;
+        int32_t e = 0;
+        const int64_t i = valid ? brick_atom(st, a.bd, la, &e) : 0;
+        const int32_t mm = valid ? min(a.cnt[i], a.M) : 0;
+        double fx = 0.0, fy = 0.0, fz = 0.0, en = 0.0, w = 0.0;
+        const double4 xi = a.pos[i];
+        STAGE_IMG_SPLIT(all_staged, has_img,
+            walk_list<STAGED, IMG>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
+                [&](bool ok, int32_t k, double dx, double dy, double dz, double r2) {
+                    const bool in = ok && r2 < rc2;
+                    double fs, V;
+                    lj_pair<MIXED>(in, r2, s2, e4, e24, s2f, e4f, e24f, fs, V);
+                    const double px = fs * dx, py = fs * dy, pz = fs * dz;
+                    fx += px;
+                    fy += py;
+                    fz += pz;
+                    if (in) add_to(k, -px, -py, -pz);
+                    en += V;
+                    w += fs * r2;
+                });
+        )
+        if (valid) {
+            // the atom's own candidate slot: its cell's first candidate plus its rank in the cell
+            const int32_t lc0 = e % g.e[0], lc1 = (e / g.e[0]) % g.e[1], lc2 = e / (g.e[0] * g.e[1]);
+            const int32_t hown = (lc0 + 1) % g.nc[0] + g.hn[0] * ((lc1 + 1) % g.nc[1] + g.hn[1] * ((lc2 + 1) % g.nc[2]));
+            add_to(soff[hown] + (la - aoff[e]), fx, fy, fz);
+            if (a.eatom != nullptr) {
+                a.eatom[i] = en;
+                a.watom[i] = w;
             }
         }
-        __syncthreads();
-        for (int32_t k = threadIdx.x; k < lim; k += blockDim.x) {
-            const int32_t j = st.j[k];
-            a.force[j] += sx[k];
-            a.force[n + j] += sy[k];
-            a.force[2 * n + j] += sz[k];
+    }
+    __syncthreads();
+    for (int32_t k = threadIdx.x; k < lim; k += blockDim.x) {
+        const int32_t j = st.j[k];
+        a.force[j] += sx[k];
+        a.force[n + j] += sy[k];
+        a.force[2 * n + j] += sz[k];
+    }
+}
+
+// ---------------------------------------------------------------- LJ, half list in waves
+// One launch per wave of bricks whose write sets (own cells plus one layer)
+// are disjoint (the appendix's construction on the brick grid): no two tasks
+// of a launch write the same atom.
+template <bool MIXED>
+__global__ __launch_bounds__(TASK_MAX_THREADS) void k_lj_wave(ForceArgs a)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const Stage st = stage_slice(lds_raw, a.cap, 3, true);    // extras: partner sums x, y, z
+    for (int32_t t = blockIdx.x; t < a.nwb; t += gridDim.x) lj_half_task<MIXED>(a, st, a.wbr[t]);
+}
+
+// ---------------------------------------------------------------- LJ, half list in dependence order
+// The tasks of all waves in one persistent launch (Sec. II.B's dependent
+// schedule): a task starts once its direct predecessors (the last earlier
+// writer of each of its cells, in wave order) have finished.  Ready tasks go
+// through a queue of n_tasks slots: workgroups take slots in order
+// (d.sched[0]) and wait until the slot is filled; a finished task decrements
+// its successors' counts and appends each that reaches zero (d.sched[1]).  The
+// tasks with no predecessor are in the queue at the start.  Since the graph is
+// acyclic and every taken slot belongs to a running workgroup, every slot is
+// filled while tasks keep finishing; a wait longer than d.limit wall-clock
+// ticks (a broken graph) raises MD_FLAG_SCHEDULE and the abort word, and every
+// workgroup then leaves.  A task's plain stores reach other XCDs through an
+// agent-scope release before its successors are counted down, and the task
+// that takes a slot performs an agent-scope acquire before it reads them.
+// Thread 0: takes the next queue slot and waits (bounded) until a task is in
+// it; returns the task, or -1 when the queue is used up, the abort word is set
+// or the wait ran past the limit (which sets the flag and the abort word).
+__device__ __forceinline__ int32_t take_task(const ForceArgs &a, const DepArgs &d)
+{
+    const int32_t q = __hip_atomic_fetch_add(&d.sched[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (q >= d.T) return -1;
+    const uint64_t t0 = wall_clock64();
+    for (;;) {
+        const int32_t t = __hip_atomic_load(&d.queue[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (t >= 0) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            return t;
         }
+        if (__hip_atomic_load(&d.sched[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return -1;
+        if ((uint64_t)wall_clock64() - t0 > d.limit) {
+            atomicOr(&a.ctl->err, MD_FLAG_SCHEDULE);
+            __hip_atomic_store(&d.sched[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return -1;
+        }
+        __builtin_amdgcn_s_sleep(16);
+    }
+}
+
+// Thread 0, after task t (every wavefront's stores of the task have
+// completed): one agent-scope release writes the task's stores back from this
+// XCD's L2, then the successors are counted down and each that reaches zero is
+// appended to the queue.  Every predecessor of a task has written its stores
+// back before its own count-down, so the task that takes the slot finds all of
+// them in memory after its acquire; the slot itself needs no further release.
+__device__ __forceinline__ void finish_task(const DepArgs &d, int32_t t)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    for (int32_t e = d.off[t]; e < d.off[t + 1]; e++) {
+        const int32_t u = d.succ[e];
+        if (__hip_atomic_fetch_add(&d.ref[u], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1) {
+            const int32_t slot = __hip_atomic_fetch_add(&d.sched[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // a task reaches zero once, so at most T - roots slots are filled
+            if (slot < d.T) __hip_atomic_store(&d.queue[slot], u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// The loop is kept uniform for the compiler: thread 0 does all of the queue
+// work between two barriers and the task index reaches the other lanes
+// through LDS and readfirstlane, so the loop branch is scalar (a branch the
+// compiler must treat as divergent lets it split the loop per lane and run
+// the next barrier without thread 0).
+template <bool MIXED>
+__global__ __launch_bounds__(TASK_MAX_THREADS) void k_lj_deps(ForceArgs a, DepArgs d)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ int32_t s_task;
+    const Stage st = stage_slice(lds_raw, a.cap, 3, true);
+    if (threadIdx.x == 0) s_task = take_task(a, d);
+    __syncthreads();
+    int32_t t = __builtin_amdgcn_readfirstlane(s_task);
+    while (t >= 0) {
+        lj_half_task<MIXED>(a, st, t);
+        // every wavefront waits until its stores have reached the L2, so that
+        // thread 0's write-back covers the whole task
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            finish_task(d, t);
+            s_task = take_task(a, d);
+        }
+        __syncthreads();
+        t = __builtin_amdgcn_readfirstlane(s_task);
+    }
+}
+
+// Working state of a dependent-schedule launch: reference counts from the
+// predecessor counts, the queue holding the tasks without predecessors (in
+// wave order) and empty slots, both slot counters and the abort word cleared.
+__global__ __launch_bounds__(256) void k_deps_init(int32_t T, const int32_t *__restrict__ npred,
+                                                   const int32_t *__restrict__ init_q, int32_t nroots,
+                                                   int32_t *ref, int32_t *queue, int32_t *sched)
+{
+    for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < T; t += gridDim.x * blockDim.x) {
+        ref[t] = npred[t];
+        queue[t] = init_q[t];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sched[0] = 0;
+        sched[1] = nroots;
+        sched[2] = 0;
+        sched[3] = 0;
     }
 }
 
@@ -645,6 +756,20 @@ void launch_eam_force(hipStream_t s, int grid, int threads, bool mixed, const Fo
 void launch_lj_wave(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a)
 {
     MD_LAUNCH_TASKS(k_lj_wave, 3, true)
+}
+
+void launch_lj_deps(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a, const DepArgs &d,
+                    const int32_t *npred, const int32_t *init_q, int32_t nroots)
+{
+    hipLaunchKernelGGL(k_deps_init, dim3((d.T + 255) / 256), dim3(256), 0, s, d.T, npred, init_q, nroots, d.ref,
+                       d.queue, d.sched);
+    const size_t lds = stage_bytes(a.cap, 3, true, a.bd.stride);
+    auto go = [&](auto kernel) {
+        allow_lds(kernel, lds);
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), lds, s, a, d);
+    };
+    if (mixed) go(k_lj_deps<true>);
+    else go(k_lj_deps<false>);
 }
 
 void launch_atom_sums(hipStream_t s, int grid, int64_t n, const double *eatom, const double *watom,

@@ -32,6 +32,7 @@
 // error bits of the sticky device word
 #define MD_FLAG_OVERFLOW 1
 #define MD_FLAG_NONFINITE 2
+#define MD_FLAG_SCHEDULE 4     // a dependent-schedule wait ran past its limit
 
 struct RepDesc {
     double L[3];
@@ -46,6 +47,17 @@ struct RepDesc {
     int64_t atom_end;
 };
 
+// Dependent schedule of the half-list tasks (one persistent launch).
+struct DepArgs {
+    const int32_t *off;    // [T+1] successor list offsets
+    const int32_t *succ;   // successor task ids
+    int32_t *ref;          // [T] predecessors still running (working copy)
+    int32_t *queue;        // [T] ready tasks, -1 = slot not filled yet
+    int32_t *sched;        // [0] next slot to take, [1] next slot to fill, [2] abort
+    int32_t T;             // tasks (= bricks)
+    uint64_t limit;        // wall-clock ticks a workgroup may wait for its slot
+};
+
 // Device-resident control words.
 struct DevCtl {
     int32_t rebuild[2];   // rebuild request, indexed by step parity
@@ -56,6 +68,7 @@ struct DevCtl {
     int32_t max_nbhd;     // largest brick halo (candidates) seen
     int32_t max_brick;    // largest brick (atoms) seen
     uint32_t done[4];     // last-block counters (one per reduction site)
+    int32_t sched[4];     // dependent-schedule slot counters and abort word
 };
 
 // ---------------------------------------------------------------- launchers
@@ -178,6 +191,8 @@ struct ForceArgs {
 void launch_lj_full(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a);
 void launch_lj_half(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a);
 void launch_lj_wave(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a);
+void launch_lj_deps(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a, const DepArgs &d,
+                    const int32_t *npred, const int32_t *init_q, int32_t nroots);
 void launch_atom_sums(hipStream_t s, int grid, int64_t n, const double *eatom, const double *watom,
                       double *energy, double *virial, double *partial, uint32_t *done);
 void launch_eam_density(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a);

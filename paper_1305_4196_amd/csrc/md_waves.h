@@ -19,6 +19,9 @@
 // axis) puts every brick in a set of its own.  The separation is checked on the
 // actual brick extents (the last brick of an axis may be shorter).
 //
+// The dependent schedule (task_graph below) replaces the barrier after each
+// wave by per-task dependences derived from the same wave order.
+//
 // Host code only.
 #pragma once
 
@@ -125,6 +128,61 @@ inline int colour_bricks(const int32_t nb[3], const int sep[3], std::vector<int3
                 w++;
             }
     return w;
+}
+
+// Cells a brick writes along one axis: its halo coordinates (o - 1 + t) mod nc,
+// t = 0 .. min(e + 2, nc) - 1 (the brick's cells and one layer around them).
+inline void axis_write_set(int o, int e, int nc, std::vector<int> &out)
+{
+    out.clear();
+    const int len = std::min(e + 2, nc);
+    for (int t = 0; t < len; t++) out.push_back(((o - 1 + t) % nc + nc) % nc);
+}
+
+// Dependences between tasks (Sec. II.B): a task waits only for the last earlier
+// task, in wave order, that writes each of its cells; these direct predecessors
+// order every pair of tasks that share a cell.  The successor lists come from
+// the backward method: walk the tasks from the last to the first, keeping for
+// every cell the next task that writes it; a task's successors are the
+// distinct entries of its cells, after which the task becomes the next writer
+// of each of them.
+//
+// order: the tasks in wave order; cells(t, out) fills the global cell ids that
+// task t writes; n_cells: number of global cells; n_tasks: tasks are numbered
+// 0 .. n_tasks - 1.  Output: succ_off (n_tasks + 1), succ (each list
+// ascending), npred (predecessor count of each task).
+template <typename Cells>
+inline void task_graph(const std::vector<int32_t> &order, Cells cells, int64_t n_cells, int64_t n_tasks,
+                       std::vector<int32_t> &succ_off, std::vector<int32_t> &succ,
+                       std::vector<int32_t> &npred)
+{
+    std::vector<int32_t> next((size_t)n_cells, -1), seen((size_t)n_tasks, -1);
+    std::vector<std::vector<int32_t>> lists((size_t)n_tasks);
+    std::vector<int64_t> mine;
+    for (size_t q = order.size(); q-- > 0;) {
+        const int32_t t = order[q];
+        mine.clear();
+        cells(t, mine);
+        std::vector<int32_t> &L = lists[(size_t)t];
+        for (int64_t c : mine) {
+            const int32_t u = next[(size_t)c];
+            if (u >= 0 && seen[(size_t)u] != t) {
+                seen[(size_t)u] = t;
+                L.push_back(u);
+            }
+            next[(size_t)c] = t;
+        }
+        std::sort(L.begin(), L.end());
+    }
+    succ_off.assign((size_t)n_tasks + 1, 0);
+    npred.assign((size_t)n_tasks, 0);
+    for (int64_t t = 0; t < n_tasks; t++) {
+        succ_off[(size_t)t + 1] = succ_off[(size_t)t] + (int32_t)lists[(size_t)t].size();
+        for (int32_t u : lists[(size_t)t]) npred[(size_t)u]++;
+    }
+    succ.clear();
+    succ.reserve((size_t)succ_off[(size_t)n_tasks]);
+    for (int64_t t = 0; t < n_tasks; t++) succ.insert(succ.end(), lists[(size_t)t].begin(), lists[(size_t)t].end());
 }
 
 } // namespace mdwaves

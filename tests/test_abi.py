@@ -62,6 +62,7 @@ def test_null_context_is_rejected(lib):
     assert lib.md_build_neighbor_list(None, 0, None) == -1
     assert lib.md_set_tuning(None, 0, 8) == -1
     assert lib.md_get_waves(None, None, 0, None) == -1
+    assert lib.md_get_task_graph(None, None, None, 0) == -1
     assert lib.md_last_error(None) == b"null context"
 
 

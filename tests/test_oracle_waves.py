@@ -111,3 +111,81 @@ def test_brick_colours_keep_write_sets_disjoint():
         for members in by.values():
             for p, q in itertools.combinations(members, 2):
                 assert any(not (sets[d][p[d]] & sets[d][q[d]]) for d in range(3)), (nc, shape, p, q)
+
+
+# ---------------------------------------------------------------- dependent schedule (Sec. II.B)
+GRIDS = [((6, 6, 6), (1, 1, 1)), ((7, 5, 4), (1, 1, 1)), ((9, 10, 11), (4, 4, 4)),
+         ((13, 7, 6), (4, 3, 2)), ((4, 4, 4), (1, 1, 1)), ((5, 6, 3), (2, 2, 1))]
+
+
+def cells_of(nc, shape):
+    return lambda t: W.brick_write_cells(nc, shape, t)
+
+
+@pytest.mark.parametrize("nc,shape", GRIDS)
+def test_forward_and_backward_methods_give_the_same_graph(nc, shape):
+    colour, _ = W.brick_colours(nc, shape)
+    order = W.wave_order(colour)
+    pred = W.predecessors_forward(order, cells_of(nc, shape))
+    succ = W.successors_backward(order, cells_of(nc, shape))
+    transposed = {t: set() for t in order}
+    for t, S in succ.items():
+        for s in S:
+            transposed[s].add(t)
+    assert transposed == pred
+
+
+@pytest.mark.parametrize("nc,shape", GRIDS[:4])
+def test_direct_predecessors_by_their_definition(nc, shape):
+    """t -> s exactly when t comes before s, both write some cell c, and no
+    task between them in wave order writes c (brute force over all pairs)."""
+    succ, order = W.brick_task_graph(nc, shape)
+    pos = {t: k for k, t in enumerate(order)}
+    cells = {t: set(W.brick_write_cells(nc, shape, t)) for t in order}
+    for t in order:
+        expect = set()
+        for s in order[pos[t] + 1:]:
+            for c in cells[t] & cells[s]:
+                if not any(c in cells[u] for u in order[pos[t] + 1:pos[s]]):
+                    expect.add(s)
+                    break
+        assert succ[t] == expect, t
+
+
+@pytest.mark.parametrize("nc,shape", GRIDS)
+def test_the_graph_orders_every_pair_that_shares_a_cell(nc, shape):
+    """The paper's argument: waiting for the last earlier writer of each cell
+    orders a task after every earlier task it shares a cell with."""
+    succ, order = W.brick_task_graph(nc, shape)
+    reach = {}
+    for t in reversed(order):                 # successors come later in the order
+        r = set()
+        for s in succ[t]:
+            r |= {s} | reach[s]
+        reach[t] = r
+    cells = {t: set(W.brick_write_cells(nc, shape, t)) for t in order}
+    for i, t in enumerate(order):
+        for s in order[i + 1:]:
+            if cells[t] & cells[s]:
+                assert s in reach[t], (t, s)
+
+
+@pytest.mark.parametrize("nc,shape", GRIDS)
+def test_no_edge_inside_a_wave_and_depth_within_the_wave_count(nc, shape):
+    colour, nw = W.brick_colours(nc, shape)
+    succ, order = W.brick_task_graph(nc, shape)
+    depth = {}
+    for t in reversed(order):
+        for s in succ[t]:
+            assert colour[s] > colour[t]
+        depth[t] = 1 + max((depth[s] for s in succ[t]), default=0)
+    assert max(depth.values()) <= nw
+
+
+def test_cell_tasks_have_at_most_27_direct_predecessors():
+    nc = (7, 8, 10)
+    pred = W.predecessors_forward(W.wave_order(W.brick_colours(nc, (1, 1, 1))[0]),
+                                  cells_of(nc, (1, 1, 1)))
+    assert max(len(p) for p in pred.values()) <= 27
+    assert sum(len(p) == 0 for p in pred.values()) == sum(
+        1 for c in W.brick_colours(nc, (1, 1, 1))[0] if c == 0)
