@@ -146,6 +146,20 @@ def neighbor_list(x: np.ndarray, L, rl: float, full: bool = True) -> Tuple[np.nd
     return start, nbr[:tot]
 
 
+def shell_list(x: np.ndarray, L, rl: float) -> Tuple[np.ndarray, np.ndarray]:
+    """CSR of the half list over 14 of the 27 cells (each pair once, held by the
+    atom that sees the partner's cell in the forward half); x must be wrapped."""
+    x = _f64(x)
+    n = x.shape[1]
+    start = np.zeros(n + 1, dtype=np.int64)
+    tot = lib().orc_neighbor_list(n, _p(x), _p(_box(L)), rl, 2, _p(start, _i64), 0, None)
+    if tot < 0:
+        raise ValueError("box shorter than twice the list cutoff")
+    nbr = np.zeros(max(tot, 1), dtype=np.int32)
+    lib().orc_neighbor_list(n, _p(x), _p(_box(L)), rl, 2, _p(start, _i64), tot, _p(nbr, _i32))
+    return start, nbr[:tot]
+
+
 def half_pairs(x: np.ndarray, L, rl: float) -> Tuple[np.ndarray, np.ndarray]:
     """Unordered pairs within rl (each once) from the linked-cell half list."""
     start, nbr = neighbor_list(x, L, rl, full=False)

@@ -165,10 +165,35 @@ int64_t orc_pairs_brute(int64_t n, const double *x, const double L[3], double cu
 
 /* Verlet lists built cell by cell (Sec. II.A): for every atom, the distinct
  * cells of its 27-cell neighbourhood are scanned and atoms with r2 < rl^2 kept.
- * x must be wrapped.  full != 0: every neighbour; full == 0: only neighbours
+ * x must be wrapped.  full == 1: every neighbour; full == 0: only neighbours
  * that come later in the cell-sorted order (rank[j] > rank[i]), so each pair is
- * held once (Sec. II.D.3).  start[n+1] receives offsets; each atom's entries are
- * ascending atom ids.  Writes up to cap entries; returns the total. */
+ * held once (Sec. II.D.3); full == 2: the half list over 14 of the 27 cells
+ * (Sec. II.D.3): j is kept when its cell, seen through the pair's minimum image,
+ * lies in the forward half of the neighbourhood (shell_forward), so an atom's
+ * partners lie in its own cell, the cell above in x, the three above in y and
+ * the nine above in z -- a 3 x 3 x 2 block of cells.  start[n+1] receives
+ * offsets; each atom's entries are ascending atom ids.  Writes up to cap
+ * entries; returns the total. */
+/* Unwrapped cell offset of j seen from i along one axis: j's cell, shifted by
+ * nc when the minimum image moves j by a whole box (x_i - x_j > L/2: j is seen
+ * at x_j + L), minus i's cell. */
+static int32_t cell_offset(double xi, double xj, double L, int32_t ci, int32_t cj, int32_t nc)
+{
+    double d = xi - xj;
+    int32_t s = d > 0.5 * L ? 1 : (d < -0.5 * L ? -1 : 0);
+    return cj + s * nc - ci;
+}
+
+/* forward half of the cell neighbourhood: above in z; else above in y; else
+ * above in x; within the same cell, later in the sorted order */
+static int shell_forward(int32_t ox, int32_t oy, int32_t oz, int32_t ri, int32_t rj)
+{
+    if (oz != 0) return oz > 0;
+    if (oy != 0) return oy > 0;
+    if (ox != 0) return ox > 0;
+    return rj > ri;
+}
+
 int64_t orc_neighbor_list(int64_t n, const double *x, const double L[3], double rl, int full,
                           int64_t *start, int64_t cap, int32_t *nbr)
 {
@@ -194,7 +219,15 @@ int64_t orc_neighbor_list(int64_t n, const double *x, const double L[3], double 
             for (int32_t s = cstart[cells[k]]; s < cstart[cells[k] + 1]; s++) {
                 int32_t j = order[s];
                 if (j == i) continue;
-                if (!full && !(rank[j] > rank[i])) continue;
+                if (full == 0 && !(rank[j] > rank[i])) continue;
+                if (full == 2) {
+                    int32_t c2 = cell_of[j];
+                    int32_t jx = c2 % nc[0], jy = (c2 / nc[0]) % nc[1], jz = c2 / (nc[0] * nc[1]);
+                    int32_t ox = cell_offset(X(x, n, i), X(x, n, j), L[0], cx, jx, nc[0]);
+                    int32_t oy = cell_offset(Y(x, n, i), Y(x, n, j), L[1], cy, jy, nc[1]);
+                    int32_t oz = cell_offset(Z(x, n, i), Z(x, n, j), L[2], cz, jz, nc[2]);
+                    if (!shell_forward(ox, oy, oz, rank[i], rank[j])) continue;
+                }
                 if (sep(x, n, i, j, L, d) < rl2) {
                     if (total < cap) nbr[total] = j;
                     total++;

@@ -26,6 +26,11 @@ seen so far while walking the tasks first to last (predecessor lists); the
 backward method keeps, per cell, the next task while walking last to first
 (successor lists).
 
+Stricter overlap (Sec. II.D.3): with the half list over 14 of the 27 cells an
+atom's partners never lie in the layer below its cell, so a cell task writes a
+3 x 3 x 2 block instead of 3 x 3 x 3, and tasks two cells apart along z no
+longer overlap (below = 0 along z in write_set).
+
 Brick colouring (this design's GPU tasks are bricks of cells): a brick writes
 the cells of its halo (its cells and one layer around them, the same
 coordinates the brick record uses); two bricks may share a wave only if their
@@ -127,29 +132,39 @@ def brick_ranges(nc: int, b: int) -> List[Tuple[int, int]]:
     return [(o, min(b, nc - o)) for o in range(0, nc, b)]
 
 
-def write_set(o: int, e: int, nc: int) -> set:
-    """Cells a brick writes along one axis: its halo coordinates (o - 1 + t) mod nc."""
-    return {(o - 1 + t) % nc for t in range(min(e + 2, nc))}
+def write_set(o: int, e: int, nc: int, below: int = 1) -> set:
+    """Cells a brick writes along one axis: its cells, `below` layers under them
+    and one above, (o - below + t) mod nc.  below = 1 for a list whose partners
+    lie on both sides; below = 0 along z for the 14-cell half list (Sec. II.D.3:
+    the 3 x 3 x 2 overlap)."""
+    return {(o - below + t) % nc for t in range(min(e + 1 + below, nc))}
 
 
-def axis_separation(nc: int, b: int) -> int:
+def axis_separation(nc: int, b: int, below: int = 1) -> int:
     """Smallest separation (2, then 3) such that any two bricks of the axis at
     least that far apart (cyclically, in brick index) have disjoint write sets;
     the number of bricks when neither works (each brick a set of its own)."""
     br = brick_ranges(nc, b)
     D = len(br)
-    ws = [write_set(o, e, nc) for o, e in br]
+    ws = [write_set(o, e, nc, below) for o, e in br]
     for s in (2, 3):
         if all(not (ws[p] & ws[q]) for p in range(D) for q in range(p + 1, D) if cyc_dist(p, q, D) >= s):
             return s
     return D
 
 
-def brick_colours(nc: Sequence[int], bshape: Sequence[int]) -> Tuple[List[int], int]:
+def below_layers(shell: bool) -> List[int]:
+    """Layers under a brick that it writes, per axis: one on every axis, except
+    along z for the 14-cell half list, whose partners never lie below."""
+    return [1, 1, 0 if shell else 1]
+
+
+def brick_colours(nc: Sequence[int], bshape: Sequence[int], shell: bool = False) -> Tuple[List[int], int]:
     """Colour (wave index) of every brick of one replica, bricks numbered x
     fastest, and the number of colours."""
     nb = [len(brick_ranges(nc[d], bshape[d])) for d in range(3)]
-    seps = [axis_separation(nc[d], bshape[d]) for d in range(3)]
+    lo = below_layers(shell)
+    seps = [axis_separation(nc[d], bshape[d], lo[d]) for d in range(3)]
     ws = waves(nb, seps)
     colour = [-1] * (nb[0] * nb[1] * nb[2])
     for w, cells in enumerate(ws):
@@ -159,14 +174,16 @@ def brick_colours(nc: Sequence[int], bshape: Sequence[int]) -> Tuple[List[int], 
 
 
 # ---------------------------------------------------------------- dependences
-def brick_write_cells(nc: Sequence[int], bshape: Sequence[int], b: int) -> List[Tuple[int, int, int]]:
+def brick_write_cells(nc: Sequence[int], bshape: Sequence[int], b: int,
+                      shell: bool = False) -> List[Tuple[int, int, int]]:
     """Cells (x, y, z) written by brick b (numbered x fastest) of a grid nc cut into bshape bricks."""
     nb = [len(brick_ranges(nc[d], bshape[d])) for d in range(3)]
     idx = (b % nb[0], (b // nb[0]) % nb[1], b // (nb[0] * nb[1]))
+    lo = below_layers(shell)
     sets = []
     for d in range(3):
         o, e = brick_ranges(nc[d], bshape[d])[idx[d]]
-        sets.append(sorted(write_set(o, e, nc[d])))
+        sets.append(sorted(write_set(o, e, nc[d], lo[d])))
     return [(x, y, z) for z in sets[2] for y in sets[1] for x in sets[0]]
 
 
@@ -201,10 +218,10 @@ def successors_backward(order: Sequence[int], cells) -> dict:
     return succ
 
 
-def brick_task_graph(nc: Sequence[int], bshape: Sequence[int]) -> Tuple[dict, List[int]]:
+def brick_task_graph(nc: Sequence[int], bshape: Sequence[int], shell: bool = False) -> Tuple[dict, List[int]]:
     """Successor sets of the bricks of one grid (backward method over the wave
     order of brick_colours) and that order."""
-    colour, _ = brick_colours(nc, bshape)
+    colour, _ = brick_colours(nc, bshape, shell)
     order = wave_order(colour)
-    succ = successors_backward(order, lambda t: brick_write_cells(nc, bshape, t))
+    succ = successors_backward(order, lambda t: brick_write_cells(nc, bshape, t, shell))
     return succ, order

@@ -170,3 +170,56 @@ def test_fcc_neighbour_shells():
     assert np.all(np.diff(start) == 78)
     start, _ = oracle.neighbor_list(x, L, 2.5, full=True)
     assert np.all(np.diff(start) == 54)
+
+
+# ---------------------------------------------------------------- the 14-cell half list
+def unwrapped_offset(x, L, nc, coords, i, j):
+    """Cell offset of j's minimum image from i's cell, per axis."""
+    o = []
+    for a in range(3):
+        d = x[a, i] - x[a, j]
+        s = 1 if d > 0.5 * L[a] else (-1 if d < -0.5 * L[a] else 0)
+        o.append(int(coords[a, j] + s * nc[a] - coords[a, i]))
+    return tuple(o)
+
+
+@pytest.mark.parametrize("L,rl,n", CASES)
+def test_shell_list_holds_every_pair_once_within_a_3x3x2_block(L, rl, n):
+    x, L = random_box(17, n, L)
+    x = oracle.wrap(x, L)
+    start, nbr = oracle.shell_list(x, L, rl)
+    sh = csr_pairs(start, nbr)
+    ref = numpy_pairs(x, L, rl, False)
+    assert len(sh) == len(ref)
+    assert {(min(i, j), max(i, j)) for i, j in sh} == ref
+    b = oracle.bin_cells(x, L, rl)
+    nc, cell = b["nc"], b["cell_of"]
+    coords = np.stack([cell % nc[0], (cell // nc[0]) % nc[1], cell // (nc[0] * nc[1])])
+    seen = set()
+    for i, j in sh:
+        o = unwrapped_offset(x, L, nc, coords, i, j)
+        assert all(-1 <= v <= 1 for v in o)
+        assert o[2] in (0, 1)              # never a partner in the layer below
+        seen.add(o)
+    # of two mirrored cell offsets only one is ever used: 13 + the own cell
+    assert not any(tuple(-v for v in o) in seen for o in seen if o != (0, 0, 0))
+    assert len(seen) <= 14
+    if min(nc) >= 3:
+        assert len(seen) == 14
+
+
+def test_shell_list_gives_the_half_list_forces():
+    """Same pairs, other owners: forces, energy and virial agree to rounding."""
+    x, L = random_box(5, 700, (12.0, 12.0, 12.0))
+    x = oracle.wrap(x, L)
+    rl = 2.8
+    hs, hn = oracle.neighbor_list(x, L, rl, full=False)
+    ss, sn = oracle.shell_list(x, L, rl)
+    out = []
+    for st, nb in ((hs, hn), (ss, sn)):
+        pi = np.repeat(np.arange(x.shape[1], dtype=np.int32), np.diff(st)).astype(np.int32)
+        out.append(oracle.lj(x, L, pi, nb.astype(np.int32), rc=2.5))
+    (Fa, Ea, Wa), (Fb, Eb, Wb) = out
+    assert np.max(np.abs(Fa - Fb)) <= 1e-12 * np.max(np.abs(Fa))
+    assert Eb == pytest.approx(Ea, rel=1e-13)
+    assert Wb == pytest.approx(Wa, rel=1e-12)

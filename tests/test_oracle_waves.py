@@ -189,3 +189,48 @@ def test_cell_tasks_have_at_most_27_direct_predecessors():
     assert max(len(p) for p in pred.values()) <= 27
     assert sum(len(p) == 0 for p in pred.values()) == sum(
         1 for c in W.brick_colours(nc, (1, 1, 1))[0] if c == 0)
+
+
+# ---------------------------------------------------------------- stricter overlap (Sec. II.D.3)
+def test_stricter_overlap_puts_50_percent_more_cell_tasks_in_a_wave():
+    """With the 3 x 3 x 2 overlap, cell tasks on a 6 x 6 x 6 grid need 18 waves
+    of 12 tasks instead of 27 waves of 8 (the paper's figure of up to 50 %)."""
+    c27, n27 = W.brick_colours((6, 6, 6), (1, 1, 1))
+    c18, n18 = W.brick_colours((6, 6, 6), (1, 1, 1), shell=True)
+    assert (n27, n18) == (27, 18)
+    assert all(c27.count(k) == 8 for k in range(27))
+    assert all(c18.count(k) == 12 for k in range(18))
+    assert W.axis_separation(6, 1, below=0) == 2 and W.axis_separation(6, 1) == 3
+
+
+@pytest.mark.parametrize("nc,shape", [((38, 38, 38), (1, 1, 1)), ((9, 10, 11), (4, 4, 4)),
+                                      ((7, 5, 13), (1, 1, 1)), ((6, 6, 5), (2, 3, 1)),
+                                      ((3, 4, 5), (1, 2, 2)), ((13, 7, 6), (4, 3, 2))])
+def test_shell_colours_keep_the_3x3x2_write_sets_disjoint(nc, shape):
+    colour, n = W.brick_colours(nc, shape, shell=True)
+    nb = [len(W.brick_ranges(nc[d], shape[d])) for d in range(3)]
+    lo = W.below_layers(True)
+    sets = [[W.write_set(o, e, nc[d], lo[d]) for o, e in W.brick_ranges(nc[d], shape[d])] for d in range(3)]
+    by = {}
+    for idx, c in enumerate(colour):
+        by.setdefault(c, []).append((idx % nb[0], (idx // nb[0]) % nb[1], idx // (nb[0] * nb[1])))
+    assert sorted(by) == list(range(n))
+    for members in by.values():
+        for p, q in itertools.combinations(members, 2):
+            assert any(not (sets[d][p[d]] & sets[d][q[d]]) for d in range(3)), (nc, shape, p, q)
+    assert n <= W.brick_colours(nc, shape)[1]
+
+
+@pytest.mark.parametrize("nc,shape", GRIDS[:4])
+def test_shell_graph_by_its_definition(nc, shape):
+    succ, order = W.brick_task_graph(nc, shape, shell=True)
+    pos = {t: k for k, t in enumerate(order)}
+    cells = {t: set(W.brick_write_cells(nc, shape, t, shell=True)) for t in order}
+    for t in order:
+        expect = set()
+        for s in order[pos[t] + 1:]:
+            for c in cells[t] & cells[s]:
+                if not any(c in cells[u] for u in order[pos[t] + 1:pos[s]]):
+                    expect.add(s)
+                    break
+        assert succ[t] == expect, t
