@@ -83,6 +83,8 @@ def main():
     ap.add_argument("--wgpc", type=int, default=0)
     ap.add_argument("--brick", type=str, default="", help="brick shape bx,by,bz (cells per task)")
     ap.add_argument("--threads", type=int, default=0, help="threads per brick task")
+    ap.add_argument("--shell", action="store_true",
+                    help="half lists over 14 of the 27 cells (the 3x3x2 task overlap)")
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
     ap.add_argument("--thermo", type=int, default=100,
                     help="record E_pot, KE, W every this many steps (and after the last)")
@@ -131,6 +133,8 @@ def main():
         B.md_set_tuning(sysm.ctx, 3, bx | by << 8 | bz << 16)
     if args.threads:
         B.md_set_tuning(sysm.ctx, 4, args.threads)
+    if args.shell:
+        B.md_set_tuning(sysm.ctx, 6, 1)
     pos0 = torch.tensor(w.pos, dtype=torch.float64, device="cuda")
     vel0 = torch.tensor(w.vel, dtype=torch.float64, device="cuda")
     F = torch.empty_like(pos0)
@@ -170,7 +174,8 @@ def main():
         tuning = {"brick": B.md_query(sysm.ctx, 3), "threads": B.md_query(sysm.ctx, 4),
                   "lds_candidates": B.md_query(sysm.ctx, 0), "row_capacity": B.md_query(sysm.ctx, 2),
                   "bricks": B.md_query(sysm.ctx, 5), "grid": B.md_query(sysm.ctx, 9),
-                  "max_halo": B.md_query(sysm.ctx, 6), "max_brick_atoms": B.md_query(sysm.ctx, 7)}
+                  "max_halo": B.md_query(sysm.ctx, 6), "max_brick_atoms": B.md_query(sysm.ctx, 7),
+                  "waves": B.md_query(sysm.ctx, 11), "half_rule": "14-cell" if B.md_query(sysm.ctx, 13) else "sorted"}
         tuning["brick"] = "x".join(str((tuning["brick"] >> s) & 255) for s in (0, 8, 16))
         nbar = B.md_query(sysm.ctx, 10) / n
         results[name] = dict(

@@ -235,7 +235,16 @@ int64_t md_get_task_graph(md_ctx *ctx, int32_t *succ_off, int32_t *succ, int64_t
  *   them with the shape; drops the current list;
  * key 5 = longest wait of a dependent-schedule workgroup for a ready task, in
  *   microseconds (default 2,000,000; 0 ends a launch at the first wait, the
- *   way the failure path is tested).
+ *   way the failure path is tested);
+ * key 6 = which atom of a pair holds it in the half lists (MD_LIST_HALF,
+ *   MD_LIST_WAVES, MD_LIST_DEPS): 0 (default) the one that comes first in the
+ *   cell-sorted order; 1 the half list over 14 of the 27 cells (Sec. II.D.3):
+ *   the atom that sees the partner's cell, through the pair's minimum image,
+ *   above its own in z, else above in y, else above in x, else (same cell)
+ *   the one first in the sorted order.  Partners then lie in the atom's cell
+ *   and the layer above, so a task writes a 3 x 3 x 2 block of cells per cell
+ *   and the waves and task graphs use that stricter overlap.  The list is
+ *   built full and filtered.  Drops the current list.
  * Returns MD_OK or MD_ERR_ARG. */
 int md_set_tuning(md_ctx *ctx, int32_t key, int32_t value);
 
@@ -246,7 +255,7 @@ int md_set_tuning(md_ctx *ctx, int32_t key, int32_t value);
  * sizing pass (both synchronise), 8 LDS bytes a workgroup may use, 9 workgroups
  * of the LJ force grid, 10 entries of the current list (synchronises), 11
  * waves of the current wave schedule (0 if none), 12 edges of the current
- * task graph (0 if none).
+ * task graph (0 if none), 13 the half-list rule (key 6).
  * Returns MD_OK, MD_ERR_ARG, MD_ERR_STATE (key 10 without a list) or MD_ERR_HIP. */
 int md_query(md_ctx *ctx, int32_t key, int64_t *value);
 

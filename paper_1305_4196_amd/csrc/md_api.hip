@@ -122,6 +122,9 @@ struct md_ctx {
     int64_t dag_alloc_t = 0, dag_alloc_e = 0;
     int32_t dag_roots = 0;
     int64_t wait_us = 2000000;            // longest wait for a queue slot (microseconds)
+    // half lists over 14 of the 27 cells (built full, then filtered) and the
+    // 3 x 3 x 2 task overlap they allow
+    bool shell = false;
     int64_t wall_khz = 100000;            // device wall clock (kHz)
 
     // atoms (cell-sorted)
@@ -401,6 +404,10 @@ int plan_bricks(md_ctx *c, hipStream_t s)
     return MD_OK;
 }
 
+// layers under a brick that its tasks write along axis k: none along z for the
+// 14-cell half list, whose partners never lie below an atom's cell
+int below_layers(const md_ctx *c, int k) { return k == 2 && c->shell ? 0 : 1; }
+
 // Colours the bricks of every replica (md_waves.h); colour k of all replicas
 // runs in one launch (replicas never interact).
 int plan_waves(md_ctx *c, hipStream_t s)
@@ -411,7 +418,7 @@ int plan_waves(md_ctx *c, hipStream_t s)
     for (int32_t r = 0; r < c->R; r++) {
         const RepDesc &d = c->reps_h[r];
         int sep[3];
-        for (int k = 0; k < 3; k++) sep[k] = mdwaves::axis_separation(d.nc[k], d.bd[k]);
+        for (int k = 0; k < 3; k++) sep[k] = mdwaves::axis_separation(d.nc[k], d.bd[k], below_layers(c, k));
         std::vector<int32_t> col;
         ncol = std::max(ncol, (int32_t)mdwaves::colour_bricks(d.nb, sep, col));
         std::copy(col.begin(), col.end(), c->brick_colour.begin() + d.brick_off);
@@ -459,7 +466,7 @@ int plan_deps(md_ctx *c, hipStream_t s)
         const int bi[3] = {(int)(lb % d.nb[0]), (int)(lb / d.nb[0] % d.nb[1]), (int)(lb / ((int64_t)d.nb[0] * d.nb[1]))};
         for (int k = 0; k < 3; k++) {
             const int o = bi[k] * d.bd[k];
-            mdwaves::axis_write_set(o, std::min(d.bd[k], d.nc[k] - o), d.nc[k], ax[k]);
+            mdwaves::axis_write_set(o, std::min(d.bd[k], d.nc[k] - o), d.nc[k], below_layers(c, k), ax[k]);
         }
         for (int z : ax[2])
             for (int y : ax[1])
@@ -579,6 +586,17 @@ int ensure_list_capacity(md_ctx *c, const double4 *src, int half, hipStream_t s)
 {
     if (!c->bricks_valid || c->M == 0 || c->need_M > c->M) return size_list(c, src, half, s);
     return MD_OK;
+}
+
+// The list builder's pair rule for a list kind: the sorted-order half list is
+// built directly; the 14-cell half list is built full and then filtered.
+int builder_half(const md_ctx *c, int half) { return half && !c->shell ? 1 : 0; }
+
+// one list build (la made with builder_half), and the filter of the 14-cell half list
+void build_list(md_ctx *c, hipStream_t s, int half, const ListArgs &la)
+{
+    launch_build_list(s, c->grid_tasks(0, la.half != 0), c->threads, la);
+    if (half && c->shell) launch_shell_filter(s, c->grid_tasks(0, false), c->threads, la);
 }
 
 ForceArgs force_args(md_ctx *c, const md_potential *p)
@@ -796,13 +814,13 @@ int md_build_neighbor_list(md_ctx *c, int32_t kind, void *stream)
     hipStream_t s = (hipStream_t)stream;
     c->last = s;
     const int half = kind != MD_LIST_FULL;
-    int rcode = ensure_list_capacity(c, c->pos[c->cur], half, s);
+    int rcode = ensure_list_capacity(c, c->pos[c->cur], builder_half(c, half), s);
     if (rcode != MD_OK) return rcode;
     if (kind == MD_LIST_WAVES && ((rcode = fit_wave_stage(c)) != MD_OK || (rcode = plan_waves(c, s)) != MD_OK))
         return rcode;
     if (kind == MD_LIST_DEPS && ((rcode = fit_wave_stage(c)) != MD_OK || (rcode = plan_deps(c, s)) != MD_OK))
         return rcode;
-    launch_build_list(s, c->grid_tasks(0, half != 0), c->threads, list_args(c, c->one, c->pos[c->cur], half));
+    build_list(c, s, half, list_args(c, c->one, c->pos[c->cur], builder_half(c, half)));
     c->have_list = true;
     c->list_kind = kind;
     return check_hip(c, "md_build_neighbor_list");
@@ -891,19 +909,19 @@ int md_verlet_step(md_ctx *c, const md_potential *p, int32_t precision, int32_t 
     hipLaunchKernelGGL(k_set_ctl, dim3(1), dim3(64), 0, s, c->ctl, 1, 1);
     launch_load_user(s, ga, c->n, pos, vel, c->pos[c->cur], c->vel, c->id);
     sort_into_tmp(c, c->one, true, s);
-    if ((rcode = ensure_list_capacity(c, c->pos_t, half, s)) != MD_OK) return rcode;
+    if ((rcode = ensure_list_capacity(c, c->pos_t, builder_half(c, half), s)) != MD_OK) return rcode;
     if (waves && ((rcode = fit_wave_stage(c)) != MD_OK ||
                   (rcode = kind == MD_LIST_DEPS ? plan_deps(c, s) : plan_waves(c, s)) != MD_OK))
         return rcode;
     {
-        ListArgs la = list_args(c, c->one, c->pos_t, half);
+        ListArgs la = list_args(c, c->one, c->pos_t, builder_half(c, half));
         la.vel_src = c->vel_t;
         la.id_src = c->id_t;
         la.pos_dst = c->pos[c->cur];
         la.vel_dst = c->vel;
         la.id_dst = c->id;
         la.xref = c->xref;
-        launch_build_list(s, c->grid_tasks(0, half != 0), c->threads, la);
+        build_list(c, s, half, la);
     }
     c->have_list = true;
     c->list_kind = kind;
@@ -989,14 +1007,14 @@ int md_verlet_step(md_ctx *c, const md_potential *p, int32_t precision, int32_t 
     for (int32_t st = 1; st <= n_steps; st++) {
         int32_t *pred = &c->ctl->rebuild[st & 1];
         sort_into_tmp(c, pred, true, s);
-        ListArgs la = list_args(c, pred, c->pos_t, half);
+        ListArgs la = list_args(c, pred, c->pos_t, builder_half(c, half));
         la.vel_src = c->vel_t;
         la.id_src = c->id_t;
         la.pos_dst = c->pos[c->cur];
         la.vel_dst = c->vel;
         la.id_dst = c->id;
         la.xref = c->xref;
-        timed(c, s, c->ev_list, [&] { launch_build_list(s, half ? gh : gf, c->threads, la); });
+        timed(c, s, c->ev_list, [&] { build_list(c, s, half, la); });
         const int mode = st < n_steps ? 2 : 3;
         // energies of every hist_every-th step and of the last one
         const bool rec = hist != nullptr && (st % hist_every == 0 || st == n_steps);
@@ -1184,9 +1202,16 @@ int md_set_tuning(md_ctx *c, int32_t key, int32_t value)
         c->wait_us = value;
         return MD_OK;
     }
+    if (key == 6 && (value == 0 || value == 1)) {
+        c->shell = value == 1;
+        c->have_list = false;
+        c->waves_valid = false;
+        c->deps_valid = false;
+        return MD_OK;
+    }
     return fail(c, MD_ERR_ARG, "tuning: key 0 in 64..4096 (multiple of 64, within the LDS), key 1 in 1..8, key 2 in 1..4096, "
                                "key 3 a brick shape, key 4 threads per task (0 or 128..512, multiple of 64), "
-                               "key 5 a wait limit >= 0 (microseconds)");
+                               "key 5 a wait limit >= 0 (microseconds), key 6 the half-list rule (0 or 1)");
 }
 
 int md_query(md_ctx *c, int32_t key, int64_t *value)
@@ -1227,6 +1252,7 @@ int md_query(md_ctx *c, int32_t key, int64_t *value)
     }
     case 11: *value = c->waves_valid ? c->ncol : 0; return MD_OK;
     case 12: *value = c->deps_valid ? (int64_t)c->dag_succ_h.size() : 0; return MD_OK;
+    case 13: *value = c->shell ? 1 : 0; return MD_OK;
     default: return fail(c, MD_ERR_ARG, "query: key 0..11");
     }
 }

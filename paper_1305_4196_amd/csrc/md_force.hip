@@ -257,8 +257,8 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_lj_half(ForceArgs a)
 // One half-list brick task: stages the halo with a sorted index and three
 // binary64 partner-force sums per candidate, walks the brick's lists (own force
 // in registers, -f of each pair added to the partner's LDS sums with binary64
-// LDS atomics between the lanes of the workgroup), then adds every sum to its
-// atom's force in HBM with plain loads and stores.  Correct only while no
+// LDS atomics between the lanes of the workgroup), then adds every non-zero
+// sum to its atom's force in HBM with plain loads and stores.  Correct only while no
 // other task that writes the same atoms runs at the same time (the callers'
 // schedules guarantee it).  Candidates past the LDS stage take global atomics.
 // Energy and virial are per atom (the pairs an atom holds).  Begins with a
@@ -339,11 +339,16 @@ __device__ __forceinline__ void lj_half_task(const ForceArgs &a, const Stage &st
         }
     }
     __syncthreads();
+    // only atoms the task changed are stored: a halo atom that is no partner of
+    // the brick's atoms (the layer below, with the 14-cell half list) may be
+    // written by a task running at the same time
     for (int32_t k = threadIdx.x; k < lim; k += blockDim.x) {
+        const double fx = sx[k], fy = sy[k], fz = sz[k];
+        if (fx == 0.0 && fy == 0.0 && fz == 0.0) continue;
         const int32_t j = st.j[k];
-        a.force[j] += sx[k];
-        a.force[n + j] += sy[k];
-        a.force[2 * n + j] += sz[k];
+        a.force[j] += fx;
+        a.force[n + j] += fy;
+        a.force[2 * n + j] += fz;
     }
 }
 

@@ -135,6 +135,7 @@ struct ListArgs {
     double4 *xref;
     DevCtl *ctl;
 };
+void launch_shell_filter(hipStream_t s, int grid, int threads, const ListArgs &a);
 void launch_build_list(hipStream_t s, int grid, int threads, const ListArgs &a);
 
 // forces

@@ -456,6 +456,70 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_build_list(ListArgs a)
 
 } // namespace
 
+// Half list over 14 of the 27 cells (Sec. II.D.3), from a full list in place:
+// an atom keeps a partner whose cell, seen through the entry's image, lies in
+// the forward half of its neighbourhood -- above in z; at the same z, above in
+// y; at the same z and y, above in x -- or in its own cell with a larger sorted
+// index.  The partner's cell is its halo cell (the record's soff table), moved
+// by the entry's image code (per-entry bits, or the halo cell's image in
+// bricks staged through their images); the offset is taken in whole cells,
+// (o - 1 + t) mod n + s n - (own cell), so the two atoms of a pair see
+// opposite offsets and exactly one keeps it.  Partners then lie in a
+// 3 x 3 x 2 block of cells: the atom's cell and the layer above it in z, one
+// cell around in x and y.  Each lane compacts its own atom's row.
+__global__ __launch_bounds__(TASK_MAX_THREADS) void k_shell_filter(ListArgs a)
+{
+    if (*a.pred == 0) return;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const Stage st = stage_slice(lds_raw, 0, 0, false);
+    const int32_t M = a.M;
+    for (int64_t b = blockIdx.x; b < a.B; b += gridDim.x) {
+        const int32_t *grec = a.brec + b * (int64_t)a.bd.stride;
+        const int32_t natoms = __builtin_amdgcn_readfirstlane(grec[BR_ATOMS]);
+        if (natoms == 0) continue;
+        __syncthreads();
+        for (int32_t t = threadIdx.x; t < a.bd.stride; t += blockDim.x) st.rec[t] = grec[t];
+        __syncthreads();
+        const BrickGeom g = brick_geom(a.reps, a.R, b);
+        const bool shifted = st.rec[BR_SHIFT] != 0;
+        const int32_t *soff = st.rec + br_soff(a.bd), *sbeg = st.rec + br_sbeg(a.bd);
+        const int32_t *himg = st.rec + br_himg(a.bd);
+        for (int32_t la = threadIdx.x; la < natoms; la += blockDim.x) {
+            int32_t e = 0;
+            const int64_t i = brick_atom(st, a.bd, la, &e);
+            const int32_t ci[3] = {g.o[0] + e % g.e[0], g.o[1] + (e / g.e[0]) % g.e[1], g.o[2] + e / (g.e[0] * g.e[1])};
+            const int32_t m = min(a.cnt[i], M);
+            int32_t q = 0;
+            for (int32_t p = 0; p < m; p++) {
+                const uint32_t w = a.nbr[ell_word(i, p, M)];
+                const int32_t k = shifted ? (int32_t)w : (int32_t)(w & MD_IDX_MASK);
+                const int32_t h = halo_cell(st, k);
+                const uint32_t code = shifted ? (uint32_t)himg[h] : (w >> MD_IDX_BITS);
+                const int32_t t[3] = {h % g.hn[0], (h / g.hn[0]) % g.hn[1], h / (g.hn[0] * g.hn[1])};
+                int32_t off[3];
+                for (int d = 0; d < 3; d++) {
+                    const uint32_t c = (code >> (2 * d)) & 3u;
+                    const int32_t sft = c == 2u ? 1 : (c == 1u ? -1 : 0);   // bit 1: partner at x + L
+                    off[d] = (g.o[d] - 1 + t[d] + g.nc[d]) % g.nc[d] + sft * g.nc[d] - ci[d];
+                }
+                const int64_t j = sbeg[h] + (k - soff[h]);
+                const bool fwd = off[2] != 0 ? off[2] > 0
+                               : off[1] != 0 ? off[1] > 0
+                               : off[0] != 0 ? off[0] > 0 : j > i;
+                if (fwd) a.nbr[ell_word(i, q++, M)] = w;
+            }
+            a.cnt[i] = q;
+        }
+    }
+}
+
+void launch_shell_filter(hipStream_t s, int grid, int threads, const ListArgs &a)
+{
+    const size_t lds = stage_bytes(0, 0, false, a.bd.stride);
+    allow_lds(k_shell_filter, lds);
+    hipLaunchKernelGGL(k_shell_filter, dim3(grid), dim3(threads), lds, s, a);
+}
+
 void launch_build_list(hipStream_t s, int grid, int threads, const ListArgs &a)
 {
     const size_t lds = stage_bytes(a.cap, 0, a.half != 0, a.bd.stride);

@@ -13,7 +13,9 @@
 // position once more.
 //
 // Here the tasks are bricks of cells.  A brick writes its halo (its cells and
-// one layer around them); along an axis, two bricks s positions apart have
+// one layer around them; with the 14-cell half list of Sec. II.D.3 no partner
+// lies below an atom's cell, so along z only the layer above: the 3 x 3 x 2
+// overlap); along an axis, two bricks s positions apart have
 // disjoint write sets for s = 2 as soon as bricks are at least two cells wide,
 // and for s = 3 in general; an axis where neither holds (a halo that covers the
 // axis) puts every brick in a set of its own.  The separation is checked on the
@@ -92,21 +94,23 @@ inline bool rings_meet(int a, int la, int b, int lb, int n)
     return ba < la || ab < lb;
 }
 
-// Separation along one axis of nc cells cut into bricks of bd cells.
-inline int axis_separation(int nc, int bd)
+// Separation along one axis of nc cells cut into bricks of bd cells, each
+// writing its cells, `below` layers under them (1, or 0 along z for the
+// 14-cell half list) and one layer above.
+inline int axis_separation(int nc, int bd, int below = 1)
 {
     const int D = (nc + bd - 1) / bd;
     std::vector<int> o(D), len(D);
     for (int p = 0; p < D; p++) {
         o[p] = p * bd;
         const int e = std::min(bd, nc - o[p]);
-        len[p] = std::min(e + 2, nc);
+        len[p] = std::min(e + 1 + below, nc);
     }
     for (int s = 2; s <= 3; s++) {
         bool ok = true;
         for (int p = 0; p < D && ok; p++)
             for (int q = p + 1; q < D && ok; q++)
-                if (cyc(p, q, D) >= s && rings_meet(o[p] - 1 + nc, len[p], o[q] - 1 + nc, len[q], nc)) ok = false;
+                if (cyc(p, q, D) >= s && rings_meet(o[p] - below + nc, len[p], o[q] - below + nc, len[q], nc)) ok = false;
         if (ok) return s;
     }
     return D;
@@ -130,13 +134,14 @@ inline int colour_bricks(const int32_t nb[3], const int sep[3], std::vector<int3
     return w;
 }
 
-// Cells a brick writes along one axis: its halo coordinates (o - 1 + t) mod nc,
-// t = 0 .. min(e + 2, nc) - 1 (the brick's cells and one layer around them).
-inline void axis_write_set(int o, int e, int nc, std::vector<int> &out)
+// Cells a brick writes along one axis: (o - below + t) mod nc,
+// t = 0 .. min(e + 1 + below, nc) - 1 (the brick's cells, `below` layers under
+// them and one above).
+inline void axis_write_set(int o, int e, int nc, int below, std::vector<int> &out)
 {
     out.clear();
-    const int len = std::min(e + 2, nc);
-    for (int t = 0; t < len; t++) out.push_back(((o - 1 + t) % nc + nc) % nc);
+    const int len = std::min(e + 1 + below, nc);
+    for (int t = 0; t < len; t++) out.push_back(((o - below + t) % nc + nc) % nc);
 }
 
 // Dependences between tasks (Sec. II.B): a task waits only for the last earlier
