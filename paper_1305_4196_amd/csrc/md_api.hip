@@ -311,7 +311,7 @@ ListArgs list_args(md_ctx *c, const int32_t *pred, const double4 *src, int half)
 int64_t cap_limit(const md_ctx *c)
 {
     const int64_t room = c->lds_max - 4096 - 4 * (int64_t)c->bd.stride;
-    return std::max<int64_t>(64, room / (int64_t)(4 * sizeof(double)) / 64 * 64);
+    return std::max<int64_t>(64, room / (int64_t)(4 * sizeof(double) + sizeof(uint16_t)) / 64 * 64);
 }
 
 // Brick shape and workgroup size from the mean occupancy `occ` of the
@@ -510,7 +510,7 @@ int fit_wave_stage(md_ctx *c)
     const int64_t room = (int64_t)c->lds_max - 256;
     if ((int64_t)stage_bytes(c->cap, 3, true, c->bd.stride) <= room) return MD_OK;
     if (c->cap_user) return fail(c, MD_ERR_ARG, "wave-scheduled list: the LDS stage set with md_set_tuning is too large");
-    const int64_t fit = (room - 4 * (int64_t)c->bd.stride) / (6 * 8 + 4) / 64 * 64;
+    const int64_t fit = (room - 16 - 4 * (int64_t)c->bd.stride) / (6 * 8 + 4 + 2) / 64 * 64;
     if (fit < 64) return fail(c, MD_ERR_STATE, "wave-scheduled list: brick record leaves no LDS stage");
     c->cap = (int32_t)fit;
     return MD_OK;
@@ -1154,7 +1154,7 @@ int md_set_tuning(md_ctx *c, int32_t key, int32_t value)
 {
     if (c == nullptr) return MD_ERR_ARG;
     // the largest record a brick of at most 64 cells can need
-    const int64_t cap_max = (c->lds_max - 4096 - 4 * (int64_t)br_stride(512, 64)) / (int64_t)(4 * sizeof(double));
+    const int64_t cap_max = (c->lds_max - 4096 - 4 * (int64_t)br_stride(512, 64)) / (int64_t)(4 * sizeof(double) + sizeof(uint16_t));
     if (key == 0 && value >= 64 && value <= 4096 && value % 64 == 0 && value <= cap_max) {
         // the list's entry format depends on which halos fit the stage
         c->cap = value;

@@ -96,11 +96,12 @@ inline void allow_lds(K kernel, size_t bytes)
 
 // dynamic LDS of a task: staged (x, y, z) (binary64, interleaved) of `cap`
 // candidates, `nextra` more binary64 per candidate, their sorted indices
-// (optional) and the brick record
+// (optional), the brick record and the halo cell of each staged candidate
+// (16 bits)
 __host__ __device__ inline size_t stage_bytes(int cap, int nextra, bool with_j, int32_t stride)
 {
     return (size_t)cap * ((3 + nextra) * sizeof(double) + (with_j ? sizeof(int32_t) : 0)) +
-           (size_t)stride * sizeof(int32_t);
+           (size_t)stride * sizeof(int32_t) + (((size_t)cap * sizeof(uint16_t) + 15) & ~(size_t)15);
 }
 
 #ifdef __HIPCC__
@@ -109,7 +110,7 @@ struct Stage {
     double *xyz;        // x, y, z of candidate g at xyz[3g .. 3g+2]
     double *ex;         // extra k of candidate g at ex[k * cap + g] (null if none)
     int32_t *j;         // sorted index of each candidate (null if not staged)
-    int32_t *rec;       // brick record
+    int32_t *rec;       // brick record (then, in brick tasks, the halo cell of each staged candidate)
     int cap;
 };
 
@@ -300,8 +301,17 @@ __device__ __forceinline__ void brick_load(const Stage &s, const BrickDims &d, c
     const bool shifted = s.rec[BR_SHIFT] != 0;
     const RepDesc &rep = reps[s.rec[BR_REP]];
     const double Lx = rep.L[0], Ly = rep.L[1], Lz = rep.L[2];
+    // the halo cell of every staged candidate, one cell per thread, so that
+    // the staging below reads it instead of searching the cell offsets
+    uint16_t *hc = (uint16_t *)(s.rec + d.stride);
+    const int32_t H = s.rec[BR_H];
+    for (int32_t h = threadIdx.x; h < H; h += blockDim.x) {
+        const int32_t b0 = s.rec[BR_HDR + h], b1 = min(s.rec[BR_HDR + h + 1], lim);
+        for (int32_t k = b0; k < b1; k++) hc[k] = (uint16_t)h;
+    }
+    __syncthreads();
     for (int32_t k = threadIdx.x; k < lim; k += blockDim.x) {
-        const int32_t h = halo_cell(s, k);
+        const int32_t h = hc[k];
         const int32_t g = s.rec[br_sbeg(d) + h] + (k - s.rec[BR_HDR + h]);
         const double4 p = pos[g];
         if (shifted) {
