@@ -409,7 +409,10 @@ __device__ __forceinline__ void walk_list(const Stage &s, const BrickDims &d, co
                 dy = dy + image_shift(c, 4u, Ly);
                 dz = dz + image_shift(c, 16u, Lz);
             }
-            const double r2 = (dx * dx + dy * dy) + dz * dz;
+            // fused: one rounding fewer than the list build's r2 (whose pair
+            // sets must equal the oracle's); here r2 only feeds the pair
+            // arithmetic and a cutoff test
+            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
             body(ok, k, dx, dy, dz, r2);
         }
     }
