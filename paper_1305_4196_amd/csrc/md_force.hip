@@ -172,9 +172,33 @@ __device__ __forceinline__ void lj_pair(bool in, double r2, double s2, double e4
     }
 }
 
+// The LJ pair without its energy scale: fs / (24 eps) and V / (4 eps), for
+// sums that take the scale once per atom.
+template <bool MIXED, bool EN = true>
+__device__ __forceinline__ void lj_pair_unit(bool in, double r2, double s2, float s2f, double &fs, double &V)
+{
+    if (MIXED) {
+        const float ir2 = in ? __builtin_amdgcn_rcpf((float)r2) : 0.0f;
+        const float q2 = s2f * ir2;
+        const float q6 = q2 * q2 * q2;
+        const float q12 = q6 * q6;
+        fs = (double)(__builtin_fmaf(2.0f, q12, -q6) * ir2);
+        V = EN ? (double)(q12 - q6) : 0.0;
+    } else {
+        const double ir2 = in ? rcp64(r2) : 0.0;
+        const double q2 = s2 * ir2;
+        const double q6 = q2 * q2 * q2;
+        const double q12 = q6 * q6;
+        fs = (2.0 * q12 - q6) * ir2;
+        V = q12 - q6;
+    }
+}
+
 // ---------------------------------------------------------------- LJ, full list
 // EN: the launch returns energy or virial (steps that record no energy skip
-// their per-pair terms)
+// their per-pair terms).  An atom's sums are taken without the energy scale,
+// which multiplies them once at the end (24 eps for force and virial, 4 eps
+// for the energy).
 template <bool MIXED, bool EN>
 __global__ __launch_bounds__(TASK_MAX_THREADS) void k_lj_full(ForceArgs a)
 {
@@ -184,7 +208,7 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_lj_full(ForceArgs a)
     if (a.flag_clear != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *a.flag_clear = 0;
     const double eps = a.lj[0], sig = a.lj[1];
     const double s2 = sig * sig, e4 = 4.0 * eps, e24 = 24.0 * eps;
-    const float s2f = (float)s2, e4f = (float)e4, e24f = (float)e24;
+    const float s2f = (float)s2;
     const double rc2 = a.rc2;
     double accE = 0.0, accW = 0.0, accK = 0.0;
     BRICK_TASK_BEGIN(st, a.pos, nullptr, nullptr)
@@ -194,7 +218,7 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_lj_full(ForceArgs a)
             walk_list<STAGED, IMG>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
                 [&](bool ok, int32_t, double dx, double dy, double dz, double r2) {
                     double fs, V;
-                    lj_pair<MIXED, EN>(ok && r2 < rc2, r2, s2, e4, e24, s2f, e4f, e24f, fs, V);
+                    lj_pair_unit<MIXED, EN>(ok && r2 < rc2, r2, s2, s2f, fs, V);
                     fx = fma(fs, dx, fx);
                     fy = fma(fs, dy, fy);
                     fz = fma(fs, dz, fz);
@@ -204,7 +228,8 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_lj_full(ForceArgs a)
                     }
                 });
         )
-        if (valid) finish_atom(a, i, xi, fx, fy, fz, 0.5 * e, 0.5 * w, accE, accW, accK);
+        if (valid)
+            finish_atom(a, i, xi, e24 * fx, e24 * fy, e24 * fz, (0.5 * e4) * e, (0.5 * e24) * w, accE, accW, accK);
     BRICK_TASK_END
     finish_block(a, accE, accW, accK, lds);
 }
