@@ -68,7 +68,7 @@ def cpu_baseline(w, steps: int):
     dt = time.perf_counter() - t0
     return {"value": w.n * steps / dt, "unit": "atom-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"{steps} steps of the same {w.n:,}-atom run from its initial state, "
-                      f"including the reference's initial neighbour-list build ({dt:.1f} s)"}
+                      f"including the oracle's initial neighbour-list build ({dt:.1f} s)"}
 
 
 def main():
