@@ -244,7 +244,13 @@ int64_t md_get_task_graph(md_ctx *ctx, int32_t *succ_off, int32_t *succ, int64_t
  *   the one first in the sorted order.  Partners then lie in the atom's cell
  *   and the layer above, so a task writes a 3 x 3 x 2 block of cells per cell
  *   and the waves and task graphs use that stricter overlap.  The list is
- *   built full and filtered.  Drops the current list.
+ *   built full and filtered.  Drops the current list;
+ * key 7 = how the force and adjoint kernels share the bricks among their
+ *   workgroups: 1 static cost-balanced ranges; 2 a queue from which
+ *   workgroups take one brick at a time (better where empty regions leave the
+ *   static ranges uneven); 0 (default) the queue when more than 5 % of the
+ *   cells were empty at the last brick plan, else the static ranges.  Forces
+ *   do not depend on it; energy and virial sums may differ in the last bits.
  * Returns MD_OK or MD_ERR_ARG. */
 int md_set_tuning(md_ctx *ctx, int32_t key, int32_t value);
 
@@ -255,7 +261,8 @@ int md_set_tuning(md_ctx *ctx, int32_t key, int32_t value);
  * sizing pass (both synchronise), 8 LDS bytes a workgroup may use, 9 workgroups
  * of the LJ force grid, 10 entries of the current list (synchronises), 11
  * waves of the current wave schedule (0 if none), 12 edges of the current
- * task graph (0 if none), 13 the half-list rule (key 6).
+ * task graph (0 if none), 13 the half-list rule (key 6), 14 the brick
+ * schedule in use (1 static ranges, 2 queue).
  * Returns MD_OK, MD_ERR_ARG, MD_ERR_STATE (key 10 without a list) or MD_ERR_HIP. */
 int md_query(md_ctx *ctx, int32_t key, int64_t *value);
 

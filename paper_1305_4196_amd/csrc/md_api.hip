@@ -106,6 +106,12 @@ struct md_ctx {
     int64_t *bwork = nullptr;         // [B+1] their prefix
     int64_t bcost_alloc = 0;
     TaskQueue *tq = nullptr;
+    // brick schedule of the force and adjoint kernels: static cost-balanced
+    // ranges, or the queue (systems with empty regions, where the static
+    // ranges leave workgroups idle); sched_mode 0 picks from `sparse`
+    TaskQueue *ftq = nullptr;
+    int32_t sched_mode = 0;
+    bool sparse = false;
     // waves of bricks with disjoint write sets (MD_LIST_WAVES)
     bool waves_valid = false;
     int32_t ncol = 0;
@@ -352,14 +358,15 @@ void choose_shape(md_ctx *c, double occ, int32_t out[4])
 int plan_bricks(md_ctx *c, hipStream_t s)
 {
     int32_t shape[4] = {c->bshape[0], c->bshape[1], c->bshape[2], c->threads_req > 0 ? c->threads_req : 256};
+    std::vector<int32_t> cs(c->C + 1);
+    if (hipMemcpyAsync(cs.data(), c->start, sizeof(int32_t) * (c->C + 1), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(c, MD_ERR_HIP, "brick plan: cell readback");
+    int64_t ne = 0;
+    for (int64_t k = 0; k < c->C; k++) ne += cs[k + 1] > cs[k];
+    // more than 5 % empty cells: a system with voids or vacuum
+    c->sparse = (double)ne < 0.95 * (double)c->C;
     if (shape[0] == 0) {
-        std::vector<int32_t> cs(c->C + 1);
-        if (hipMemcpyAsync(cs.data(), c->start, sizeof(int32_t) * (c->C + 1), hipMemcpyDeviceToHost, s) !=
-                hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
-            return fail(c, MD_ERR_HIP, "brick plan: cell readback");
-        int64_t ne = 0;
-        for (int64_t k = 0; k < c->C; k++) ne += cs[k + 1] > cs[k];
         choose_shape(c, (double)c->n / (double)std::max<int64_t>(1, ne), shape);
         if (c->threads_req > 0) shape[3] = c->threads_req;
     }
@@ -602,6 +609,8 @@ void build_list(md_ctx *c, hipStream_t s, int half, const ListArgs &la)
 ForceArgs force_args(md_ctx *c, const md_potential *p)
 {
     ForceArgs a{};
+    a.ftq = c->ftq;
+    a.dyn = c->sched_mode == 2 || (c->sched_mode == 0 && c->sparse) ? 1 : 0;
     a.n = c->n;
     a.R = c->R;
     a.reps = c->reps;
@@ -746,7 +755,7 @@ int md_create(md_ctx **out, int64_t n, int32_t R, const int64_t *off)
           dalloc(&c->fpp, n) && dalloc(&c->rdot, n);
     ok &= dalloc(&c->u_s, 3 * n) && dalloc(&c->gx_s, 3 * n);
     ok &= dalloc(&c->partial, (size_t)c->max_grid() * 4 * 4) && dalloc(&c->zeros_R, R);
-    ok &= dalloc(&c->reps, R) && dalloc(&c->ctl, 1) && dalloc(&c->one, 1) && dalloc(&c->tq, 1);
+    ok &= dalloc(&c->reps, R) && dalloc(&c->ctl, 1) && dalloc(&c->one, 1) && dalloc(&c->tq, 1) && dalloc(&c->ftq, 1);
     if (!ok) {
         md_destroy(c);
         return MD_ERR_HIP;
@@ -762,6 +771,7 @@ int md_create(md_ctx **out, int64_t n, int32_t R, const int64_t *off)
          hipMemcpy(c->one, &one, sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(c->ctl, &z, sizeof(DevCtl), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(c->tq, &zq, sizeof(TaskQueue), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(c->ftq, &zq, sizeof(TaskQueue), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(c->zeros_R, zr.data(), sizeof(double) * R, hipMemcpyHostToDevice) == hipSuccess;
     if (!ok) {
         md_destroy(c);
@@ -778,7 +788,7 @@ void md_destroy(md_ctx *c)
     dfree(c->pos[0]); dfree(c->pos[1]); dfree(c->pos_t); dfree(c->xref);
     dfree(c->vel); dfree(c->vel_t); dfree(c->force);
     dfree(c->id); dfree(c->id_t); dfree(c->cell_of); dfree(c->slot); dfree(c->perm);
-    dfree(c->count); dfree(c->start); dfree(c->nbr); dfree(c->cnt); dfree(c->rep_of); dfree(c->brec); dfree(c->bcost); dfree(c->bwork); dfree(c->tq); dfree(c->wave_br);
+    dfree(c->count); dfree(c->start); dfree(c->nbr); dfree(c->cnt); dfree(c->rep_of); dfree(c->brec); dfree(c->bcost); dfree(c->bwork); dfree(c->tq); dfree(c->ftq); dfree(c->wave_br);
     dfree(c->dag_off); dfree(c->dag_succ); dfree(c->dag_npred); dfree(c->dag_init); dfree(c->dag_ref); dfree(c->dag_queue);
     dfree(c->eatom); dfree(c->watom); dfree(c->rho); dfree(c->fp); dfree(c->fpp); dfree(c->rdot);
     dfree(c->u_s); dfree(c->gx_s); dfree(c->partial); dfree(c->zeros_R);
@@ -1202,6 +1212,10 @@ int md_set_tuning(md_ctx *c, int32_t key, int32_t value)
         c->wait_us = value;
         return MD_OK;
     }
+    if (key == 7 && value >= 0 && value <= 2) {
+        c->sched_mode = value;
+        return MD_OK;
+    }
     if (key == 6 && (value == 0 || value == 1)) {
         c->shell = value == 1;
         c->have_list = false;
@@ -1211,7 +1225,8 @@ int md_set_tuning(md_ctx *c, int32_t key, int32_t value)
     }
     return fail(c, MD_ERR_ARG, "tuning: key 0 in 64..4096 (multiple of 64, within the LDS), key 1 in 1..8, key 2 in 1..4096, "
                                "key 3 a brick shape, key 4 threads per task (0 or 128..512, multiple of 64), "
-                               "key 5 a wait limit >= 0 (microseconds), key 6 the half-list rule (0 or 1)");
+                               "key 5 a wait limit >= 0 (microseconds), key 6 the half-list rule (0 or 1), "
+                               "key 7 the brick schedule (0 auto, 1 static ranges, 2 queue)");
 }
 
 int md_query(md_ctx *c, int32_t key, int64_t *value)
@@ -1253,6 +1268,7 @@ int md_query(md_ctx *c, int32_t key, int64_t *value)
     case 11: *value = c->waves_valid ? c->ncol : 0; return MD_OK;
     case 12: *value = c->deps_valid ? (int64_t)c->dag_succ_h.size() : 0; return MD_OK;
     case 13: *value = c->shell ? 1 : 0; return MD_OK;
+    case 14: *value = c->sched_mode == 2 || (c->sched_mode == 0 && c->sparse) ? 2 : 1; return MD_OK;
     default: return fail(c, MD_ERR_ARG, "query: key 0..11");
     }
 }

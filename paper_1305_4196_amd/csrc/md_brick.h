@@ -454,15 +454,30 @@ __device__ __forceinline__ int64_t next_brick(TaskQueue *q, int64_t nb, int32_t 
             const int y = (x + d) & 7;
             const int64_t lo = y * per, hi = lo + per < nb ? lo + per : nb;
             if (lo >= hi) continue;
-            const uint32_t seen = __hip_atomic_load(&q->next[y], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t seen = __hip_atomic_load(&q->next[32 * y], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if ((int64_t)seen >= hi - lo) continue;
-            const uint32_t t = atomicAdd(&q->next[y], 1u);
+            const uint32_t t = atomicAdd(&q->next[32 * y], 1u);
             if (lo + (int64_t)t < hi) b = lo + t;
         }
         *slot = (int32_t)b;
     }
     __syncthreads();
-    return *slot;
+    return __builtin_amdgcn_readfirstlane(*slot);
+}
+
+// End of a queue-driven force launch: the last workgroup resets the queue.
+// No fence: every workgroup's last take has returned before it counts itself
+// done, and the launch publishes nothing else through the queue.
+__device__ __forceinline__ void queue_done(TaskQueue *q)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t prev = atomicAdd(&q->done, 1u);
+        if (prev == gridDim.x - 1) {
+            for (int k = 0; k < 8; k++) __hip_atomic_store(&q->next[32 * k], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&q->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
 }
 
 // End of a queue-driven launch: returns true (in every thread) in the last
@@ -476,7 +491,7 @@ __device__ __forceinline__ bool tasks_done(TaskQueue *q)
         const uint32_t prev = atomicAdd(&q->done, 1u);
         last_ = prev == gridDim.x - 1 ? 1 : 0;
         if (last_) {
-            for (int k = 0; k < 8; k++) __hip_atomic_store(&q->next[k], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int k = 0; k < 8; k++) __hip_atomic_store(&q->next[32 * k], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&q->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
@@ -536,15 +551,20 @@ __device__ __forceinline__ BrickRange balanced_bricks(const int64_t *w, int64_t 
 }
 
 // Brick-task loop of the force and adjoint kernels: the workgroup walks its
-// bricks (balanced_bricks), loads each record and stages the halo, then its
+// bricks -- its static cost-balanced ranges (balanced_bricks), or, with a.dyn,
+// bricks taken one at a time from the queue (next_brick: its XCD's share
+// first, then the others') -- loads each record and stages the halo, then its
 // lanes take the brick's atoms (la = a0 + thread) in rounds of blockDim.x.
 // Defines for the body: natoms, rep_r, Lx/Ly/Lz, all_staged, has_img, valid,
 // la, i (sorted index), mm (list length, capped at M).
 #define BRICK_TASK_BEGIN(ST, POS, EXTRA0, EXTRA1)                                          \
-    const BrickRange br_ = balanced_bricks(a.bwork, a.B);                                 \
-    for (int64_t b_ = br_.first; b_ < br_.end; b_ += br_.stride) {                        \
+    const bool dyn_ = a.dyn != 0;                                                         \
+    const BrickRange br_ = dyn_ ? BrickRange{0, a.B, 1} : balanced_bricks(a.bwork, a.B);  \
+    __shared__ int32_t qslot_;                                                            \
+    for (int64_t b_ = dyn_ ? next_brick(a.ftq, a.B, &qslot_) : br_.first; b_ >= 0 && b_ < br_.end; \
+         b_ = dyn_ ? next_brick(a.ftq, a.B, &qslot_) : b_ + br_.stride) {                 \
         const int32_t *grec_ = a.brec + b_ * (int64_t)a.bd.stride;                        \
-        const int32_t natoms = grec_[BR_ATOMS];                                           \
+        const int32_t natoms = __builtin_amdgcn_readfirstlane(grec_[BR_ATOMS]);           \
         if (natoms == 0) continue;                                                        \
         __syncthreads();                                                                  \
         brick_load(ST, a.bd, grec_, a.reps, POS, EXTRA0, EXTRA1);                         \
@@ -561,6 +581,7 @@ __device__ __forceinline__ BrickRange balanced_bricks(const int64_t *w, int64_t 
 
 #define BRICK_TASK_END                                                                    \
         }                                                                                 \
-    }
+    }                                                                                     \
+    if (dyn_) queue_done(a.ftq);
 
 #endif

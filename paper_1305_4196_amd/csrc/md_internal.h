@@ -96,9 +96,9 @@ void launch_copy_back(hipStream_t s, int grid, const int32_t *pred, int64_t n,
 // then from the others' (next[x] counts the bricks handed out of range x).  The
 // last workgroup of a launch resets it.
 struct TaskQueue {
-    uint32_t next[8];
+    uint32_t next[8 * 32];   // counter of range x at next[32 x]: one 128-byte line each
     uint32_t done;
-    uint32_t pad[7];
+    uint32_t pad[31];
 };
 
 // brick record sizes: halo cells and own cells of the largest brick, record stride
@@ -140,6 +140,8 @@ void launch_build_list(hipStream_t s, int grid, int threads, const ListArgs &a);
 
 // forces
 struct ForceArgs {
+    TaskQueue *ftq;       // brick queue of the force and adjoint kernels (dyn = 1)
+    int32_t dyn;          // 1: bricks from the queue; 0: static cost-balanced ranges
     int64_t n;
     int32_t R;
     const RepDesc *reps;      // R entries (device)
