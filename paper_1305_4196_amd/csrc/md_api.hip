@@ -550,7 +550,12 @@ void launch_waves(md_ctx *c, hipStream_t s, bool mixed, ForceArgs a)
 
 // first build: count pass, then size the lists (1.25 x the longest + margin)
 // and the LDS stage (the largest halo seen + 5 %)
-int size_list(md_ctx *c, const double4 *src, int half, hipStream_t s)
+// per_cand: LDS bytes per staged candidate of the kernels that will use the
+// list (xyz, the halo-cell table, extras, sorted indices); callers that do not
+// know the potential pass the largest brick-task layout (EAM, one extra)
+constexpr int STAGE_BYTES_ANY = 3 * 8 + 2 + 8;
+
+int size_list(md_ctx *c, const double4 *src, int half, hipStream_t s, int per_cand)
 {
     if (!c->bricks_valid) {
         int rc = plan_bricks(c, s);
@@ -572,9 +577,10 @@ int size_list(md_ctx *c, const double4 *src, int half, hipStream_t s)
         hipStreamSynchronize(s) != hipSuccess)
         return fail(c, MD_ERR_HIP, "list sizing: readback");
     // LDS stage: the largest halo seen plus 5 %, in multiples of 64, within
-    // half a CU's LDS (larger halos read their last candidates from global memory)
+    // half a CU's LDS for the kernels' layout (larger halos read their last
+    // candidates from global memory)
     if (!c->cap_user) {
-        const int64_t half_cu = ((160 * 1024) / 2 - 512 - 4 * (int64_t)c->bd.stride) / 32 / 64 * 64;
+        const int64_t half_cu = ((160 * 1024) / 2 - 512 - 16 - 4 * (int64_t)c->bd.stride) / per_cand / 64 * 64;
         c->cap = (int32_t)std::max<int64_t>(
             64, std::min<int64_t>(std::min<int64_t>(cap_limit(c), half_cu), ((int64_t)(1.05 * nbhd) + 63) / 64 * 64));
     }
@@ -589,9 +595,10 @@ int size_list(md_ctx *c, const double4 *src, int half, hipStream_t s)
     return MD_OK;
 }
 
-int ensure_list_capacity(md_ctx *c, const double4 *src, int half, hipStream_t s)
+int ensure_list_capacity(md_ctx *c, const double4 *src, int half, hipStream_t s,
+                         int per_cand = STAGE_BYTES_ANY)
 {
-    if (!c->bricks_valid || c->M == 0 || c->need_M > c->M) return size_list(c, src, half, s);
+    if (!c->bricks_valid || c->M == 0 || c->need_M > c->M) return size_list(c, src, half, s, per_cand);
     return MD_OK;
 }
 
@@ -919,7 +926,9 @@ int md_verlet_step(md_ctx *c, const md_potential *p, int32_t precision, int32_t 
     hipLaunchKernelGGL(k_set_ctl, dim3(1), dim3(64), 0, s, c->ctl, 1, 1);
     launch_load_user(s, ga, c->n, pos, vel, c->pos[c->cur], c->vel, c->id);
     sort_into_tmp(c, c->one, true, s);
-    if ((rcode = ensure_list_capacity(c, c->pos_t, builder_half(c, half), s)) != MD_OK) return rcode;
+    // the potential is known here: the stage is sized for its kernels' layout
+    const int per_cand = 3 * 8 + 2 + (p->kind == MD_POT_EAM ? 8 : 0) + (half ? 4 : 0);
+    if ((rcode = ensure_list_capacity(c, c->pos_t, builder_half(c, half), s, per_cand)) != MD_OK) return rcode;
     if (waves && ((rcode = fit_wave_stage(c)) != MD_OK ||
                   (rcode = kind == MD_LIST_DEPS ? plan_deps(c, s) : plan_waves(c, s)) != MD_OK))
         return rcode;
