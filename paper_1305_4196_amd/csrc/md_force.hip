@@ -51,10 +51,13 @@ __device__ __forceinline__ void spl64(const double *tab, double u, int nk, doubl
     fu = c.y + t * (2.0 * c.z + 3.0 * t * c.w);
 }
 
-__device__ __forceinline__ void spl32(const float *tab, double u, int nk, float &f, float &fu)
+// the same in binary32 throughout (the mixed path's pair tables): truncation
+// picks the same segment as floor once clamped to [0, nk-2]
+__device__ __forceinline__ void spl32f(const float *tab, float u, int nk, float &f, float &fu)
 {
-    const int k = seg(u, nk);
-    const float t = (float)(u - (double)k);
+    int k = (int)u;
+    k = k > nk - 2 ? nk - 2 : (k < 0 ? 0 : k);
+    const float t = u - (float)k;
     const float4 c = reinterpret_cast<const float4 *>(tab)[k];
     f = c.x + t * (c.y + t * (c.z + t * c.w));
     fu = c.y + t * (2.0f * c.z + 3.0f * t * c.w);
@@ -549,6 +552,7 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_density(ForceArgs a)
     const Stage st = stage_slice(lds_raw, a.cap, 0, false);
     const int nk = a.nk[1];
     const double x0 = a.x0[1], ih = a.inv_h[1], rrho2 = a.rrho2;
+    const float x0f = (float)x0, ihf = (float)ih;
     BRICK_TASK_BEGIN(st, a.pos, nullptr, nullptr)
         double rho = 0.0;
         const double4 xi = a.pos[i];
@@ -556,15 +560,15 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_density(ForceArgs a)
             walk_list<STAGED, IMG>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
                 [&](bool ok, int32_t, double, double, double, double r2) {
                     const bool in = ok && r2 < rrho2;
-                    const double uu = (sqrt(r2) - x0) * ih;
                     double f;
                     if (MIXED) {
+                        // r and the table argument in binary32, like the table
                         float ff, fu;
-                        spl32(a.tabf[1], uu, nk, ff, fu);
+                        spl32f(a.tabf[1], (__builtin_sqrtf((float)r2) - x0f) * ihf, nk, ff, fu);
                         f = (double)ff;
                     } else {
                         double fu;
-                        spl64(a.tab[1], uu, nk, f, fu);
+                        spl64(a.tab[1], (sqrt(r2) - x0) * ih, nk, f, fu);
                     }
                     rho += in ? f : 0.0;
                 });
@@ -593,6 +597,7 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, (MIXED || !EN) ? 4 : 1) void k_ea
     if (a.flag_clear != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *a.flag_clear = 0;
     const int nkp = a.nk[0], nkr = a.nk[1];
     const double x0p = a.x0[0], ihp = a.inv_h[0], x0r = a.x0[1], ihr = a.inv_h[1];
+    const float x0pf = (float)x0p, ihpf = (float)ihp, x0rf = (float)x0r, ihrf = (float)ihr;
     const double rphi2 = a.rphi2, rrho2 = a.rrho2;
     double accE = 0.0, accW = 0.0, accK = 0.0;
     BRICK_TASK_BEGIN(st, a.pos, a.fp, nullptr)
@@ -604,20 +609,23 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, (MIXED || !EN) ? 4 : 1) void k_ea
                 [&](bool ok, int32_t k, double dx, double dy, double dz, double r2) {
                     const bool in_phi = ok && r2 < rphi2, in_rho = ok && r2 < rrho2;
                     const double fpj = (STAGED || k < st.cap) ? st.ex[k] : a.fp[candidate_index(st, a.bd, k)];
-                    const double r = sqrt(r2);
-                    double gsc, grr, ep;
+                    double gsc, grr, ep, r;
                     if (MIXED) {
-                        // pair scalar in binary32: dV/dr / r with the binary32 reciprocal
+                        // pair scalar in binary32 (r, table arguments, dV/dr / r with
+                        // the binary32 reciprocal); r2 and the cutoff tests stay binary64
+                        const float rf = __builtin_sqrtf((float)r2);
                         float f, fu, g, h;
-                        spl32(a.tabf[0], (r - x0p) * ihp, nkp, f, fu);
-                        spl32(a.tabf[1], (r - x0r) * ihr, nkr, g, h);
-                        const float gp = in_phi ? fu * (float)ihp : 0.0f;
-                        const float gr = in_rho ? (float)(fpi + fpj) * h * (float)ihr : 0.0f;
+                        spl32f(a.tabf[0], (rf - x0pf) * ihpf, nkp, f, fu);
+                        spl32f(a.tabf[1], (rf - x0rf) * ihrf, nkr, g, h);
+                        const float gp = in_phi ? fu * ihpf : 0.0f;
+                        const float gr = in_rho ? (float)(fpi + fpj) * h * ihrf : 0.0f;
                         const float gsf = gp + gr;
                         gsc = (double)gsf;
-                        grr = (double)(gsf * __builtin_amdgcn_rcpf((float)r));
+                        grr = (double)(gsf * __builtin_amdgcn_rcpf(rf));
                         ep = in_phi ? (double)f : 0.0;
+                        r = (double)rf;
                     } else {
+                        r = sqrt(r2);
                         double f, fu, g, h;
                         spl64(a.tab[0], (r - x0p) * ihp, nkp, f, fu);
                         spl64(a.tab[1], (r - x0r) * ihr, nkr, g, h);
