@@ -194,6 +194,25 @@ struct md_ctx {
     }
     // persistent grid of brick tasks (one 256-thread workgroup per brick): as
     // many workgroups per CU as the LDS allows (160 KiB per CU), at most wgpc
+    // workgroups of a brick-task grid whose workgroups take lds_block bytes of LDS
+    int grid_with(size_t lds_block) const
+    {
+        const size_t per_block = lds_block + 512;
+        int per_cu = (int)std::min<size_t>((size_t)wgpc, std::max<size_t>(1, (160 * 1024) / per_block));
+        per_cu = std::max(1, std::min(per_cu, 32 / (threads / 64)));
+        const int64_t g = std::min<int64_t>(B, (int64_t)n_cu * per_cu);
+        return (int)std::max<int64_t>(1, g);
+    }
+    // the mixed density pass also holds its binary32 table in LDS when it fits
+    bool density_table_in_lds(bool mixed, const md_potential *p) const
+    {
+        return mixed && stage_bytes(cap, 0, false, bd.stride) + (size_t)(p->rho.n_knots - 1) * 16 + 256 <= (size_t)lds_max;
+    }
+    int grid_density(bool mixed, const md_potential *p) const
+    {
+        return grid_with(stage_bytes(cap, 0, false, bd.stride) +
+                         (density_table_in_lds(mixed, p) ? (size_t)(p->rho.n_knots - 1) * 16 : 0));
+    }
     int grid_tasks(int nextra, bool with_j) const
     {
         const size_t per_block = stage_bytes(cap, nextra, with_j, bd.stride) + 512;
@@ -616,6 +635,7 @@ void build_list(md_ctx *c, hipStream_t s, int half, const ListArgs &la)
 ForceArgs force_args(md_ctx *c, const md_potential *p)
 {
     ForceArgs a{};
+    a.lds_tab = p->kind == MD_POT_EAM && c->density_table_in_lds(true, p) ? 1 : 0;
     a.ftq = c->ftq;
     a.dyn = c->sched_mode == 2 || (c->sched_mode == 0 && c->sparse) ? 1 : 0;
     a.n = c->n;
@@ -890,7 +910,7 @@ int md_compute_forces(md_ctx *c, const md_potential *p, int32_t precision, doubl
     } else if (p->kind == MD_POT_LJ) {
         launch_lj_full(s, gf, c->threads, mixed, a);
     } else {
-        launch_eam_density(s, gf, c->threads, mixed, a);
+        launch_eam_density(s, c->grid_density(mixed, p), c->threads, mixed, a);
         launch_eam_force(s, gf1, c->threads, mixed, a);
     }
     if (c->R > 1 && (energy != nullptr || virial != nullptr))
@@ -1013,7 +1033,7 @@ int md_verlet_step(md_ctx *c, const md_potential *p, int32_t precision, int32_t 
         } else {
             if (mode == 1) a.outE = a.outK = a.outW = nullptr;
             timed(c, s, c->ev_force, [&] {
-                launch_eam_density(s, gf, c->threads, mixed, a);
+                launch_eam_density(s, c->grid_density(mixed, p), c->threads, mixed, a);
                 launch_eam_force(s, gf1, c->threads, mixed, a);
             });
         }

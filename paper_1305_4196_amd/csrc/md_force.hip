@@ -553,6 +553,15 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_density(ForceArgs a)
     const int nk = a.nk[1];
     const double x0 = a.x0[1], ih = a.inv_h[1], rrho2 = a.rrho2;
     const float x0f = (float)x0, ihf = (float)ih;
+    // the mixed path reads its binary32 density table from LDS when it fits
+    // beside the stage (a.lds_tab), else from global memory
+    float4 *ltab = reinterpret_cast<float4 *>(lds_raw + stage_bytes(a.cap, 0, false, a.bd.stride));
+    const bool lt = MIXED && a.lds_tab != 0;
+    if (lt) {
+        const float4 *g = reinterpret_cast<const float4 *>(a.tabf[1]);
+        for (int32_t t = threadIdx.x; t < nk - 1; t += blockDim.x) ltab[t] = g[t];
+        __syncthreads();
+    }
     BRICK_TASK_BEGIN(st, a.pos, nullptr, nullptr)
         double rho = 0.0;
         const double4 xi = a.pos[i];
@@ -564,7 +573,9 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_density(ForceArgs a)
                     if (MIXED) {
                         // r and the table argument in binary32, like the table
                         float ff, fu;
-                        spl32f(a.tabf[1], (__builtin_sqrtf((float)r2) - x0f) * ihf, nk, ff, fu);
+                        const float uf = (__builtin_sqrtf((float)r2) - x0f) * ihf;
+                        if (lt) spl32f(reinterpret_cast<const float *>(ltab), uf, nk, ff, fu);
+                        else spl32f(a.tabf[1], uf, nk, ff, fu);
                         f = (double)ff;
                     } else {
                         double fu;
@@ -771,7 +782,14 @@ void launch_lj_half(hipStream_t s, int grid, int threads, bool mixed, const Forc
 
 void launch_eam_density(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a)
 {
-    MD_LAUNCH_TASKS(k_eam_density, 0, false)
+    const size_t lds = stage_bytes(a.cap, 0, false, a.bd.stride) + (mixed && a.lds_tab ? (size_t)(a.nk[1] - 1) * 16 : 0);
+    if (mixed) {
+        allow_lds(k_eam_density<true>, lds);
+        hipLaunchKernelGGL((k_eam_density<true>), dim3(grid), dim3(threads), lds, s, a);
+    } else {
+        allow_lds(k_eam_density<false>, lds);
+        hipLaunchKernelGGL((k_eam_density<false>), dim3(grid), dim3(threads), lds, s, a);
+    }
 }
 
 void launch_eam_force(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a)

@@ -141,6 +141,7 @@ void launch_build_list(hipStream_t s, int grid, int threads, const ListArgs &a);
 // forces
 struct ForceArgs {
     TaskQueue *ftq;       // brick queue of the force and adjoint kernels (dyn = 1)
+    int32_t lds_tab;      // mixed EAM density pass: its binary32 table is copied to LDS
     int32_t dyn;          // 1: bricks from the queue; 0: static cost-balanced ranges
     int64_t n;
     int32_t R;

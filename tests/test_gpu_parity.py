@@ -280,6 +280,24 @@ def test_eam_forces_mixed_within_1e5(cells, seed):
     assert E.item() == pytest.approx(Eo, rel=1e-7)
 
 
+def test_eam_mixed_with_a_density_table_too_large_for_lds():
+    """12,001 knots make the binary32 density table 192 KB: the mixed density
+    pass reads it from global memory instead of LDS, with the same result."""
+    w = eam_case(5, 1)
+    w.pot = W.fs_eam_potential(n_knots=12001)
+    s = MDSystem.from_workload(w)
+    F, E, _ = s.forces(B.MD_MIXED)
+    L = w.boxes[0]
+    Fo, Eo, _ = oracle.forces(oracle.wrap(w.pos, L), L, w.pot, skin=w.skin)
+    assert rel(F.cpu().numpy(), Fo) <= MIXED_TOL
+    assert E.item() == pytest.approx(Eo, rel=1e-7)
+    w2 = eam_case(5, 1)
+    s2 = MDSystem.from_workload(w2)
+    F2, _, _ = s2.forces(B.MD_MIXED)
+    Fo2, _, _ = oracle.forces(oracle.wrap(w2.pos, L), L, w2.pot, skin=w2.skin)
+    assert rel(F2.cpu().numpy(), Fo2) <= MIXED_TOL
+
+
 # ---------------------------------------------------------------- velocity Verlet
 @pytest.mark.parametrize("kind", [B.MD_LIST_FULL, B.MD_LIST_HALF])
 def test_verlet_small_lj_fp64(kind):
