@@ -131,6 +131,7 @@ struct md_ctx {
     // half lists over 14 of the 27 cells (built full, then filtered) and the
     // 3 x 3 x 2 task overlap they allow
     bool shell = false;
+    bool eam_seen = false;               // an EAM potential was used with this context
     int64_t wall_khz = 100000;            // device wall clock (kHz)
 
     // atoms (cell-sorted)
@@ -571,8 +572,9 @@ void launch_waves(md_ctx *c, hipStream_t s, bool mixed, ForceArgs a)
 // and the LDS stage (the largest halo seen + 5 %)
 // per_cand: LDS bytes per staged candidate of the kernels that will use the
 // list (xyz, the halo-cell table, extras, sorted indices); callers that do not
-// know the potential pass the largest brick-task layout (EAM, one extra)
-constexpr int STAGE_BYTES_ANY = 3 * 8 + 2 + 8;
+// know the potential pass the largest layout of the potentials the context has
+// seen (LJ with sorted indices: 30; EAM, one extra value: 34)
+inline int stage_bytes_any(const md_ctx *c) { return 3 * 8 + 2 + (c->eam_seen ? 8 : 4); }
 
 int size_list(md_ctx *c, const double4 *src, int half, hipStream_t s, int per_cand)
 {
@@ -599,7 +601,8 @@ int size_list(md_ctx *c, const double4 *src, int half, hipStream_t s, int per_ca
     // half a CU's LDS for the kernels' layout (larger halos read their last
     // candidates from global memory)
     if (!c->cap_user) {
-        const int64_t half_cu = ((160 * 1024) / 2 - 512 - 16 - 4 * (int64_t)c->bd.stride) / per_cand / 64 * 64;
+        // (1 KB kept free for the allocation granularity)
+        const int64_t half_cu = ((160 * 1024) / 2 - 512 - 1024 - 4 * (int64_t)c->bd.stride) / per_cand / 64 * 64;
         c->cap = (int32_t)std::max<int64_t>(
             64, std::min<int64_t>(std::min<int64_t>(cap_limit(c), half_cu), ((int64_t)(1.05 * nbhd) + 63) / 64 * 64));
     }
@@ -614,9 +617,9 @@ int size_list(md_ctx *c, const double4 *src, int half, hipStream_t s, int per_ca
     return MD_OK;
 }
 
-int ensure_list_capacity(md_ctx *c, const double4 *src, int half, hipStream_t s,
-                         int per_cand = STAGE_BYTES_ANY)
+int ensure_list_capacity(md_ctx *c, const double4 *src, int half, hipStream_t s, int per_cand = 0)
 {
+    if (per_cand == 0) per_cand = stage_bytes_any(c);
     if (!c->bricks_valid || c->M == 0 || c->need_M > c->M) return size_list(c, src, half, s, per_cand);
     return MD_OK;
 }
@@ -691,6 +694,7 @@ int check_pot(md_ctx *c, const md_potential *p)
         return MD_OK;
     }
     if (p->kind != MD_POT_EAM) return fail(c, MD_ERR_ARG, "unknown potential kind");
+    c->eam_seen = true;     // later list sizings leave room for the EAM layout
     const md_spline *sp[3] = {&p->phi, &p->rho, &p->embed};
     for (int k = 0; k < 3; k++) {
         if (sp[k]->coef == nullptr || sp[k]->n_knots < 2 || !finite_pos(sp[k]->h) || !isfinite(sp[k]->x0))

@@ -48,7 +48,10 @@
 // atoms of a row group read 1 KiB contiguously.  M is a multiple of 8.
 #pragma once
 
+#include <algorithm>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <unordered_map>
 
 #include "md_internal.h"
@@ -92,6 +95,36 @@ template <typename K>
 inline void allow_lds(K kernel, size_t bytes)
 {
     allow_lds_ptr(reinterpret_cast<const void *>(kernel), bytes);
+}
+
+// At most as many workgroups as the device keeps resident at once (registers,
+// LDS and wavefront slots all counted): a persistent brick-task grid with more
+// would run its surplus after the first ones and double the tail of the static
+// schedules.  Queried once per kernel, block size, LDS size and device.
+inline int resident_grid_ptr(const void *kernel, int grid, int threads, size_t lds)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<const void *, int, size_t, int>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return grid;
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_tuple(kernel, threads, lds, dev);
+    auto it = cache.find(key);
+    if (it == cache.end()) {
+        int occ = 0, ncu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, threads, lds) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || occ <= 0 ||
+            ncu <= 0)
+            return grid;
+        it = cache.emplace(key, occ * ncu).first;
+    }
+    return std::max(1, std::min(grid, it->second));
+}
+
+template <typename K>
+inline int resident_grid(K kernel, int grid, int threads, size_t lds)
+{
+    return resident_grid_ptr(reinterpret_cast<const void *>(kernel), grid, threads, lds);
 }
 
 // dynamic LDS of a task: staged (x, y, z) (binary64, interleaved) of `cap`

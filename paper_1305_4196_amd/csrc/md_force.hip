@@ -750,10 +750,12 @@ __global__ __launch_bounds__(256) void k_replica_sums(const RepDesc *__restrict_
     const size_t lds = stage_bytes(a.cap, NEXTRA, WITH_J, a.bd.stride);                    \
     if (mixed) {                                                                            \
         allow_lds(KERNEL<true>, lds);                                                       \
-        hipLaunchKernelGGL((KERNEL<true>), dim3(grid), dim3(threads), lds, s, a);           \
+        hipLaunchKernelGGL((KERNEL<true>), dim3(resident_grid(KERNEL<true>, grid, threads, lds)), \
+                           dim3(threads), lds, s, a);                                       \
     } else {                                                                                \
         allow_lds(KERNEL<false>, lds);                                                      \
-        hipLaunchKernelGGL((KERNEL<false>), dim3(grid), dim3(threads), lds, s, a);          \
+        hipLaunchKernelGGL((KERNEL<false>), dim3(resident_grid(KERNEL<false>, grid, threads, lds)), \
+                           dim3(threads), lds, s, a);                                       \
     }
 
 } // namespace
@@ -764,7 +766,7 @@ void launch_lj_full(hipStream_t s, int grid, int threads, bool mixed, const Forc
     const bool en = a.outE != nullptr || a.outW != nullptr || a.eatom != nullptr;
     auto go = [&](auto kernel) {
         allow_lds(kernel, lds);
-        hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), lds, s, a);
+        hipLaunchKernelGGL(kernel, dim3(resident_grid(kernel, grid, threads, lds)), dim3(threads), lds, s, a);
     };
     if (mixed) {
         if (en) go(k_lj_full<true, true>);
@@ -785,10 +787,12 @@ void launch_eam_density(hipStream_t s, int grid, int threads, bool mixed, const 
     const size_t lds = stage_bytes(a.cap, 0, false, a.bd.stride) + (mixed && a.lds_tab ? (size_t)(a.nk[1] - 1) * 16 : 0);
     if (mixed) {
         allow_lds(k_eam_density<true>, lds);
-        hipLaunchKernelGGL((k_eam_density<true>), dim3(grid), dim3(threads), lds, s, a);
+        hipLaunchKernelGGL((k_eam_density<true>), dim3(resident_grid(k_eam_density<true>, grid, threads, lds)),
+                           dim3(threads), lds, s, a);
     } else {
         allow_lds(k_eam_density<false>, lds);
-        hipLaunchKernelGGL((k_eam_density<false>), dim3(grid), dim3(threads), lds, s, a);
+        hipLaunchKernelGGL((k_eam_density<false>), dim3(resident_grid(k_eam_density<false>, grid, threads, lds)),
+                           dim3(threads), lds, s, a);
     }
 }
 
@@ -798,7 +802,7 @@ void launch_eam_force(hipStream_t s, int grid, int threads, bool mixed, const Fo
     const bool en = a.outE != nullptr || a.outW != nullptr || a.eatom != nullptr;
     auto go = [&](auto kernel) {
         allow_lds(kernel, lds);
-        hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), lds, s, a);
+        hipLaunchKernelGGL(kernel, dim3(resident_grid(kernel, grid, threads, lds)), dim3(threads), lds, s, a);
     };
     if (mixed) {
         if (en) go(k_eam_force<true, true>);
@@ -822,7 +826,7 @@ void launch_lj_deps(hipStream_t s, int grid, int threads, bool mixed, const Forc
     const size_t lds = stage_bytes(a.cap, 3, true, a.bd.stride);
     auto go = [&](auto kernel) {
         allow_lds(kernel, lds);
-        hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), lds, s, a, d);
+        hipLaunchKernelGGL(kernel, dim3(resident_grid(kernel, grid, threads, lds)), dim3(threads), lds, s, a, d);
     };
     if (mixed) go(k_lj_deps<true>);
     else go(k_lj_deps<false>);

@@ -66,7 +66,8 @@ __device__ __forceinline__ void embed_full(const ForceArgs &a, double rho, doubl
 }
 
 // ---------------------------------------------------------------- LJ
-__global__ __launch_bounds__(TASK_MAX_THREADS) void k_lj_vjp(VjpArgs v)
+// two 512-thread workgroups per CU (at most 128 VGPRs)
+__global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_lj_vjp(VjpArgs v)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ double lds[4 * TASK_MAX_THREADS / 64];
@@ -275,21 +276,21 @@ void launch_lj_vjp(hipStream_t s, int grid, int threads, const VjpArgs &a)
 {
     const size_t lds = stage_bytes(a.f.cap, 0, true, a.f.bd.stride);
     allow_lds(k_lj_vjp, lds);
-    hipLaunchKernelGGL(k_lj_vjp, dim3(grid), dim3(threads), lds, s, a);
+    hipLaunchKernelGGL(k_lj_vjp, dim3(resident_grid(k_lj_vjp, grid, threads, lds)), dim3(threads), lds, s, a);
 }
 
 void launch_eam_vjp_a(hipStream_t s, int grid, int threads, const VjpArgs &a)
 {
     const size_t lds = stage_bytes(a.f.cap, 0, true, a.f.bd.stride);
     allow_lds(k_eam_vjp_a, lds);
-    hipLaunchKernelGGL(k_eam_vjp_a, dim3(grid), dim3(threads), lds, s, a);
+    hipLaunchKernelGGL(k_eam_vjp_a, dim3(resident_grid(k_eam_vjp_a, grid, threads, lds)), dim3(threads), lds, s, a);
 }
 
 void launch_eam_vjp_b(hipStream_t s, int grid, int threads, const VjpArgs &a)
 {
     const size_t lds = stage_bytes(a.f.cap, 0, true, a.f.bd.stride);
     allow_lds(k_eam_vjp_b, lds);
-    hipLaunchKernelGGL(k_eam_vjp_b, dim3(grid), dim3(threads), lds, s, a);
+    hipLaunchKernelGGL(k_eam_vjp_b, dim3(resident_grid(k_eam_vjp_b, grid, threads, lds)), dim3(threads), lds, s, a);
 }
 
 void launch_eam_vjp_embed(hipStream_t s, int grid, const VjpArgs &a)
