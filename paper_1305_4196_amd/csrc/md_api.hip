@@ -1165,12 +1165,15 @@ int64_t md_get_neighbor_list(md_ctx *c, int64_t *start, int32_t *nbr, int64_t ca
         const int32_t H = r[BR_H], E = r[BR_E];
         const int32_t *soff = r + br_soff(c->bd), *sbeg = r + br_sbeg(c->bd);
         const int32_t *aoff = r + br_aoff(c->bd), *abeg = r + br_abeg(c->bd);
+        const bool narrow = r[BR_SHIFT] != 0;
+        const uint16_t *half = reinterpret_cast<const uint16_t *>(words.data());
         for (int32_t e = 0; e < E; e++)
             for (int32_t a = aoff[e]; a < aoff[e + 1]; a++) {
                 const int64_t i = abeg[e] + (a - aoff[e]);
                 const int64_t u = id[i];
                 for (int64_t p = 0; p < len[u]; p++) {
-                    const int32_t k = (int32_t)(words[(size_t)ell_word(i, p, c->M)] & MD_IDX_MASK);
+                    const int32_t k = narrow ? (int32_t)half[(size_t)ell_half(i, p, c->M)]
+                                             : (int32_t)(words[(size_t)ell_word(i, p, c->M)] & MD_IDX_MASK);
                     int32_t h = H - 1;
                     while (h > 0 && soff[h] > k) h--;
                     nbr[start[u] + p] = id[sbeg[h] + (k - soff[h])];

@@ -37,7 +37,8 @@
 // force and adjoint tasks so that they skip the setup):
 //   [BR_TOTAL] candidates  [BR_ATOMS] atoms  [BR_REP] replica  [BR_H] halo cells
 //   [BR_E] own cells  [BR_IMG] 1 if pairs need the per-entry image codes
-//   [BR_SHIFT] 1 if the halo is staged through the cell images (entries carry no code)
+//   [BR_SHIFT] 1 if the halo is staged through the cell images (entries carry no
+//              code and use the narrow 16-bit layout)
 //   soff[Hm+1]  sbeg[Hm]  aoff[Em+1]  abeg[Em]  himg[Hm]
 // (aoff/abeg: the same for the brick's own cells, in x-fastest order; himg:
 // the image code of each halo cell, in the list-entry encoding.)
@@ -45,7 +46,9 @@
 // List layout (interleaved rows): entry p of sorted atom i is word
 //   ((i/64) * M/4 + p/4) * 256 + (i%64) * 4 + p%4
 // so lane i reads its entries four at a time (one 16-byte load) and the 64
-// atoms of a row group read 1 KiB contiguously.  M is a multiple of 8.
+// atoms of a row group read 1 KiB contiguously.  M is a multiple of 8.  Atoms
+// of BR_SHIFT bricks store 16-bit entries in the same rows, eight per 16-byte
+// group (ell_half), and read half the bytes.
 #pragma once
 
 #include <algorithm>
@@ -75,6 +78,16 @@ __host__ __device__ inline int32_t br_stride(int32_t Hm, int32_t Em)
 __host__ __device__ inline int64_t ell_word(int64_t i, int64_t p, int32_t M)
 {
     return (((i >> 6) * (M >> 2) + (p >> 2)) << 8) + ((i & 63) << 2) + (p & 3);
+}
+
+// 16-bit index of entry p of sorted atom i in the narrow layout (bricks with
+// BR_SHIFT = 1, whose entries are bare candidate indices below 65536): the same
+// 16-byte groups hold eight entries, entry p at halfword
+//   ((i/64) * M/4 + p/8) * 512 + (i%64) * 8 + p%8
+// (the first M/8 groups of the atom's rows)
+__host__ __device__ inline int64_t ell_half(int64_t i, int64_t p, int32_t M)
+{
+    return (((i >> 6) * (M >> 2) + (p >> 3)) << 9) + ((i & 63) << 3) + (p & 7);
 }
 
 // allow a kernel to take `bytes` of dynamic LDS (the attribute is set only when a
@@ -274,7 +287,7 @@ __device__ __forceinline__ void brick_setup(const Stage &s, const BrickDims &d, 
         bool img = false;
         for (int k = 0; k < 3; k++) img |= g.nc[k] < 4 || g.e[k] + 2 > g.nc[k];
         rec[BR_IMG] = img ? 1 : 0;
-        rec[BR_SHIFT] = !img && soff[H] <= s.cap ? 1 : 0;
+        rec[BR_SHIFT] = !img && soff[H] <= s.cap && soff[H] <= 65536 ? 1 : 0;
     }
     __syncthreads();
 }
@@ -403,9 +416,43 @@ __device__ __forceinline__ int32_t candidate_j(const Stage &s, const BrickDims &
     return candidate_index(s, d, k);
 }
 
-// Walks the list of one atom four entries at a time, prefetching the next
-// 16-byte group, and calls body(ok, k, j-entry, dx, dy, dz, r2) for every slot;
-// slots past the list's end come with ok = false and a valid dummy candidate.
+// Four list entries: the four positions first, then the four pairs.  Slots
+// at or past `rem` are called with ok = false and candidate 0 (a valid dummy).
+template <bool STAGED, bool IMG, typename Body>
+__device__ __forceinline__ void walk_four(const Stage &s, const BrickDims &d, const double4 *pos,
+                                          const uint32_t es[4], int32_t rem, const double4 &xi,
+                                          double Lx, double Ly, double Lz, Body &body)
+{
+    double px[4], py[4], pz[4];
+    _Pragma("unroll")
+    for (int u = 0; u < 4; u++)
+        candidate_pos<STAGED>(s, d, (int32_t)(IMG ? ((u < rem ? es[u] : 0u) & MD_IDX_MASK) : (u < rem ? es[u] : 0u)),
+                              pos, px[u], py[u], pz[u]);
+    _Pragma("unroll")
+    for (int u = 0; u < 4; u++) {
+        const bool ok = u < rem;
+        const uint32_t en = ok ? es[u] : 0u;
+        const int32_t k = (int32_t)(IMG ? en & MD_IDX_MASK : en);
+        double dx = xi.x - px[u], dy = xi.y - py[u], dz = xi.z - pz[u];
+        if (IMG) {
+            const uint32_t c = en >> MD_IDX_BITS;
+            dx = dx + image_shift(c, 1u, Lx);
+            dy = dy + image_shift(c, 4u, Ly);
+            dz = dz + image_shift(c, 16u, Lz);
+        }
+        // fused: one rounding fewer than the list build's r2 (whose pair
+        // sets must equal the oracle's); here r2 only feeds the pair
+        // arithmetic and a cutoff test
+        const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        body(ok, k, dx, dy, dz, r2);
+    }
+}
+
+// Walks the list of one atom one 16-byte group at a time, with the next two
+// groups in flight, and calls body(ok, k, dx, dy, dz, r2) for every slot; slots
+// past the list's end come with ok = false and a valid dummy candidate.  IMG =
+// false (a brick staged through its cell images) reads the narrow layout:
+// 16-bit entries, eight per group, half the bytes of the 32-bit one.
 template <bool STAGED, bool IMG, typename Body>
 __device__ __forceinline__ void walk_list(const Stage &s, const BrickDims &d, const double4 *pos,
                                           const uint32_t *nbr, int64_t i, int32_t M, int32_t mm,
@@ -413,8 +460,8 @@ __device__ __forceinline__ void walk_list(const Stage &s, const BrickDims &d, co
                                           Body &&body)
 {
     const uint4 *row = reinterpret_cast<const uint4 *>(nbr) + (((i >> 6) * (int64_t)(M >> 2)) << 6) + (i & 63);
-    const int32_t nq = (mm + 3) >> 2;
-    // two groups in flight: the load for group q + 2 is issued while q is used
+    constexpr int PER = IMG ? 4 : 8;
+    const int32_t nq = (mm + PER - 1) / PER;
     uint4 n1 = make_uint4(0u, 0u, 0u, 0u), n2 = n1;
     if (nq > 0) n1 = row[0];
     if (nq > 1) n2 = row[64];
@@ -422,31 +469,19 @@ __device__ __forceinline__ void walk_list(const Stage &s, const BrickDims &d, co
         const uint4 ev = n1;
         n1 = n2;
         if (q + 2 < nq) n2 = row[(int64_t)(q + 2) << 6];
-        const uint32_t es[4] = {ev.x, ev.y, ev.z, ev.w};
-        const int32_t rem = mm - 4 * q;
-        // the four positions first, then the four pairs
-        double px[4], py[4], pz[4];
-        _Pragma("unroll")
-        for (int u = 0; u < 4; u++)
-            candidate_pos<STAGED>(s, d, (int32_t)(IMG ? ((u < rem ? es[u] : 0u) & MD_IDX_MASK) : (u < rem ? es[u] : 0u)),
-                                  pos, px[u], py[u], pz[u]);
-        _Pragma("unroll")
-        for (int u = 0; u < 4; u++) {
-            const bool ok = u < rem;
-            const uint32_t en = ok ? es[u] : 0u;
-            const int32_t k = (int32_t)(IMG ? en & MD_IDX_MASK : en);
-            double dx = xi.x - px[u], dy = xi.y - py[u], dz = xi.z - pz[u];
-            if (IMG) {
-                const uint32_t c = en >> MD_IDX_BITS;
-                dx = dx + image_shift(c, 1u, Lx);
-                dy = dy + image_shift(c, 4u, Ly);
-                dz = dz + image_shift(c, 16u, Lz);
+        const int32_t rem = mm - PER * q;
+        if (IMG) {
+            const uint32_t es[4] = {ev.x, ev.y, ev.z, ev.w};
+            walk_four<STAGED, IMG>(s, d, pos, es, rem, xi, Lx, Ly, Lz, body);
+        } else {
+            // one copy of the pair code for both halves (as many registers
+            // live as in the 32-bit walk)
+            _Pragma("unroll 1")
+            for (int h = 0; h < 2 && rem > 4 * h; h++) {
+                const uint32_t w0 = h != 0 ? ev.z : ev.x, w1 = h != 0 ? ev.w : ev.y;
+                const uint32_t es[4] = {w0 & 0xffffu, w0 >> 16, w1 & 0xffffu, w1 >> 16};
+                walk_four<STAGED, IMG>(s, d, pos, es, rem - 4 * h, xi, Lx, Ly, Lz, body);
             }
-            // fused: one rounding fewer than the list build's r2 (whose pair
-            // sets must equal the oracle's); here r2 only feeds the pair
-            // arithmetic and a cutoff test
-            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-            body(ok, k, dx, dy, dz, r2);
         }
     }
 }

@@ -13,7 +13,8 @@
 // and no atomics are needed (each task owns its lists, Sec. II.C).  An entry
 // holds the candidate index and the pair's image code, except in bricks that
 // stage their halo through the cell images (BR_SHIFT), where the code equals
-// the candidate's halo-cell image and is left out.
+// the candidate's halo-cell image and is left out and the bare index is stored
+// in 16 bits (the narrow layout; half the list's bytes to write and read).
 //
 // The three cells of a stencil row along x are consecutive in the halo order
 // (or, on a grid of at most bx + 1 cells, wrap around it), so each of the 9
@@ -126,8 +127,10 @@ __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, co
     const double hx = rep.hL[0], hy = rep.hL[1], hz = rep.hL[2];
     const double rl2 = a.rl2;
     const int32_t M = a.nbr == nullptr ? 0 : a.M;
-    // bricks staged through their cell images store bare candidate indices
-    const uint32_t cmask = st.rec[BR_SHIFT] != 0 ? 0u : ~0u;
+    // bricks staged through their cell images store bare candidate indices,
+    // 16 bits each (every candidate index is below 65536 there)
+    const bool narrow = st.rec[BR_SHIFT] != 0;
+    const uint32_t cmask = narrow ? 0u : ~0u;
     int32_t tot = 0;
     // the cell's atoms in groups of up to 128 (two per lane)
     for (int32_t g0 = 0; g0 < na_all; g0 += 128) {
@@ -224,8 +227,10 @@ __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, co
                 const double yi = readlane_f64(ay, l);
                 const double zi = readlane_f64(az, l);
                 int32_t ni = t0 == 0 ? 0 : __builtin_amdgcn_readlane(cnt, l);
-                // the atom's row (uniform); entry p at word (p/4) * 256 + p%4 of it
+                // the atom's row (uniform); entry p at word (p/4) * 256 + p%4 of
+                // it, or in the narrow layout at halfword (p/8) * 512 + p%8
                 uint32_t *base = a.nbr + (((i >> 6) * (int64_t)(a.M >> 2)) << 8) + ((i & 63) << 2);
+                uint16_t *base16 = reinterpret_cast<uint16_t *>(a.nbr) + (((i >> 6) * (int64_t)(a.M >> 2)) << 9) + ((i & 63) << 3);
                 _Pragma("unroll")
                 for (int c = 0; c < TILE; c++) {
                     if (c < nch) {
@@ -256,9 +261,14 @@ __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, co
                         if (HALF) mask &= __builtin_amdgcn_ballot_w64(cj[c] > i);
                         if (mask != 0) {
                             const int32_t p = ni + (int32_t)lanes_below(mask);
-                            const uint32_t off = ((uint32_t)p >> 2 << 8) | ((uint32_t)p & 3u);
-                            const uint32_t word = WRAP ? (uint32_t)ck[c] | ((code << MD_IDX_BITS) & cmask) : (uint32_t)ck[c];
-                            if (hit && p < M) base[off] = word;
+                            if (narrow) {
+                                const uint32_t off = ((uint32_t)p >> 3 << 9) | ((uint32_t)p & 7u);
+                                if (hit && p < M) base16[off] = (uint16_t)ck[c];
+                            } else {
+                                const uint32_t off = ((uint32_t)p >> 2 << 8) | ((uint32_t)p & 3u);
+                                const uint32_t word = WRAP ? (uint32_t)ck[c] | ((code << MD_IDX_BITS) & cmask) : (uint32_t)ck[c];
+                                if (hit && p < M) base[off] = word;
+                            }
                             ni += (int32_t)__popcll(mask);
                         }
                     }
@@ -473,6 +483,7 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_shell_filter(ListArgs a)
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const Stage st = stage_slice(lds_raw, 0, 0, false);
     const int32_t M = a.M;
+    uint16_t *nbr16 = reinterpret_cast<uint16_t *>(a.nbr);
     for (int64_t b = blockIdx.x; b < a.B; b += gridDim.x) {
         const int32_t *grec = a.brec + b * (int64_t)a.bd.stride;
         const int32_t natoms = __builtin_amdgcn_readfirstlane(grec[BR_ATOMS]);
@@ -491,7 +502,7 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_shell_filter(ListArgs a)
             const int32_t m = min(a.cnt[i], M);
             int32_t q = 0;
             for (int32_t p = 0; p < m; p++) {
-                const uint32_t w = a.nbr[ell_word(i, p, M)];
+                const uint32_t w = shifted ? (uint32_t)nbr16[ell_half(i, p, M)] : a.nbr[ell_word(i, p, M)];
                 const int32_t k = shifted ? (int32_t)w : (int32_t)(w & MD_IDX_MASK);
                 const int32_t h = halo_cell(st, k);
                 const uint32_t code = shifted ? (uint32_t)himg[h] : (w >> MD_IDX_BITS);
@@ -506,7 +517,11 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_shell_filter(ListArgs a)
                 const bool fwd = off[2] != 0 ? off[2] > 0
                                : off[1] != 0 ? off[1] > 0
                                : off[0] != 0 ? off[0] > 0 : j > i;
-                if (fwd) a.nbr[ell_word(i, q++, M)] = w;
+                if (fwd) {
+                    if (shifted) nbr16[ell_half(i, q, M)] = (uint16_t)w;
+                    else a.nbr[ell_word(i, q, M)] = w;
+                    q++;
+                }
             }
             a.cnt[i] = q;
         }
