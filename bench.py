@@ -178,10 +178,12 @@ def main():
                   "waves": B.md_query(sysm.ctx, 11), "half_rule": "14-cell" if B.md_query(sysm.ctx, 13) else "sorted"}
         tuning["brick"] = "x".join(str((tuning["brick"] >> s) & 255) for s in (0, 8, 16))
         nbar = B.md_query(sysm.ctx, 10) / n
+        # share of the entries stored in 16 bits (the rest take 32)
+        narrow = B.md_query(sysm.ctx, 15) / max(nbar * n, 1)
         results[name] = dict(
             seconds=t1 - t0, atom_steps=n * args.steps / (t1 - t0), rebuilds=int(nreb.item()),
             force_ms_avg=fms / max(fn, 1), force_launches=fn, list_ms_total=lms, list_launches=ln,
-            nbar=nbar, drift=float(np.max(np.abs(etot - etot[0])) / abs(etot[0])),
+            nbar=nbar, narrow=narrow, drift=float(np.max(np.abs(etot - etot[0])) / abs(etot[0])),
             T_end=float(2 * h[-1, 1] / (3 * n - 3)), capacity=cap, tuning=tuning)
         log(f"{name}: {results[name]['atom_steps'] / 1e9:.3f} G atom-steps/s, "
             f"{1e3 * (t1 - t0) / args.steps:.3f} ms/step, force kernel {results[name]['force_ms_avg'] * 1e3:.1f} us, "
@@ -218,11 +220,12 @@ def main():
     # algorithmic lane-ops per atom-step are OPS_LISTED per listed pair plus
     # OPS_INSIDE per pair inside rc, plus OPS_ENERGY per pair inside rc on the
     # steps that record energies; its algorithmic bytes per atom-step are
-    # list 4 nbar + x read 24 + v read/write 48 + x' write 24 + x_ref read 24.
+    # list 2 nbar (16-bit entries; 4 for any entry kept in 32 bits) + x read 24
+    # + v read/write 48 + x' write 24 + x_ref read 24.
     t_s = r["force_ms_avg"] * 1e-3
     nbar = r["nbar"]
     ops_per_atom = OPS_LISTED * nbar + (OPS_INSIDE + OPS_ENERGY / args.thermo) * nbar * inside_frac
-    bytes_per_atom = 4.0 * nbar + 120.0
+    bytes_per_atom = (2.0 * r["narrow"] + 4.0 * (1.0 - r["narrow"])) * nbar + 120.0
     achieved_alu = n * ops_per_atom / t_s / 1e12
     achieved_hbm = n * bytes_per_atom / t_s / 1e9
     traffic = None
@@ -239,7 +242,8 @@ def main():
                 "ops_per_atom_step": round(ops_per_atom, 1), "inside_rc_fraction": round(inside_frac, 4),
                 "hbm": {"achieved": round(achieved_hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(achieved_hbm / HBM_PEAK_GBS, 4),
-                        "bytes_per_atom_step": round(bytes_per_atom, 1)}}
+                        "bytes_per_atom_step": round(bytes_per_atom, 1),
+                        "list_entries_16bit": round(r["narrow"], 4)}}
 
     line = {
         "metric": "atom-steps/s (forces+neighbor rebuild), FP32-mixed vs FP64 path at stated error",

@@ -262,8 +262,11 @@ int md_set_tuning(md_ctx *ctx, int32_t key, int32_t value);
  * of the LJ force grid, 10 entries of the current list (synchronises), 11
  * waves of the current wave schedule (0 if none), 12 edges of the current
  * task graph (0 if none), 13 the half-list rule (key 6), 14 the brick
- * schedule in use (1 static ranges, 2 queue).
- * Returns MD_OK, MD_ERR_ARG, MD_ERR_STATE (key 10 without a list) or MD_ERR_HIP. */
+ * schedule in use (1 static ranges, 2 queue), 15 entries of the current list
+ * stored as 16-bit candidate indices (bricks on axes of at least 4 cells
+ * whose whole halo fits the LDS stage; the others store 32-bit entries with
+ * an image code; synchronises).
+ * Returns MD_OK, MD_ERR_ARG, MD_ERR_STATE (keys 10 and 15 without a list) or MD_ERR_HIP. */
 int md_query(md_ctx *ctx, int32_t key, int64_t *value);
 
 /* Kernel timing with HIP events on the stream of the timed calls.

@@ -1305,7 +1305,27 @@ int md_query(md_ctx *c, int32_t key, int64_t *value)
     case 12: *value = c->deps_valid ? (int64_t)c->dag_succ_h.size() : 0; return MD_OK;
     case 13: *value = c->shell ? 1 : 0; return MD_OK;
     case 14: *value = c->sched_mode == 2 || (c->sched_mode == 0 && c->sparse) ? 2 : 1; return MD_OK;
-    default: return fail(c, MD_ERR_ARG, "query: key 0..11");
+    case 15: {
+        // entries of atoms in bricks whose list uses the 16-bit layout
+        if (!c->have_list) return fail(c, MD_ERR_STATE, "no list");
+        if (c->last != nullptr && hipStreamSynchronize(c->last) != hipSuccess) return fail(c, MD_ERR_HIP, "synchronise");
+        const int32_t stride = c->bd.stride;
+        std::vector<int32_t> cnt(c->n), rec((size_t)(c->B * stride));
+        if (hipMemcpy(cnt.data(), c->cnt, sizeof(int32_t) * c->n, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(rec.data(), c->brec, sizeof(int32_t) * rec.size(), hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(c, MD_ERR_HIP, "list readback");
+        int64_t t = 0;
+        for (int64_t b = 0; b < c->B; b++) {
+            const int32_t *r = &rec[(size_t)(b * stride)];
+            if (r[BR_SHIFT] == 0) continue;
+            const int32_t *aoff = r + br_aoff(c->bd), *abeg = r + br_abeg(c->bd);
+            for (int32_t e = 0; e < r[BR_E]; e++)
+                for (int32_t a = 0; a < aoff[e + 1] - aoff[e]; a++) t += std::min(cnt[(size_t)(abeg[e] + a)], c->M);
+        }
+        *value = t;
+        return MD_OK;
+    }
+    default: return fail(c, MD_ERR_ARG, "query: key 0..15");
     }
 }
 

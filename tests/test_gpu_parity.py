@@ -166,6 +166,36 @@ def test_brick_shapes_lists_and_forces(name, shape, cap):
     assert user_pairs(*s.neighbor_list()) == user_pairs(hs, hn)
 
 
+# entry width per brick: 16 bits where the halo is staged through the cell
+# images (7 cells per axis, whole halo in LDS), 32 bits with an image code
+# where an axis has 4 cells, and both in one list where the stage holds the
+# halo of the smaller edge bricks only
+@pytest.mark.parametrize("name,cap,width", [("ragged_6859", 0, "16"), ("fcc2048_thermal", 0, "32"),
+                                            ("ragged_6859", 64, "32"), ("ragged_6859", 1664, "both")])
+@pytest.mark.parametrize("kind", [B.MD_LIST_FULL, B.MD_LIST_HALF])
+def test_list_entry_width(name, cap, width, kind):
+    w = materialise(lj_cases()[name])
+    L = w.boxes[0]
+    x = oracle.wrap(w.pos, L)
+    s = shaped_system(w, (4, 3, 2), cap)
+    s.build(kind)
+    total, narrow = B.md_query(s.ctx, 10), B.md_query(s.ctx, 15)
+    if width == "16":
+        assert narrow == total > 0
+    elif width == "32":
+        assert narrow == 0
+    else:
+        assert 0 < narrow < total
+    start, nbr = s.neighbor_list()
+    os_, on = oracle.neighbor_list(x, L, w.pot.rc + w.skin, full=(kind == B.MD_LIST_FULL))
+    assert user_pairs(start, nbr) == user_pairs(os_, on)
+    Fo, Eo, Wo = oracle.forces(x, L, w.pot, skin=w.skin)
+    for prec, tol in ((B.MD_FP64, FP64_TOL), (B.MD_MIXED, MIXED_TOL)):
+        F, E, _ = s.forces(prec, kind, rebuild=False)
+        assert rel(F.cpu().numpy(), Fo) <= tol
+        assert E.item() == pytest.approx(Eo, rel=10 * tol)
+
+
 @pytest.mark.parametrize("kind", [B.MD_LIST_FULL, B.MD_LIST_HALF])
 @pytest.mark.parametrize("shape,cap", [((1, 1, 1), 0), ((2, 2, 2), 256)])
 def test_dense_cells_lists(kind, shape, cap):
