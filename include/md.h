@@ -250,7 +250,13 @@ int64_t md_get_task_graph(md_ctx *ctx, int32_t *succ_off, int32_t *succ, int64_t
  *   workgroups take one brick at a time (better where empty regions leave the
  *   static ranges uneven); 0 (default) the queue when more than 5 % of the
  *   cells were empty at the last brick plan, else the static ranges.  Forces
- *   do not depend on it; energy and virial sums may differ in the last bits.
+ *   do not depend on it; energy and virial sums may differ in the last bits;
+ * key 8 = most intervals of each EAM table whose parameter gradient a
+ *   workgroup of md_force_vjp sums in LDS before adding it to g_params: -1
+ *   (default) as many as fit beside the stage (the last intervals of the phi
+ *   and rho tables, where the pairs fall, and the embedding table when it
+ *   fits whole); 0 none (every term a global atomic).  The gradient does not
+ *   depend on it beyond the summation order.
  * Returns MD_OK or MD_ERR_ARG. */
 int md_set_tuning(md_ctx *ctx, int32_t key, int32_t value);
 

@@ -111,6 +111,7 @@ struct md_ctx {
     // ranges leave workgroups idle); sched_mode 0 picks from `sparse`
     TaskQueue *ftq = nullptr;
     int32_t sched_mode = 0;
+    int32_t gwin_limit = -1;   // most table intervals the EAM adjoint sums in LDS (-1: as many as fit)
     bool sparse = false;
     // waves of bricks with disjoint write sets (MD_LIST_WAVES)
     bool waves_valid = false;
@@ -1111,8 +1112,8 @@ int md_force_vjp(md_ctx *c, const md_potential *p, int32_t precision, const doub
             launch_zero(s, 64, g_params, total);
         }
         launch_eam_vjp_a(s, gh, c->threads, v);
-        launch_eam_vjp_b(s, gh, c->threads, v);
-        if (g_params != nullptr) launch_eam_vjp_embed(s, ga, v);
+        launch_eam_vjp_b(s, gh, c->threads, v, c->lds_max, c->gwin_limit);
+        if (g_params != nullptr) launch_eam_vjp_embed(s, ga, v, c->lds_max, c->gwin_limit);
     }
     if (g_pos != nullptr) launch_to_user(s, ga, c->n, c->id, c->gx_s, g_pos);
     return check_hip(c, "md_force_vjp");
@@ -1252,6 +1253,10 @@ int md_set_tuning(md_ctx *c, int32_t key, int32_t value)
         c->sched_mode = value;
         return MD_OK;
     }
+    if (key == 8 && value >= -1) {
+        c->gwin_limit = value;
+        return MD_OK;
+    }
     if (key == 6 && (value == 0 || value == 1)) {
         c->shell = value == 1;
         c->have_list = false;
@@ -1262,7 +1267,8 @@ int md_set_tuning(md_ctx *c, int32_t key, int32_t value)
     return fail(c, MD_ERR_ARG, "tuning: key 0 in 64..4096 (multiple of 64, within the LDS), key 1 in 1..8, key 2 in 1..4096, "
                                "key 3 a brick shape, key 4 threads per task (0 or 128..512, multiple of 64), "
                                "key 5 a wait limit >= 0 (microseconds), key 6 the half-list rule (0 or 1), "
-                               "key 7 the brick schedule (0 auto, 1 static ranges, 2 queue)");
+                               "key 7 the brick schedule (0 auto, 1 static ranges, 2 queue), "
+                               "key 8 the EAM adjoint's LDS intervals (>= -1)");
 }
 
 int md_query(md_ctx *c, int32_t key, int64_t *value)

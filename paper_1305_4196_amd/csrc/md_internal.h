@@ -225,11 +225,15 @@ struct VjpArgs {
     double *rdot;             // EAM pass A output
     double *fpp;              // EAM F''
     double *gout;             // LJ: 2 doubles out (final)
+    int32_t gw_p, gw_r;       // EAM: trailing intervals of the phi and rho tables whose
+                              // parameter gradient a workgroup sums in LDS first
+                              // (embedding pass: gw_p = intervals of its table, or 0)
+    int32_t gw_off;           // byte offset of those sums in the dynamic LDS
 };
 void launch_lj_vjp(hipStream_t s, int grid, int threads, const VjpArgs &a);
 void launch_eam_vjp_a(hipStream_t s, int grid, int threads, const VjpArgs &a);
-void launch_eam_vjp_b(hipStream_t s, int grid, int threads, const VjpArgs &a);
-void launch_eam_vjp_embed(hipStream_t s, int grid, const VjpArgs &a);
+void launch_eam_vjp_b(hipStream_t s, int grid, int threads, const VjpArgs &a, int32_t lds_max, int32_t limit);
+void launch_eam_vjp_embed(hipStream_t s, int grid, const VjpArgs &a, int32_t lds_max, int32_t limit);
 
 // ---------------------------------------------------------------- device helpers
 #ifdef __HIPCC__

@@ -174,6 +174,14 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_vjp_b(VjpArgs v)
     const double rphi2 = a.rphi2, rrho2 = a.rrho2;
     double *gphi = v.gtab;
     double *grho = v.gtab + 4 * (int64_t)(nkp - 1);
+    // the last gw_p (gw_r) intervals of the phi (rho) table, where the pairs of
+    // a crystal fall, are summed in LDS and added to the gradient once per
+    // workgroup; pairs below them add to it directly
+    const int32_t wp = v.gtab != nullptr ? v.gw_p : 0, wr = v.gtab != nullptr ? v.gw_r : 0;
+    const int32_t kp0 = nkp - 1 - wp, kr0 = nkr - 1 - wr;
+    double *lphi = reinterpret_cast<double *>(lds_raw + v.gw_off), *lrho = lphi + 4 * wp;
+    for (int32_t t = threadIdx.x; t < 4 * (wp + wr); t += blockDim.x) lphi[t] = 0.0;
+    __syncthreads();
     BRICK_TASK_BEGIN(st, a.pos, nullptr, nullptr)
         double F[3] = {0.0, 0.0, 0.0}, Hu[3] = {0.0, 0.0, 0.0};
         const double vE = v.vE[rep_r];
@@ -219,16 +227,24 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_vjp_b(VjpArgs v)
                             const double t2 = tp * tp;
                             const double pw[4] = {1.0, tp, t2, t2 * tp};
                             const double dp[4] = {0.0, 1.0, 2.0 * tp, 3.0 * t2};
-                            for (int p = 0; p < 4; p++)
-                                atomicAdd(&gphi[4 * (int64_t)kp + p], vE * pw[p] - s * dp[p] * ihp);
+                            double gv[4];
+                            for (int p = 0; p < 4; p++) gv[p] = vE * pw[p] - s * dp[p] * ihp;
+                            // separate branches keep LDS and global atomics apart (no flat atomics)
+                            if (kp >= kp0)
+                                for (int p = 0; p < 4; p++) atomicAdd(&lphi[4 * (kp - kp0) + p], gv[p]);
+                            else
+                                for (int p = 0; p < 4; p++) atomicAdd(&gphi[4 * (int64_t)kp + p], gv[p]);
                         }
                         if (in_rho) {
                             const double t2 = tr * tr;
                             const double pw[4] = {1.0, tr, t2, t2 * tr};
                             const double dp[4] = {0.0, 1.0, 2.0 * tr, 3.0 * t2};
-                            for (int p = 0; p < 4; p++)
-                                atomicAdd(&grho[4 * (int64_t)kr + p],
-                                          vE * Fs * pw[p] - (s * Fs * dp[p] * ihr + qq * pw[p]));
+                            double gv[4];
+                            for (int p = 0; p < 4; p++) gv[p] = vE * Fs * pw[p] - (s * Fs * dp[p] * ihr + qq * pw[p]);
+                            if (kr >= kr0)
+                                for (int p = 0; p < 4; p++) atomicAdd(&lrho[4 * (kr - kr0) + p], gv[p]);
+                            else
+                                for (int p = 0; p < 4; p++) atomicAdd(&grho[4 * (int64_t)kr + p], gv[p]);
                         }
                     }
                 });
@@ -236,16 +252,28 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_vjp_b(VjpArgs v)
         if (valid)
             for (int c = 0; c < 3; c++) v.gx[c * n + i] = -vE * F[c] - Hu[c];
     BRICK_TASK_END
+    __syncthreads();
+    for (int32_t t = threadIdx.x; t < 4 * wp; t += blockDim.x)
+        if (lphi[t] != 0.0) atomicAdd(&gphi[4 * (int64_t)kp0 + t], lphi[t]);
+    for (int32_t t = threadIdx.x; t < 4 * wr; t += blockDim.x)
+        if (lrho[t] != 0.0) atomicAdd(&grho[4 * (int64_t)kr0 + t], lrho[t]);
 }
 
 // embedding-table gradient: one entry per atom
 __global__ __launch_bounds__(256) void k_eam_vjp_embed(VjpArgs v)
 {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
     const ForceArgs &a = v.f;
     const int64_t n = a.n;
     const int nkp = a.nk[0], nkr = a.nk[1];
     double *gemb = v.gtab + 4 * (int64_t)(nkp - 1) + 4 * (int64_t)(nkr - 1);
     const double ih = a.inv_h[2];
+    // with gw_p > 0 the workgroup sums the whole embedding table's gradient in
+    // LDS (gw_p = its intervals) and adds it once at the end
+    const int32_t wf = v.gw_p;
+    double *lemb = reinterpret_cast<double *>(lds_raw);
+    for (int32_t t = threadIdx.x; t < 4 * wf; t += blockDim.x) lemb[t] = 0.0;
+    __syncthreads();
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         double F, Fp, Fpp, t;
@@ -265,9 +293,13 @@ __global__ __launch_bounds__(256) void k_eam_vjp_embed(VjpArgs v)
                 dF = tp;
                 dFp = dtp * ih;
             }
-            atomicAdd(&gemb[4 * (int64_t)k + p], vE * dF - rd * dFp);
+            if (wf > 0) atomicAdd(&lemb[4 * k + p], vE * dF - rd * dFp);
+            else atomicAdd(&gemb[4 * (int64_t)k + p], vE * dF - rd * dFp);
         }
     }
+    __syncthreads();
+    for (int32_t t = threadIdx.x; t < 4 * wf; t += blockDim.x)
+        if (lemb[t] != 0.0) atomicAdd(&gemb[t], lemb[t]);
 }
 
 } // namespace
@@ -286,14 +318,48 @@ void launch_eam_vjp_a(hipStream_t s, int grid, int threads, const VjpArgs &a)
     hipLaunchKernelGGL(k_eam_vjp_a, dim3(resident_grid(k_eam_vjp_a, grid, threads, lds)), dim3(threads), lds, s, a);
 }
 
-void launch_eam_vjp_b(hipStream_t s, int grid, int threads, const VjpArgs &a)
+// The parameter-gradient sums in LDS take what the workgroups that fit on a CU
+// leave of its LDS (lds_max, the LDS of one CU; the kernel's registers allow one
+// 512-thread workgroup per CU): as many trailing intervals of each pair table
+// as fit, none when the stage alone fills it.
+void launch_eam_vjp_b(hipStream_t s, int grid, int threads, const VjpArgs &a0, int32_t lds_max, int32_t limit)
 {
-    const size_t lds = stage_bytes(a.f.cap, 0, true, a.f.bd.stride);
+    VjpArgs a = a0;
+    const size_t stage = (stage_bytes(a.f.cap, 0, true, a.f.bd.stride) + 15) & ~(size_t)15;
+    size_t lds = stage;
+    a.gw_p = a.gw_r = 0;
+    a.gw_off = (int32_t)stage;
+    if (a.gtab != nullptr) {
+        allow_lds(k_eam_vjp_b, stage);
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_eam_vjp_b, threads, stage) != hipSuccess || occ < 1) occ = 1;
+        // 256 bytes stay free for the kernel's static LDS
+        const int64_t room = (int64_t)lds_max / occ - 256 - (int64_t)stage;
+        int64_t w = room > 0 ? room / 64 : 0;                       // 32 bytes per interval and table
+        if (limit >= 0) w = std::min<int64_t>(w, limit);
+        a.gw_p = (int32_t)std::min<int64_t>(w, a.f.nk[0] - 1);
+        a.gw_r = (int32_t)std::min<int64_t>(w, a.f.nk[1] - 1);
+        lds = stage + 32 * (size_t)(a.gw_p + a.gw_r);
+    }
     allow_lds(k_eam_vjp_b, lds);
     hipLaunchKernelGGL(k_eam_vjp_b, dim3(resident_grid(k_eam_vjp_b, grid, threads, lds)), dim3(threads), lds, s, a);
 }
 
-void launch_eam_vjp_embed(hipStream_t s, int grid, const VjpArgs &a)
+// The whole embedding table's gradient goes to LDS when it fits two 256-thread
+// workgroups per CU and the limit allows the whole table (then the grid is the
+// resident one, each workgroup striding over many atoms); otherwise every term
+// is a global atomic.
+void launch_eam_vjp_embed(hipStream_t s, int grid, const VjpArgs &a0, int32_t lds_max, int32_t limit)
 {
+    VjpArgs a = a0;
+    a.gw_p = 0;
+    const int32_t nk = a.f.nk[2];
+    const size_t lds = 32 * (size_t)(nk - 1);
+    if ((int64_t)lds <= (int64_t)lds_max / 2 - 256 && (limit < 0 || limit >= nk - 1)) {
+        a.gw_p = nk - 1;
+        allow_lds(k_eam_vjp_embed, lds);
+        hipLaunchKernelGGL(k_eam_vjp_embed, dim3(resident_grid(k_eam_vjp_embed, grid, 256, lds)), dim3(256), lds, s, a);
+        return;
+    }
     hipLaunchKernelGGL(k_eam_vjp_embed, dim3(grid), dim3(256), 0, s, a);
 }

@@ -20,9 +20,10 @@ def flat_params(pot):
                         dtype=torch.float64, device="cuda")
 
 
-def make_fit(kind, n_replicas):
+def make_fit(kind, n_replicas, window=-1):
     w = W.replica_batch(kind, n_replicas=n_replicas, nmin=200, nmax=1200)
     s = MDSystem.from_workload(w)
+    B.md_set_tuning(s.ctx, 8, window)
     F_star, _, _ = s.forces(B.MD_FP64)                      # targets at the reference parameters
     start = W.perturb_params(w.pot)
     fit = BatchedFit(s, F_star, flat_params(start))
@@ -69,9 +70,10 @@ def test_graph_replays_match_eager(kind):
             assert torch.allclose(g, g_eager, rtol=1e-12, atol=1e-14 * float(g_eager.abs().max()))
 
 
-@pytest.mark.parametrize("kind", ["lj", "eam"])
-def test_batch_gradient_matches_oracle(kind):
-    w, s, start, fit = make_fit(kind, 8 if kind == "eam" else 12)
+# (EAM also with its parameter gradient summed without LDS, key 8 = 0)
+@pytest.mark.parametrize("kind,window", [("lj", -1), ("eam", -1), ("eam", 0)])
+def test_batch_gradient_matches_oracle(kind, window):
+    w, s, start, fit = make_fit(kind, 8 if kind == "eam" else 12, window)
     g = fit.gradient().cpu().numpy()
     go = oracle_gradient(w, w.pot, fit.F_star.cpu().numpy(), start)
     assert np.linalg.norm(g - go) <= 1e-10 * np.linalg.norm(go)

@@ -466,10 +466,17 @@ def test_lj_vjp_matches_oracle():
     assert np.allclose(gp.cpu().numpy(), gpo, rtol=1e-11)
 
 
-def test_eam_vjp_matches_oracle():
+# key 8: the parameter gradient summed in LDS for every interval (-1; the
+# stage of this case leaves room for whole tables), for none (0), or for the
+# last 400 intervals of the pair tables only (the second neighbour shell; the
+# first lies below them and, with the whole embedding table, goes to the
+# gradient directly)
+@pytest.mark.parametrize("window", [-1, 0, 400])
+def test_eam_vjp_matches_oracle(window):
     w = eam_case(5, 7, sd=0.08)
     L = w.boxes[0]
     s = MDSystem.from_workload(w)
+    B.md_set_tuning(s.ctx, 8, window)
     g = np.random.default_rng(21)
     u = g.normal(size=w.pos.shape)
     vE = -0.4
