@@ -321,7 +321,8 @@ void launch_eam_vjp_a(hipStream_t s, int grid, int threads, const VjpArgs &a)
 // The parameter-gradient sums in LDS take what the workgroups that fit on a CU
 // leave of its LDS (lds_max, the LDS of one CU; the kernel's registers allow one
 // 512-thread workgroup per CU): as many trailing intervals of each pair table
-// as fit, none when the stage alone fills it.
+// as fit, none when the stage alone fills it.  Smaller workgroups would fit
+// several per CU; then the LDS request may leave fewer of them resident.
 void launch_eam_vjp_b(hipStream_t s, int grid, int threads, const VjpArgs &a0, int32_t lds_max, int32_t limit)
 {
     VjpArgs a = a0;
@@ -333,9 +334,17 @@ void launch_eam_vjp_b(hipStream_t s, int grid, int threads, const VjpArgs &a0, i
         allow_lds(k_eam_vjp_b, stage);
         int occ = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_eam_vjp_b, threads, stage) != hipSuccess || occ < 1) occ = 1;
-        // 256 bytes stay free for the kernel's static LDS
-        const int64_t room = (int64_t)lds_max / occ - 256 - (int64_t)stage;
-        int64_t w = room > 0 ? room / 64 : 0;                       // 32 bytes per interval and table
+        // fewer workgroups per CU when that is what it takes to hold the upper
+        // half of the larger pair table (global atomics on the hot intervals
+        // cost far more than the lost occupancy); 256 bytes stay free for the
+        // kernel's static LDS; 32 bytes per interval and table
+        const int64_t want = (std::max(a.f.nk[0], a.f.nk[1]) - 1) / 2;
+        int64_t w = 0;
+        for (; occ >= 1; occ--) {
+            const int64_t room = (int64_t)lds_max / occ - 256 - (int64_t)stage;
+            w = room > 0 ? room / 64 : 0;
+            if (w >= want) break;
+        }
         if (limit >= 0) w = std::min<int64_t>(w, limit);
         a.gw_p = (int32_t)std::min<int64_t>(w, a.f.nk[0] - 1);
         a.gw_r = (int32_t)std::min<int64_t>(w, a.f.nk[1] - 1);
