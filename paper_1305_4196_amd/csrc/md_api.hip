@@ -785,7 +785,7 @@ int md_create(md_ctx **out, int64_t n, int32_t R, const int64_t *off)
           dalloc(&c->perm, n) && dalloc(&c->cnt, n) && dalloc(&c->rep_of, n);
     ok &= dalloc(&c->eatom, n) && dalloc(&c->watom, n) && dalloc(&c->rho, n) && dalloc(&c->fp, n) &&
           dalloc(&c->fpp, n) && dalloc(&c->rdot, n);
-    ok &= dalloc(&c->u_s, 3 * n) && dalloc(&c->gx_s, 3 * n);
+    ok &= dalloc(&c->u_s, 4 * n) && dalloc(&c->gx_s, 3 * n);
     ok &= dalloc(&c->partial, (size_t)c->max_grid() * 4 * 4) && dalloc(&c->zeros_R, R);
     ok &= dalloc(&c->reps, R) && dalloc(&c->ctl, 1) && dalloc(&c->one, 1) && dalloc(&c->tq, 1) && dalloc(&c->ftq, 1);
     if (!ok) {
@@ -1090,11 +1090,11 @@ int md_force_vjp(md_ctx *c, const md_potential *p, int32_t precision, const doub
     if (pos != nullptr)
         hipLaunchKernelGGL(k_pos_from_user, dim3(ga), dim3(256), 0, s, c->n, c->reps, c->rep_of, c->id,
                            pos, c->xref, c->pos[c->cur]);
-    launch_from_user(s, ga, c->n, c->id, u, c->u_s);
+    launch_from_user(s, ga, c->n, c->id, u, reinterpret_cast<double4 *>(c->u_s));
     VjpArgs v{};
     v.f = force_args(c, p);
     v.f.done = &c->ctl->done[3];
-    v.u = c->u_s;
+    v.u = reinterpret_cast<const double4 *>(c->u_s);
     v.vE = vE != nullptr ? vE : c->zeros_R;
     v.gx = c->gx_s;
     v.gpart = c->partial + (size_t)c->max_grid() * 12;

@@ -684,15 +684,15 @@ __global__ void k_to_user(int64_t n, const int32_t *__restrict__ id, const doubl
     }
 }
 
+// user-ordered [3][n] -> sorted (x, y, z, 0) per atom: a kernel that gathers
+// the vector of a partner reads one 32-byte record instead of three arrays
 __global__ void k_from_user(int64_t n, const int32_t *__restrict__ id, const double *__restrict__ src,
-                            double *__restrict__ dst)
+                            double4 *__restrict__ dst)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t u = id[i];
-        dst[i] = src[u];
-        dst[n + i] = src[n + u];
-        dst[2 * n + i] = src[2 * n + u];
+        dst[i] = make_double4(src[u], src[n + u], src[2 * n + u], 0.0);
     }
 }
 
@@ -861,9 +861,9 @@ void launch_to_user(hipStream_t s, int grid, int64_t n, const int32_t *id, const
 }
 
 void launch_from_user(hipStream_t s, int grid, int64_t n, const int32_t *id,
-                      const double *src_user, double *dst3)
+                      const double *src_user, double4 *dst)
 {
-    hipLaunchKernelGGL(k_from_user, dim3(grid), dim3(256), 0, s, n, id, src_user, dst3);
+    hipLaunchKernelGGL(k_from_user, dim3(grid), dim3(256), 0, s, n, id, src_user, dst);
 }
 
 void launch_pos_to_user(hipStream_t s, int grid, int64_t n, int32_t R, const RepDesc *reps,

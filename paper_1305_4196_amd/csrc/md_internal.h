@@ -211,13 +211,13 @@ void launch_pos_to_user(hipStream_t s, int grid, int64_t n, int32_t R, const Rep
                         const int32_t *rep_of, const int32_t *id, const double4 *pos,
                         double *dst_user);
 void launch_from_user(hipStream_t s, int grid, int64_t n, const int32_t *id,
-                      const double *src_user, double *dst3);
+                      const double *src_user, double4 *dst);
 void launch_tables_f32(hipStream_t s, const double *src, float *dst, int64_t m);
 
 // adjoint
 struct VjpArgs {
     ForceArgs f;
-    const double *u;          // [3][n] sorted cotangent
+    const double4 *u;         // [n] sorted cotangent (x, y, z, 0)
     const double *vE;         // [R]
     double *gx;               // [3][n] sorted out
     double *gpart;            // LJ: [grid][4] parameter partials

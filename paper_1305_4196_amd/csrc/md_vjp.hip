@@ -82,7 +82,8 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_lj_vjp(VjpArgs v)
         double F[3] = {0.0, 0.0, 0.0}, Hu[3] = {0.0, 0.0, 0.0};
         const double vE = v.vE[rep_r];
         const double4 xi = a.pos[i];
-        const double ui[3] = {v.u[i], v.u[n + i], v.u[2 * n + i]};
+        const double4 ui4 = v.u[i];
+        const double ui[3] = {ui4.x, ui4.y, ui4.z};
         STAGE_IMG_SPLIT(all_staged, has_img,
             walk_list<STAGED, IMG>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
                 [&](bool ok, int32_t k, double dx, double dy, double dz, double r2) {
@@ -96,17 +97,19 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_lj_vjp(VjpArgs v)
                     const double fs = 24.0 * eps * (2.0 * q12 - q6) * ir2;
                     const double B = -fs;
                     const double C = 96.0 * eps * (7.0 * q12 - 2.0 * q6) * (ir2 * ir2);
-                    const double uij[3] = {ui[0] - v.u[j], ui[1] - v.u[n + j], ui[2] - v.u[2 * n + j]};
+                    const double4 uj = v.u[j];
+                    const double uij[3] = {ui[0] - uj.x, ui[1] - uj.y, ui[2] - uj.z};
                     const double du = (d[0] * uij[0] + d[1] * uij[1]) + d[2] * uij[2];
                     for (int c = 0; c < 3; c++) {
                         F[c] = fma(fs, d[c], F[c]);
                         Hu[c] += B * uij[c] + C * du * d[c];
                     }
                     // each unordered pair is visited twice: half weight
+                    // (the sigma terms are summed times sigma and divided once at the end)
                     const double dVde = 4.0 * (q12 - q6);
-                    const double dVds = 24.0 * eps * (2.0 * q12 - q6) / sig;
+                    const double dVds = 24.0 * eps * (2.0 * q12 - q6);
                     const double dufe = du * 24.0 * (2.0 * q12 - q6) * ir2;
-                    const double dufs = du * 144.0 * eps * (4.0 * q12 - q6) * ir2 / sig;
+                    const double dufs = du * 144.0 * eps * (4.0 * q12 - q6) * ir2;
                     acc_e += 0.5 * (vE * dVde + dufe);
                     acc_s += 0.5 * (vE * dVds + dufs);
                 });
@@ -114,7 +117,7 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_lj_vjp(VjpArgs v)
         if (valid)
             for (int c = 0; c < 3; c++) v.gx[c * n + i] = -vE * F[c] - Hu[c];
     BRICK_TASK_END
-    double s[4] = {acc_e, acc_s, 0.0, 0.0};
+    double s[4] = {acc_e, acc_s / sig, 0.0, 0.0};
     if (mdred::last_block_sum4(s, v.gpart, a.done, lds) && threadIdx.x == 0 && v.gout != nullptr) {
         v.gout[0] = s[0];
         v.gout[1] = s[1];
@@ -133,7 +136,8 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_vjp_a(VjpArgs v)
     BRICK_TASK_BEGIN(st, a.pos, nullptr, nullptr)
         double rho = 0.0, rdot = 0.0;
         const double4 xi = a.pos[i];
-        const double ui[3] = {v.u[i], v.u[n + i], v.u[2 * n + i]};
+        const double4 ui4 = v.u[i];
+        const double ui[3] = {ui4.x, ui4.y, ui4.z};
         STAGE_IMG_SPLIT(all_staged, has_img,
             walk_list<STAGED, IMG>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
                 [&](bool ok, int32_t k, double dx, double dy, double dz, double r2) {
@@ -143,7 +147,8 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_vjp_a(VjpArgs v)
                     int kk;
                     double tt, f, fu, fuu;
                     spl_full(a.tab[1], (r - x0r) * ihr, nkr, kk, tt, f, fu, fuu);
-                    const double uij[3] = {ui[0] - v.u[j], ui[1] - v.u[n + j], ui[2] - v.u[2 * n + j]};
+                    const double4 uj = v.u[j];
+                    const double uij[3] = {ui[0] - uj.x, ui[1] - uj.y, ui[2] - uj.z};
                     const double s = ((dx * uij[0] + dy * uij[1]) + dz * uij[2]) / r;
                     rho += f;
                     rdot += (fu * ihr) * s;
@@ -186,7 +191,8 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_vjp_b(VjpArgs v)
         double F[3] = {0.0, 0.0, 0.0}, Hu[3] = {0.0, 0.0, 0.0};
         const double vE = v.vE[rep_r];
         const double4 xi = a.pos[i];
-        const double ui[3] = {v.u[i], v.u[n + i], v.u[2 * n + i]};
+        const double4 ui4 = v.u[i];
+        const double ui[3] = {ui4.x, ui4.y, ui4.z};
         const double fpi = a.fp[i];
         const double qi = v.fpp[i] * v.rdot[i];
         STAGE_IMG_SPLIT(all_staged, has_img,
@@ -197,7 +203,8 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_vjp_b(VjpArgs v)
                     const int32_t j = candidate_j<STAGED>(st, a.bd, k);
                     const double r = sqrt(r2);
                     const double e[3] = {dx / r, dy / r, dz / r};
-                    const double uij[3] = {ui[0] - v.u[j], ui[1] - v.u[n + j], ui[2] - v.u[2 * n + j]};
+                    const double4 uj = v.u[j];
+                    const double uij[3] = {ui[0] - uj.x, ui[1] - uj.y, ui[2] - uj.z};
                     const double s = (e[0] * uij[0] + e[1] * uij[1]) + e[2] * uij[2];
                     double ph = 0.0, php = 0.0, phpp = 0.0, rh = 0.0, rhp = 0.0, rhpp = 0.0;
                     double tp = 0.0, tr = 0.0;
