@@ -149,7 +149,7 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_vjp_a(VjpArgs v)
                     spl_full(a.tab[1], (r - x0r) * ihr, nkr, kk, tt, f, fu, fuu);
                     const double4 uj = v.u[j];
                     const double uij[3] = {ui[0] - uj.x, ui[1] - uj.y, ui[2] - uj.z};
-                    const double s = ((dx * uij[0] + dy * uij[1]) + dz * uij[2]) / r;
+                    const double s = ((dx * uij[0] + dy * uij[1]) + dz * uij[2]) * rcp64(r);
                     rho += f;
                     rdot += (fu * ihr) * s;
                 });
@@ -202,7 +202,9 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_vjp_b(VjpArgs v)
                     if (!ok || (!in_phi && !in_rho)) return;
                     const int32_t j = candidate_j<STAGED>(st, a.bd, k);
                     const double r = sqrt(r2);
-                    const double e[3] = {dx / r, dy / r, dz / r};
+                    // one refined reciprocal instead of four divisions
+                    const double ir = rcp64(r);
+                    const double e[3] = {dx * ir, dy * ir, dz * ir};
                     const double4 uj = v.u[j];
                     const double uij[3] = {ui[0] - uj.x, ui[1] - uj.y, ui[2] - uj.z};
                     const double s = (e[0] * uij[0] + e[1] * uij[1]) + e[2] * uij[2];
@@ -227,7 +229,7 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_vjp_b(VjpArgs v)
                     const double qq = qi + v.fpp[j] * v.rdot[j];
                     for (int c = 0; c < 3; c++) {
                         F[c] -= gsc * e[c];
-                        Hu[c] += gg * s * e[c] + (gsc / r) * (uij[c] - s * e[c]) + qq * rhp * e[c];
+                        Hu[c] += gg * s * e[c] + (gsc * ir) * (uij[c] - s * e[c]) + qq * rhp * e[c];
                     }
                     if (v.gtab != nullptr && j > i) {
                         if (in_phi) {
