@@ -453,7 +453,7 @@ __device__ __forceinline__ void walk_four(const Stage &s, const BrickDims &d, co
 // past the list's end come with ok = false and a valid dummy candidate.  IMG =
 // false (a brick staged through its cell images) reads the narrow layout:
 // 16-bit entries, eight per group, half the bytes of the 32-bit one.
-template <bool STAGED, bool IMG, typename Body>
+template <bool STAGED, bool IMG, bool UNROLL = false, typename Body>
 __device__ __forceinline__ void walk_list(const Stage &s, const BrickDims &d, const double4 *pos,
                                           const uint32_t *nbr, int64_t i, int32_t M, int32_t mm,
                                           const double4 &xi, double Lx, double Ly, double Lz,
@@ -473,6 +473,13 @@ __device__ __forceinline__ void walk_list(const Stage &s, const BrickDims &d, co
         if (IMG) {
             const uint32_t es[4] = {ev.x, ev.y, ev.z, ev.w};
             walk_four<STAGED, IMG>(s, d, pos, es, rem, xi, Lx, Ly, Lz, body);
+        } else if (UNROLL) {
+            // both halves inlined: the second half's LDS reads may be issued
+            // ahead of the first half's arithmetic (more registers live)
+            const uint32_t lo[4] = {ev.x & 0xffffu, ev.x >> 16, ev.y & 0xffffu, ev.y >> 16};
+            const uint32_t hi[4] = {ev.z & 0xffffu, ev.z >> 16, ev.w & 0xffffu, ev.w >> 16};
+            walk_four<STAGED, IMG>(s, d, pos, lo, rem, xi, Lx, Ly, Lz, body);
+            if (rem > 4) walk_four<STAGED, IMG>(s, d, pos, hi, rem - 4, xi, Lx, Ly, Lz, body);
         } else {
             // one copy of the pair code for both halves (as many registers
             // live as in the 32-bit walk)

@@ -218,7 +218,7 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_lj_full(ForceArgs a)
         double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0, w = 0.0;
         const double4 xi = a.pos[i];
         STAGE_IMG_SPLIT(all_staged, has_img,
-            walk_list<STAGED, IMG>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
+            walk_list<STAGED, IMG, true>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
                 [&](bool ok, int32_t, double dx, double dy, double dz, double r2) {
                     double fs, V;
                     lj_pair_unit<MIXED, EN>(ok && r2 < rc2, r2, s2, s2f, fs, V);
@@ -566,7 +566,7 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_density(ForceArgs a)
         double rho = 0.0;
         const double4 xi = a.pos[i];
         STAGE_IMG_SPLIT(all_staged, has_img,
-            walk_list<STAGED, IMG>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
+            walk_list<STAGED, IMG, true>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
                 [&](bool ok, int32_t, double, double, double, double r2) {
                     const bool in = ok && r2 < rrho2;
                     double f;

@@ -451,10 +451,14 @@ def test_replica_batch_forces(kind):
 
 
 # ---------------------------------------------------------------- adjoints
-def test_lj_vjp_matches_oracle():
+# 4 x 4 x 4 cells: 4 x 3 x 2 bricks wrap onto themselves along x (32-bit
+# entries with image codes), 2 x 2 x 2 bricks are staged through their cell
+# images (16-bit entries)
+@pytest.mark.parametrize("shape", [(4, 3, 2), (2, 2, 2)])
+def test_lj_vjp_matches_oracle(shape):
     w = materialise(lj_cases()["fcc2048_thermal"])
     L = w.boxes[0]
-    s = MDSystem.from_workload(w)
+    s = shaped_system(w, shape, 0)
     g = np.random.default_rng(20)
     u = g.normal(size=w.pos.shape)
     vE = 0.7
@@ -464,6 +468,8 @@ def test_lj_vjp_matches_oracle():
     gxo, gpo = oracle.lj_vjp(x, L, pi, pj, u, vE)
     assert rel(gx.cpu().numpy(), gxo) <= 1e-12
     assert np.allclose(gp.cpu().numpy(), gpo, rtol=1e-11)
+    total, narrow = B.md_query(s.ctx, 10), B.md_query(s.ctx, 15)
+    assert narrow == (0 if shape == (4, 3, 2) else total)
 
 
 # key 8: the parameter gradient summed in LDS for every interval (-1; the
