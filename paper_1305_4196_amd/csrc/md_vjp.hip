@@ -77,6 +77,7 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_lj_vjp(VjpArgs v)
     const double eps = a.lj[0], sig = a.lj[1];
     const double s2 = sig * sig;
     const double rc2 = a.rc2;
+    const double e24 = 24.0 * eps;
     double acc_e = 0.0, acc_s = 0.0;
     BRICK_TASK_BEGIN(st, a.pos, nullptr, nullptr)
         double F[3] = {0.0, 0.0, 0.0}, Hu[3] = {0.0, 0.0, 0.0};
@@ -94,7 +95,9 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_lj_vjp(VjpArgs v)
                     const double q2 = s2 * ir2;
                     const double q6 = q2 * q2 * q2;
                     const double q12 = q6 * q6;
-                    const double fs = 24.0 * eps * (2.0 * q12 - q6) * ir2;
+                    const double t2 = 2.0 * q12 - q6;
+                    const double t2r = t2 * ir2;
+                    const double fs = e24 * t2r;
                     const double B = -fs;
                     const double C = 96.0 * eps * (7.0 * q12 - 2.0 * q6) * (ir2 * ir2);
                     const double4 uj = v.u[j];
@@ -104,20 +107,19 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_lj_vjp(VjpArgs v)
                         F[c] = fma(fs, d[c], F[c]);
                         Hu[c] += B * uij[c] + C * du * d[c];
                     }
-                    // each unordered pair is visited twice: half weight
-                    // (the sigma terms are summed times sigma and divided once at the end)
-                    const double dVde = 4.0 * (q12 - q6);
-                    const double dVds = 24.0 * eps * (2.0 * q12 - q6);
-                    const double dufe = du * 24.0 * (2.0 * q12 - q6) * ir2;
-                    const double dufs = du * 144.0 * eps * (4.0 * q12 - q6) * ir2;
-                    acc_e += 0.5 * (vE * dVde + dufe);
-                    acc_s += 0.5 * (vE * dVds + dufs);
+                    // parameter terms, the common factors applied once at the end:
+                    // vE dV/deps + d(u.f)/deps = 4 [vE (q12 - q6) + 6 du t2 / r^2],
+                    // vE dV/dsigma + d(u.f)/dsigma = (24 eps / sigma) [vE t2 + 6 du (4 q12 - q6) / r^2]
+                    const double du6 = 6.0 * du;
+                    acc_e += fma(vE, q12 - q6, du6 * t2r);
+                    acc_s += fma(vE, t2, du6 * ((4.0 * q12 - q6) * ir2));
                 });
         )
         if (valid)
             for (int c = 0; c < 3; c++) v.gx[c * n + i] = -vE * F[c] - Hu[c];
     BRICK_TASK_END
-    double s[4] = {acc_e, acc_s / sig, 0.0, 0.0};
+    // each unordered pair is visited twice: half weight
+    double s[4] = {2.0 * acc_e, 12.0 * eps * acc_s / sig, 0.0, 0.0};
     if (mdred::last_block_sum4(s, v.gpart, a.done, lds) && threadIdx.x == 0 && v.gout != nullptr) {
         v.gout[0] = s[0];
         v.gout[1] = s[1];
