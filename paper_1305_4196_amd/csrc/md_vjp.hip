@@ -103,9 +103,10 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_lj_vjp(VjpArgs v)
                     const double4 uj = v.u[j];
                     const double uij[3] = {ui[0] - uj.x, ui[1] - uj.y, ui[2] - uj.z};
                     const double du = (d[0] * uij[0] + d[1] * uij[1]) + d[2] * uij[2];
+                    const double Cd = C * du;
                     for (int c = 0; c < 3; c++) {
                         F[c] = fma(fs, d[c], F[c]);
-                        Hu[c] += B * uij[c] + C * du * d[c];
+                        Hu[c] = fma(B, uij[c], fma(Cd, d[c], Hu[c]));
                     }
                     // parameter terms, the common factors applied once at the end:
                     // vE dV/deps + d(u.f)/deps = 4 [vE (q12 - q6) + 6 du t2 / r^2],
@@ -229,9 +230,12 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_vjp_b(VjpArgs v)
                     const double gsc = php + Fs * rhp;
                     const double gg = phpp + Fs * rhpp;
                     const double qq = qi + v.fpp[j] * v.rdot[j];
+                    // H u along e and along u_ij: (gg s - (gsc/r) s + qq rho') e + (gsc/r) u_ij
+                    const double G = gsc * ir;
+                    const double Ae = fma(gg - G, s, qq * rhp);
                     for (int c = 0; c < 3; c++) {
                         F[c] -= gsc * e[c];
-                        Hu[c] += gg * s * e[c] + (gsc * ir) * (uij[c] - s * e[c]) + qq * rhp * e[c];
+                        Hu[c] = fma(G, uij[c], fma(Ae, e[c], Hu[c]));
                     }
                     if (v.gtab != nullptr && j > i) {
                         if (in_phi) {
