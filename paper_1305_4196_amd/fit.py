@@ -3,9 +3,13 @@
 A batch of uneven-size replicas (one context, all replicas' bricks in each
 persistent launch) is fitted to target forces.  One gradient evaluation is
 
-    F, E   = forces(theta)                                  (md_compute_forces)
+    F      = forces(theta)                                  (md_compute_forces)
     u      = 2 (F - F*) / (3 N)                              (cotangent of the loss)
     g      = d(u . F)/d theta                                (md_force_vjp, v_E = 0)
+
+(the loss holds no energy term, so the forward pass runs the force kernels
+without their energy sums unless `with_energy` asks for the per-replica
+energies in `E`)
 
 i.e. the gradient of L = sum |F - F*|^2 / (3 N) with respect to the potential
 parameters (LJ {eps, sigma}; EAM the three tables' coefficients).  The cutoff
@@ -27,9 +31,10 @@ from .system import MDSystem
 
 class BatchedFit:
     def __init__(self, system: MDSystem, target_forces: torch.Tensor, params: torch.Tensor,
-                 precision: int = B.MD_FP64):
+                 precision: int = B.MD_FP64, with_energy: bool = False):
         self.s = system
         self.precision = precision
+        self.with_energy = with_energy
         self.F_star = target_forces.contiguous()
         self.params = params.detach().clone().contiguous()    # the graph reads this buffer
         self.dpot = B.DevicePotential(system.pot, device=system.device, params=self.params)
@@ -49,7 +54,8 @@ class BatchedFit:
         self.params.copy_(theta)
 
     def _evaluate(self):
-        B.md_compute_forces(self.s.ctx, self.dpot, self.precision, self.F, self.E, None)
+        B.md_compute_forces(self.s.ctx, self.dpot, self.precision, self.F,
+                            self.E if self.with_energy else None, None)
         torch.sub(self.F, self.F_star, out=self.u)
         self.u.mul_(self.scale)
         B.md_force_vjp(self.s.ctx, self.dpot, self.precision, None, self.u, self.vE, self.g_pos, self.g)

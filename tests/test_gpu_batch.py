@@ -132,3 +132,21 @@ def test_tuner_picks_a_working_configuration(tmp_path):
     # a second call takes the cached entry
     again = tune.tune(s, precision=B.MD_FP64, top=3, reps=1, cache_path=str(tmp_path / "t.json"))
     assert again["shape"] == best["shape"] and again["threads"] == best["threads"]
+
+
+def test_energies_on_request_leave_the_gradient_unchanged():
+    """The forward pass skips the energy sums unless asked; with them the force
+    arithmetic is the same, so forces and gradient agree bit for bit and E
+    equals a direct evaluation at the same parameters."""
+    w, s, start, fit = make_fit("lj", 6)
+    g0 = fit.gradient().clone()
+    F0 = fit.F.clone()
+    fit_e = BatchedFit(s, fit.F_star, fit.params, with_energy=True)
+    g1 = fit_e.gradient().clone()
+    torch.cuda.synchronize()
+    assert torch.equal(fit_e.F, F0)
+    assert torch.equal(g1, g0)
+    F = torch.empty_like(s.pos)
+    E = torch.zeros(s.R, dtype=torch.float64, device=s.device)
+    B.md_compute_forces(s.ctx, fit_e.dpot, B.MD_FP64, F, E)
+    assert torch.equal(fit_e.E, E)
