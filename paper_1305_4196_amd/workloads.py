@@ -53,6 +53,13 @@ FS_C = 3.25      # phi cutoff
 FS_D = 3.6       # rho cutoff
 FS_A = 1.0
 FS_LATTICE = 3.3
+# Pair-polynomial coefficients.  With c1 = c2 = 0 the fcc lattice at a = 3.3 has
+# C11 - C12 < 0 and turns into a bcc-like structure within a few hundred steps
+# (the Bain path has no barrier); c1, c2 below make it a stable minimum with
+# positive elastic constants and phonon frequencies, c0 then follows from zero
+# pressure.
+FS_C1 = -3.75
+FS_C2 = 0.7
 
 
 def rng(workload: int, purpose: str) -> np.random.Generator:
@@ -164,21 +171,29 @@ def fs_rho0(a: float = FS_LATTICE, d: float = FS_D) -> float:
 
 
 def fs_c0_zero_pressure(A: float = FS_A, a: float = FS_LATTICE, c: float = FS_C,
-                        d: float = FS_D) -> float:
-    """c0 (with c1 = c2 = 0) that gives the perfect lattice zero virial pressure."""
+                        d: float = FS_D, c1: float = 0.0, c2: float = 0.0) -> float:
+    """c0 that gives the perfect lattice zero virial pressure for given c1, c2.
+
+    Zero pressure means dE/ds = 0 under a uniform scaling r -> s r at s = 1:
+    F'(rho0) sum_n n r rho'(r) + 1/2 sum_n n r phi'(r) = 0 over the shells, with
+    F'(rho0) = -A / (2 sqrt(rho0)) and rho'(r) = 2 (r - d).  phi'(r) is linear in
+    c0 (phi' = 2 (r - c) c0 + terms in c1, c2), which gives c0 directly.
+    """
     rho0 = fs_rho0(a, d)
-    num = sum(n * (r - d) * r for r, n in fs_shells(a) if r < d) / math.sqrt(rho0)
-    den = sum(n * (r - c) * r for r, n in fs_shells(a) if r < c)
-    return A * num / den
+    emb = (2.0 * A / math.sqrt(rho0)) * sum(n * r * (r - d) for r, n in fs_shells(a) if r < d)
+    rest = sum(n * r * (2.0 * (r - c) * (c1 * r + c2 * r * r) + (r - c) ** 2 * (c1 + 2.0 * c2 * r))
+               for r, n in fs_shells(a) if r < c)
+    lin = sum(n * r * 2.0 * (r - c) for r, n in fs_shells(a) if r < c)
+    return (emb - rest) / lin
 
 
-def fs_eam_potential(A: float = FS_A, c0: Optional[float] = None, c1: float = 0.0,
-                     c2: float = 0.0, c: float = FS_C, d: float = FS_D,
+def fs_eam_potential(A: float = FS_A, c0: Optional[float] = None, c1: float = FS_C1,
+                     c2: float = FS_C2, c: float = FS_C, d: float = FS_D,
                      n_knots: int = N_KNOTS, rho_max: Optional[float] = None) -> Potential:
     """phi(r) = (r-c)^2 (c0 + c1 r + c2 r^2) [r<c], rho(r) = (r-d)^2 [r<d],
     F(rho) = -A sqrt(rho); tabulated as uniform cubic Hermite splines."""
     if c0 is None:
-        c0 = fs_c0_zero_pressure(A=A, c=c, d=d)
+        c0 = fs_c0_zero_pressure(A=A, c=c, d=d, c1=c1, c2=c2)
     if rho_max is None:
         rho_max = 2.0 * fs_rho0(d=d)
 

@@ -1,8 +1,8 @@
 """Pins of the oracle's Finnis-Sinclair-type EAM and of the tabulated functions.
 
 phi(r) = (r-c)^2 (c0 + c1 r + c2 r^2) [r < c], rho(r) = (r-d)^2 [r < d],
-F(rho) = -A sqrt(rho), each tabulated on 2,000 uniform knots (cubic Hermite).
-Pins: the tables against the analytic functions within the Hermite error bound,
+F(rho) = -A sqrt(rho), each tabulated on 2,000 uniform knots (cubic Hermite);
+the workload takes c1 = -3.75, c2 = 0.7 and c0 from zero pressure.  Pins: the tables against the analytic functions within the Hermite error bound,
 perfect-lattice closed forms (rho_0, E/N, zero force, zero virial pressure by
 the choice of c0), hand-worked two- and three-atom cases from the analytic
 functions, finite differences and Newton's third law.
@@ -19,12 +19,14 @@ POT = W.fs_eam_potential()
 AN = POT.analytic
 
 
-def phi(r, c0=AN["c0"], c1=0.0, c2=0.0, c=W.FS_C):
+def phi(r, c0=AN["c0"], c1=AN["c1"], c2=AN["c2"], c=W.FS_C):
     return (r - c) ** 2 * (c0 + c1 * r + c2 * r * r) if r < c else 0.0
 
 
-def dphi(r, c0=AN["c0"], c=W.FS_C):
-    return 2 * (r - c) * c0 if r < c else 0.0
+def dphi(r, c0=AN["c0"], c1=AN["c1"], c2=AN["c2"], c=W.FS_C):
+    if r >= c:
+        return 0.0
+    return 2 * (r - c) * (c0 + c1 * r + c2 * r * r) + (r - c) ** 2 * (c1 + 2 * c2 * r)
 
 
 def rho(r, d=W.FS_D):
@@ -58,15 +60,31 @@ def emb_slope_bound(p):
     return h ** 3 / 24 * (15 / 16) * lo ** -3.5
 
 
+# phi is a quartic with leading coefficient c2, so its fourth derivative is 24 c2 everywhere
+PHI_BOUND = POT.phi.h ** 4 / 384 * 24 * abs(AN["c2"])
+PHI_SLOPE_BOUND = POT.phi.h ** 3 / 24 * 24 * abs(AN["c2"])
+
+
 def test_quadratic_tables_are_exact():
+    """Cubic Hermite reproduces a quadratic exactly: rho always, phi when c1 = c2 = 0."""
     r = np.linspace(0.5, 3.5999, 4001)
     out = oracle.spline_eval(POT.rho, r)
     assert np.max(np.abs(out[0] - (r - 3.6) ** 2)) < 1e-12
     assert np.max(np.abs(out[1] - 2 * (r - 3.6))) < 1e-10
     assert np.max(np.abs(out[2] - 2.0)) < 1e-6
+    quad = W.fs_eam_potential(c1=0.0, c2=0.0)
+    r = np.linspace(0.5, 3.2499, 4001)
+    out = oracle.spline_eval(quad.phi, r)
+    assert np.max(np.abs(out[0] - quad.analytic["c0"] * (r - 3.25) ** 2)) < 1e-12
+
+
+def test_default_phi_within_hermite_bound():
     r = np.linspace(0.5, 3.2499, 4001)
     out = oracle.spline_eval(POT.phi, r)
-    assert np.max(np.abs(out[0] - AN["c0"] * (r - 3.25) ** 2)) < 1e-12
+    exact = np.array([phi(v) for v in r])
+    slope = np.array([dphi(v) for v in r])
+    assert np.max(np.abs(out[0] - exact)) <= PHI_BOUND * 1.01 + 1e-13
+    assert np.max(np.abs(out[1] - slope)) <= PHI_SLOPE_BOUND * 1.01 + 1e-11
 
 
 def test_embedding_table_within_hermite_bound():
@@ -99,9 +117,13 @@ def test_embedding_linear_continuation():
 
 
 def test_c0_gives_zero_pressure():
-    c0 = AN["c0"]
-    assert c0 == pytest.approx(0.3627, abs=1e-4)
+    # c1 = c2 = 0: c0 = A [sum n r (r - d) / sqrt(rho0)] / [sum n r (r - c)] over the shells
+    assert W.fs_c0_zero_pressure() == pytest.approx(0.3627, abs=1e-4)
     assert W.fs_rho0() == pytest.approx(19.790, abs=1e-3)
+    # the workload's (c1, c2) = (-3.75, 0.7) give c0 = 5.0802; that this c0 makes the
+    # virial vanish is checked on the oracle's perfect lattice below
+    assert AN["c1"] == -3.75 and AN["c2"] == 0.7
+    assert AN["c0"] == pytest.approx(5.0802, abs=1e-4)
 
 
 def test_perfect_lattice_closed_forms():
@@ -126,9 +148,9 @@ def test_dimer_hand_case():
     L = np.array([20.0, 20.0, 20.0])
     F, E, Wv, rh, Fp = oracle.eam(x, L, [0], [1], POT)
     e_cf = 2 * emb(rho(r)) + phi(r)
-    assert E == pytest.approx(e_cf, abs=2 * emb_bound(rho(r)) + 1e-13)
+    assert E == pytest.approx(e_cf, abs=2 * emb_bound(rho(r)) + PHI_BOUND + 1e-13)
     g = dphi(r) + 2 * demb(rho(r)) * drho(r)
-    tol = 2 * emb_slope_bound(rho(r)) * abs(drho(r)) + 1e-12
+    tol = 2 * emb_slope_bound(rho(r)) * abs(drho(r)) + PHI_SLOPE_BOUND + 1e-12
     # d = x0 - x1 = -r e_x; F_0 = -g d/r = g e_x
     assert F[0, 0] == pytest.approx(g, abs=tol)
     assert F[0, 1] == pytest.approx(-g, abs=tol)
@@ -144,13 +166,13 @@ def test_trimer_hand_case():
     rh_cf = [rho(2.4), rho(2.4) + rho(3.0), rho(3.0)]
     assert np.allclose(rh, rh_cf, rtol=1e-12)
     e_cf = sum(emb(p) for p in rh_cf) + phi(2.4) + phi(3.0)
-    assert E == pytest.approx(e_cf, abs=sum(2 * emb_bound(p) for p in rh_cf) + 1e-13)
+    assert E == pytest.approx(e_cf, abs=sum(2 * emb_bound(p) for p in rh_cf) + 2 * PHI_BOUND + 1e-13)
     fp = [demb(p) for p in rh_cf]
     sb = [emb_slope_bound(p) for p in rh_cf]
     g01 = dphi(2.4) + (fp[0] + fp[1]) * drho(2.4)
     g12 = dphi(3.0) + (fp[1] + fp[2]) * drho(3.0)
-    t01 = 2 * (sb[0] + sb[1]) * abs(drho(2.4)) + 1e-12
-    t12 = 2 * (sb[1] + sb[2]) * abs(drho(3.0)) + 1e-12
+    t01 = 2 * (sb[0] + sb[1]) * abs(drho(2.4)) + PHI_SLOPE_BOUND + 1e-12
+    t12 = 2 * (sb[1] + sb[2]) * abs(drho(3.0)) + PHI_SLOPE_BOUND + 1e-12
     # F_0 = g01 e_x ; F_2 = -g12 e_x ; F_1 = -g01 e_x + g12 e_x
     assert F[0, 0] == pytest.approx(g01, abs=t01)
     assert F[0, 2] == pytest.approx(-g12, abs=t12)
