@@ -285,6 +285,19 @@ int md_query(md_ctx *ctx, int32_t key, int64_t *value);
 int md_profile(md_ctx *ctx, int32_t enable, double *force_ms, int64_t *force_launches,
                double *list_ms, int64_t *list_launches);
 
+/* Timings of the md_verlet_step calls made while md_profile was enabled, taken
+ * when md_profile(ctx, 0, ...) stopped it (HIP events on the calls' stream).
+ * out [host]: n_out (at most 8) doubles:
+ *   [0] ms of the step loops (from the end of the setup to the last step's
+ *       last launch: every rebuild test, list rebuild, force and integration
+ *       launch of the steps), [1] steps in those loops,
+ *   [2] ms of their setup (user order to sorted, cells, list, F(x0)),
+ *   [3] ms of the force launches of steps that record no energies, [4] their
+ *       number, [5] ms of the force launches of recorded steps, [6] their
+ *       number, [7] ms of the setup's F(x0) launches.
+ * Errors: MD_ERR_ARG. */
+int md_profile_detail(md_ctx *ctx, double *out, int32_t n_out);
+
 /* Human-readable description of the last error on this context (static storage). */
 const char *md_last_error(md_ctx *ctx);
 

@@ -20,7 +20,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "md_oracle.c")
 _LIB = os.path.join(_HERE, "libmdoracle.so")
-CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-std=c99", "-Wall", "-shared", "-fPIC"]
+CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-std=c99", "-Wall", "-shared", "-fPIC"]
 
 
 def build(force: bool = True) -> str:
@@ -64,6 +64,9 @@ def lib() -> C.CDLL:
                                  C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
                                  C.c_double, C.c_int32, _d, _i32]
         L.orc_verlet.restype = C.c_int
+        L.orc_verlet_omp.argtypes = list(L.orc_verlet.argtypes) + [C.c_int32]
+        L.orc_verlet_omp.restype = C.c_int
+        L.orc_max_threads.restype = C.c_int
         L.orc_lj_vjp.argtypes = [C.c_int64, _d, _d, C.c_double, C.c_double, C.c_double,
                                  C.c_int64, _i32, _i32, _d, C.c_double, _d, _d]
         L.orc_eam_vjp.argtypes = [C.c_int64, _d, _d, _i32, _d, _d, _d, _d, _d, C.c_double, C.c_double,
@@ -241,8 +244,12 @@ def forces(x, L, pot, skin: float = 0.0):
     return F, E, W
 
 
-def verlet(x, v, L, pot, dt: float, mass: float, steps: int, skin: float):
-    """Velocity Verlet; returns (x, v, F, hist[steps][3] = (E_pot, KE, W), n_rebuild)."""
+def verlet(x, v, L, pot, dt: float, mass: float, steps: int, skin: float, threads: int = 0):
+    """Velocity Verlet; returns (x, v, F, hist[steps][3] = (E_pot, KE, W), n_rebuild).
+
+    threads = 0: the serial reference (half lists); threads >= 1: the OpenMP
+    full-list variant on that many threads (a CPU baseline, tested against the
+    serial one)."""
     x = _f64(x).copy()
     v = _f64(v).copy()
     n = x.shape[1]
@@ -258,9 +265,10 @@ def verlet(x, v, L, pot, dt: float, mass: float, steps: int, skin: float):
     else:
         nk, x0, h, cp, cr, ce = _eam_args(pot)
         kind, rcp, rcr = 1, pot.rc_phi, pot.rc_rho
-    rc = lib().orc_verlet(n, _p(x), _p(v), _p(F), _p(_box(L)), kind, _p(lj_par), _p(nk, _i32),
-                          _p(x0), _p(h), _p(cp), _p(cr), _p(ce), rcp, rcr, pot.rc, skin, dt, mass,
-                          steps, _p(hist), _p(nreb, _i32))
+    args = (n, _p(x), _p(v), _p(F), _p(_box(L)), kind, _p(lj_par), _p(nk, _i32),
+            _p(x0), _p(h), _p(cp), _p(cr), _p(ce), rcp, rcr, pot.rc, skin, dt, mass,
+            steps, _p(hist), _p(nreb, _i32))
+    rc = lib().orc_verlet_omp(*args, int(threads)) if threads > 0 else lib().orc_verlet(*args)
     if rc != 0:
         raise ValueError("box shorter than twice the list cutoff")
     return x, v, F, hist[:steps], int(nreb[0])
@@ -305,3 +313,8 @@ def vjp(x, L, pot, u, vE, skin: float = 0.0):
     if pot.kind == "lj":
         return lj_vjp(x, L, pi, pj, u, vE, pot.eps, pot.sigma, pot.rc)
     return eam_vjp(x, L, pi, pj, pot, u, vE)
+
+
+def max_threads() -> int:
+    """Threads the OpenMP variant uses by default (OMP_NUM_THREADS or the cores)."""
+    return int(lib().orc_max_threads())

@@ -5,9 +5,10 @@
  * baseline leg of the benchmark load this library; the product path never does.
  * It shares no source, header, table or helper with the HIP library.
  *
- * Build: gcc -O2 -fno-fast-math -ffp-contract=off -shared -fPIC, so that every
- * floating-point operation below is one individually rounded binary64 operation
- * in the order written.
+ * Build: gcc -O2 -fno-fast-math -ffp-contract=off -fopenmp -shared -fPIC, so
+ * that every floating-point operation below is one individually rounded binary64
+ * operation in the order written.  Only orc_verlet_omp (the all-cores CPU
+ * baseline, at the end) runs threads; every other routine is serial.
  *
  * What it computes (the paper cites, but does not write out, the physics; the
  * definitions below are the textbook ones for the potentials the paper names):
@@ -30,6 +31,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define X(a, n, i) ((a)[(i)])
 #define Y(a, n, i) ((a)[(n) + (i)])
@@ -654,4 +658,211 @@ void orc_eam_vjp(int64_t n, const double *x, const double L[3], const int32_t nk
         }
     }
     free(F); free(rho); free(Fp); free(Fpp); free(rdot);
+}
+
+/* ------------------------------------------------------------------------- */
+/* the same velocity Verlet threaded with OpenMP over atoms                   */
+/* ------------------------------------------------------------------------- */
+/* A CPU baseline on all host cores, not a reference: the serial orc_verlet
+ * above is the definition this one is tested against.  It uses full lists
+ * (every pair in both atoms' lists), so each thread computes and writes only
+ * its own atoms' forces and no two threads update one particle -- the
+ * invariant of Sec. II.A obtained by ownership, as the naive threaded loop of
+ * Sec. I without Newton's third law.  Energies are summed per atom (half of
+ * every listed pair) with a reduction whose order depends on the threads. */
+
+typedef struct {
+    int64_t cap;
+    int64_t *start;   /* [n+1] */
+    int32_t *nbr;
+} fulllist;
+
+static int build_full_omp(int64_t n, const double *x, const double L[3], double rl, fulllist *fl)
+{
+    int32_t nc[3];
+    if (orc_grid(L, rl, nc) != 0) return -2;
+    int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
+    int32_t *cell_of = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *cstart = (int32_t *)malloc(sizeof(int32_t) * (size_t)(ncell + 1));
+    int32_t *order = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    orc_bin(n, x, L, nc, cell_of, cstart, order);
+    double rl2 = rl * rl;
+    for (int pass = 0; pass < 2; pass++) {
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t i = 0; i < n; i++) {
+            int32_t c = cell_of[i];
+            int32_t cx = c % nc[0], cy = (c / nc[0]) % nc[1], cz = c / (nc[0] * nc[1]);
+            int32_t cells[27];
+            int ns = stencil(nc, cx, cy, cz, cells);
+            int64_t m = 0, o = pass ? fl->start[i] : 0;
+            double d[3];
+            for (int k = 0; k < ns; k++)
+                for (int32_t s = cstart[cells[k]]; s < cstart[cells[k] + 1]; s++) {
+                    int32_t j = order[s];
+                    if (j == i || !(sep(x, n, i, j, L, d) < rl2)) continue;
+                    if (pass) fl->nbr[o + m] = j;
+                    m++;
+                }
+            if (!pass) cnt[i] = m;
+        }
+        if (!pass) {
+            if (fl->start == NULL) fl->start = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+            fl->start[0] = 0;
+            for (int64_t i = 0; i < n; i++) fl->start[i + 1] = fl->start[i] + cnt[i];
+            if (fl->start[n] > fl->cap) {
+                free(fl->nbr);
+                fl->cap = fl->start[n] + fl->start[n] / 4 + 16;
+                fl->nbr = (int32_t *)malloc(sizeof(int32_t) * (size_t)fl->cap);
+            }
+        }
+    }
+    free(cell_of); free(cstart); free(order); free(cnt);
+    return 0;
+}
+
+/* forces over the full lists; ew = (E, W) */
+static void full_forces_omp(int64_t n, const double *x, const double L[3], int kind, double rc,
+                            const double *lj, const orc_eam_pot *p, const fulllist *fl, double *F,
+                            double ew[2], double *rho, double *Fp)
+{
+    double E = 0.0, W = 0.0;
+    if (kind == 0) {
+        double rc2 = rc * rc, eps = lj[0], sigma = lj[1];
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : E, W)
+        for (int64_t i = 0; i < n; i++) {
+            double f[3] = { 0.0, 0.0, 0.0 }, d[3];
+            for (int64_t q = fl->start[i]; q < fl->start[i + 1]; q++) {
+                int64_t j = fl->nbr[q];
+                double r2 = sep(x, n, i, j, L, d);
+                if (!(r2 < rc2)) continue;
+                double sr2 = (sigma * sigma) / r2;
+                double sr6 = sr2 * sr2 * sr2;
+                double sr12 = sr6 * sr6;
+                double fs = 24.0 * eps * (2.0 * sr12 - sr6) / r2;
+                f[0] += fs * d[0]; f[1] += fs * d[1]; f[2] += fs * d[2];
+                E += 0.5 * (4.0 * eps * (sr12 - sr6));
+                W += 0.5 * ((d[0] * fs * d[0] + d[1] * fs * d[1]) + d[2] * fs * d[2]);
+            }
+            X(F, n, i) = f[0]; Y(F, n, i) = f[1]; Z(F, n, i) = f[2];
+        }
+    } else {
+        double cphi2 = p->rc_phi * p->rc_phi, crho2 = p->rc_rho * p->rc_rho;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : E)
+        for (int64_t i = 0; i < n; i++) {
+            double d[3], f, fp, fpp, t; int32_t k; int lin;
+            double ri = 0.0;
+            for (int64_t q = fl->start[i]; q < fl->start[i + 1]; q++) {
+                double r2 = sep(x, n, i, fl->nbr[q], L, d);
+                if (!(r2 < crho2)) continue;
+                spline_eval(&p->rho, sqrt(r2), 0, &f, &fp, &fpp, &k, &t, &lin);
+                ri += f;
+            }
+            rho[i] = ri;
+            spline_eval(&p->emb, ri, 1, &f, &fp, &fpp, &k, &t, &lin);
+            Fp[i] = fp;
+            E += f;
+        }
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : E, W)
+        for (int64_t i = 0; i < n; i++) {
+            double d[3], f, fp, fpp, t; int32_t k; int lin;
+            double fi[3] = { 0.0, 0.0, 0.0 };
+            for (int64_t q = fl->start[i]; q < fl->start[i + 1]; q++) {
+                int64_t j = fl->nbr[q];
+                double r2 = sep(x, n, i, j, L, d);
+                int in_phi = r2 < cphi2, in_rho = r2 < crho2;
+                if (!in_phi && !in_rho) continue;
+                double r = sqrt(r2), g = 0.0;
+                if (in_phi) {
+                    spline_eval(&p->phi, r, 0, &f, &fp, &fpp, &k, &t, &lin);
+                    E += 0.5 * f;
+                    g += fp;
+                }
+                if (in_rho) {
+                    spline_eval(&p->rho, r, 0, &f, &fp, &fpp, &k, &t, &lin);
+                    g += (Fp[i] + Fp[j]) * fp;
+                }
+                double c[3] = { -g * d[0] / r, -g * d[1] / r, -g * d[2] / r };
+                fi[0] += c[0]; fi[1] += c[1]; fi[2] += c[2];
+                W += 0.5 * ((d[0] * c[0] + d[1] * c[1]) + d[2] * c[2]);
+            }
+            X(F, n, i) = fi[0]; Y(F, n, i) = fi[1]; Z(F, n, i) = fi[2];
+        }
+    }
+    ew[0] = E;
+    ew[1] = W;
+}
+
+/* Arguments and history as orc_verlet; nthreads > 0 sets the thread count.
+ * Returns 0, or -2 (box too small). */
+int orc_verlet_omp(int64_t n, double *x, double *v, double *F, const double L[3], int kind,
+                   const double *lj, const int32_t nk[3], const double x0[3], const double h[3],
+                   const double *cphi, const double *crho, const double *cemb, double rc_phi,
+                   double rc_rho, double rc, double skin, double dt, double mass, int32_t nsteps,
+                   double *hist, int32_t *nrebuild, int32_t nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    orc_eam_pot pot;
+    memset(&pot, 0, sizeof(pot));
+    if (kind == 1) pot = make_eam(nk, x0, h, cphi, crho, cemb, rc_phi, rc_rho);
+    double rl = rc + skin;
+    double thr = (0.5 * skin) * (0.5 * skin);
+    double c = 0.5 * dt / mass;
+    double ew[2];
+    double *xref = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double *rho = (double *)malloc(sizeof(double) * (size_t)n);
+    double *Fp = (double *)malloc(sizeof(double) * (size_t)n);
+    fulllist fl = { 0, NULL, NULL };
+    orc_wrap(n, x, L);
+    if (build_full_omp(n, x, L, rl, &fl) != 0) { free(xref); free(rho); free(Fp); return -2; }
+    memcpy(xref, x, sizeof(double) * 3 * (size_t)n);
+    *nrebuild = 0;
+    full_forces_omp(n, x, L, kind, rc, lj, &pot, &fl, F, ew, rho, Fp);
+    for (int32_t s = 0; s < nsteps; s++) {
+        double dmax = 0.0;
+#pragma omp parallel for reduction(max : dmax)
+        for (int64_t i = 0; i < n; i++) {
+            for (int a = 0; a < 3; a++) {
+                v[a * n + i] = v[a * n + i] + c * F[a * n + i];
+                x[a * n + i] = x[a * n + i] + dt * v[a * n + i];
+                x[a * n + i] = wrap1(x[a * n + i], L[a]);
+            }
+            double dd[3];
+            dd[0] = minimg1(X(x, n, i) - X(xref, n, i), L[0]);
+            dd[1] = minimg1(Y(x, n, i) - Y(xref, n, i), L[1]);
+            dd[2] = minimg1(Z(x, n, i) - Z(xref, n, i), L[2]);
+            double r2 = (dd[0] * dd[0] + dd[1] * dd[1]) + dd[2] * dd[2];
+            if (r2 > dmax) dmax = r2;
+        }
+        if (dmax > thr) {
+            build_full_omp(n, x, L, rl, &fl);
+            memcpy(xref, x, sizeof(double) * 3 * (size_t)n);
+            *nrebuild += 1;
+        }
+        full_forces_omp(n, x, L, kind, rc, lj, &pot, &fl, F, ew, rho, Fp);
+        double ke = 0.0;
+#pragma omp parallel for reduction(+ : ke)
+        for (int64_t i = 0; i < n; i++) {
+            for (int a = 0; a < 3; a++) v[a * n + i] = v[a * n + i] + c * F[a * n + i];
+            ke += (X(v, n, i) * X(v, n, i) + Y(v, n, i) * Y(v, n, i)) + Z(v, n, i) * Z(v, n, i);
+        }
+        hist[3 * s + 0] = ew[0];
+        hist[3 * s + 1] = 0.5 * mass * ke;
+        hist[3 * s + 2] = ew[1];
+    }
+    free(xref); free(rho); free(Fp); free(fl.start); free(fl.nbr);
+    return 0;
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -26,7 +26,7 @@ FLAG_OVERFLOW, FLAG_NONFINITE, FLAG_SCHEDULE = 1, 2, 4
 EXPORTS = ["md_create", "md_destroy", "md_build_cells", "md_build_neighbor_list",
            "md_compute_forces", "md_verlet_step", "md_force_vjp", "md_get_status",
            "md_get_neighbor_list", "md_get_cells", "md_get_waves", "md_get_task_graph", "md_set_tuning", "md_query", "md_profile",
-           "md_last_error"]
+           "md_profile_detail", "md_last_error"]
 
 
 class MDError(RuntimeError):
@@ -77,10 +77,12 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     L.md_set_tuning.argtypes = [vp, i32, i32]
     L.md_query.argtypes = [vp, i32, P(i64)]
     L.md_profile.argtypes = [vp, i32, P(d), P(i64), P(d), P(i64)]
+    L.md_profile_detail.argtypes = [vp, P(d), i32]
     L.md_last_error.argtypes = [vp]
     L.md_last_error.restype = C.c_char_p
     for name in ("md_build_cells", "md_build_neighbor_list", "md_compute_forces", "md_verlet_step",
-                 "md_force_vjp", "md_get_status", "md_get_cells", "md_set_tuning", "md_query", "md_profile"):
+                 "md_force_vjp", "md_get_status", "md_get_cells", "md_set_tuning", "md_query", "md_profile",
+                 "md_profile_detail"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -289,3 +291,13 @@ def md_profile(ctx: Context, enable: bool):
     if enable:
         return None
     return float(fm.value), int(fn.value), float(ln.value), int(lc.value)
+
+
+def md_profile_detail(ctx: Context) -> dict:
+    """Timings of the profiled md_verlet_step calls (after md_profile(ctx, False))."""
+    out = (C.c_double * 8)()
+    _check(ctx.h, load().md_profile_detail(ctx.h, out, 8))
+    v = list(out)
+    return {"loop_ms": v[0], "loop_steps": int(v[1]), "setup_ms": v[2],
+            "force_plain_ms": v[3], "force_plain_n": int(v[4]),
+            "force_energy_ms": v[5], "force_energy_n": int(v[6]), "force_setup_ms": v[7]}

@@ -171,6 +171,14 @@ struct md_ctx {
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_force, ev_list;
+    // kind of each force launch: 0 F(x0) of md_verlet_step's setup (or a
+    // md_compute_forces call), 1 a step that records no energies, 2 a recorded step
+    std::vector<int8_t> ev_force_kind;
+    int8_t force_kind = 0;
+    // md_verlet_step: its setup (load, sort, list, F(x0)) and its step loop
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_setup, ev_loop;
+    int64_t prof_steps = 0;
+    double detail[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     hipEvent_t next_event()
     {
         if (ev_used == ev_pool.size()) {
@@ -744,7 +752,17 @@ void timed(md_ctx *c, hipStream_t s, std::vector<std::pair<hipEvent_t, hipEvent_
     if (c->prof && a && b) {
         (void)hipEventRecord(b, s);
         log.emplace_back(a, b);
+        if (&log == &c->ev_force) c->ev_force_kind.push_back(c->force_kind);
     }
+}
+
+// records one event when profiling is on (null otherwise)
+hipEvent_t mark(md_ctx *c, hipStream_t s)
+{
+    if (!c->prof) return nullptr;
+    hipEvent_t e = c->next_event();
+    if (e) (void)hipEventRecord(e, s);
+    return e;
 }
 
 } // namespace
@@ -948,6 +966,7 @@ int md_verlet_step(md_ctx *c, const md_potential *p, int32_t precision, int32_t 
     const int ga = c->grid_atoms(256);
 
     // initial state: user order -> sorted, cells and list from scratch
+    hipEvent_t ev_begin = mark(c, s);
     hipLaunchKernelGGL(k_set_ctl, dim3(1), dim3(64), 0, s, c->ctl, 1, 1);
     launch_load_user(s, ga, c->n, pos, vel, c->pos[c->cur], c->vel, c->id);
     sort_into_tmp(c, c->one, true, s);
@@ -1046,8 +1065,10 @@ int md_verlet_step(md_ctx *c, const md_potential *p, int32_t precision, int32_t 
 
     if (half) launch_zero(s, ga, c->force, 3 * c->n);
     // F(x0), first half kick and drift; requests a rebuild for step 1 if needed
+    c->force_kind = 0;
     forces_and_step(1, &c->ctl->rebuild[0], &c->ctl->rebuild[1], nullptr);
     c->cur = 1 - c->cur;
+    hipEvent_t ev_loop0 = mark(c, s);
     for (int32_t st = 1; st <= n_steps; st++) {
         int32_t *pred = &c->ctl->rebuild[st & 1];
         sort_into_tmp(c, pred, true, s);
@@ -1062,9 +1083,17 @@ int md_verlet_step(md_ctx *c, const md_potential *p, int32_t precision, int32_t 
         const int mode = st < n_steps ? 2 : 3;
         // energies of every hist_every-th step and of the last one
         const bool rec = hist != nullptr && (st % hist_every == 0 || st == n_steps);
+        c->force_kind = rec ? 2 : 1;
         forces_and_step(mode, pred, &c->ctl->rebuild[(st + 1) & 1],
                         rec ? hist + 3 * (int64_t)((st + hist_every - 1) / hist_every - 1) : nullptr);
         if (mode == 2) c->cur = 1 - c->cur;
+    }
+    hipEvent_t ev_loop1 = mark(c, s);
+    c->force_kind = 0;
+    if (ev_begin && ev_loop0 && ev_loop1) {
+        c->ev_setup.emplace_back(ev_begin, ev_loop0);
+        c->ev_loop.emplace_back(ev_loop0, ev_loop1);
+        c->prof_steps += n_steps;
     }
     launch_pos_to_user(s, ga, c->n, c->R, c->reps, c->rep_of, c->id, c->pos[c->cur], pos);
     launch_to_user(s, ga, c->n, c->id, c->vel, vel);
@@ -1368,7 +1397,11 @@ int md_profile(md_ctx *c, int32_t enable, double *force_ms, int64_t *force_n, do
         if (c->last != nullptr && hipStreamSynchronize(c->last) != hipSuccess)
             return fail(c, MD_ERR_HIP, "synchronise");
         c->ev_force.clear();
+        c->ev_force_kind.clear();
         c->ev_list.clear();
+        c->ev_setup.clear();
+        c->ev_loop.clear();
+        c->prof_steps = 0;
         c->ev_used = 0;
         c->prof = true;
         return MD_OK;
@@ -1384,15 +1417,46 @@ int md_profile(md_ctx *c, int32_t enable, double *force_ms, int64_t *force_n, do
         }
         return true;
     };
-    double fm = 0.0, lm = 0.0;
-    if (!total(c->ev_force, fm) || !total(c->ev_list, lm)) return fail(c, MD_ERR_HIP, "event timing");
+    double fm = 0.0, lm = 0.0, sm = 0.0, pm = 0.0;
+    if (!total(c->ev_force, fm) || !total(c->ev_list, lm) || !total(c->ev_setup, sm) || !total(c->ev_loop, pm))
+        return fail(c, MD_ERR_HIP, "event timing");
+    // force launches by kind
+    double km[3] = {0.0, 0.0, 0.0};
+    int64_t kn[3] = {0, 0, 0};
+    for (size_t k = 0; k < c->ev_force.size(); k++) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, c->ev_force[k].first, c->ev_force[k].second) != hipSuccess)
+            return fail(c, MD_ERR_HIP, "event timing");
+        const int kind = k < c->ev_force_kind.size() ? c->ev_force_kind[k] : 0;
+        km[kind] += (double)t;
+        kn[kind] += 1;
+    }
+    c->detail[0] = pm;
+    c->detail[1] = (double)c->prof_steps;
+    c->detail[2] = sm;
+    c->detail[3] = km[1];
+    c->detail[4] = (double)kn[1];
+    c->detail[5] = km[2];
+    c->detail[6] = (double)kn[2];
+    c->detail[7] = km[0];
     if (force_ms) *force_ms = fm;
     if (force_n) *force_n = (int64_t)c->ev_force.size();
     if (list_ms) *list_ms = lm;
     if (list_n) *list_n = (int64_t)c->ev_list.size();
     c->ev_force.clear();
+    c->ev_force_kind.clear();
     c->ev_list.clear();
+    c->ev_setup.clear();
+    c->ev_loop.clear();
+    c->prof_steps = 0;
     c->ev_used = 0;
+    return MD_OK;
+}
+
+int md_profile_detail(md_ctx *c, double *out, int32_t n_out)
+{
+    if (c == nullptr || out == nullptr || n_out < 0) return MD_ERR_ARG;
+    for (int32_t k = 0; k < n_out && k < 8; k++) out[k] = c->detail[k];
     return MD_OK;
 }
 
