@@ -148,6 +148,27 @@ int md_build_neighbor_list(md_ctx *ctx, int32_t list_kind, void *stream);
 int md_compute_forces(md_ctx *ctx, const md_potential *pot, int32_t precision, double *forces,
                       double *energy, double *virial, void *stream);
 
+/* md_compute_forces for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, kernels and results, but every scratch
+ * buffer the call's kernels use -- sorted forces, block partials, counters,
+ * the brick queue, EAM densities and staged tables, per-atom energies of a
+ * multi-replica context -- lies in one static device array of the library,
+ * MD_NOALLOC_BYTES = 48 MiB per device (md_query key 16), held by every device
+ * the library runs on until the process ends.  The call allocates nothing and
+ * calls no allocating routine; the context, cells and list must already exist
+ * (md_create, md_build_cells, md_build_neighbor_list with MD_LIST_FULL).
+ * It needs 24 bytes per atom, 16 more for EAM, 16 more for energies of a
+ * multi-replica context, and about 130 KiB besides (LJ up to about 2.0M atoms,
+ * EAM up to about 1.2M); a larger system is rejected with MD_ERR_ARG before
+ * anything is enqueued.  Every call on a device shares that device's array
+ * (the counters it needs zeroed are cleared at the start of each call), so
+ * calls that overlap in time on one device -- on different streams or from
+ * different threads -- race and give wrong results; serialise them.
+ * Errors: as md_compute_forces, plus MD_ERR_STATE (list kind other than full). */
+int md_compute_forces_noalloc(md_ctx *ctx, const md_potential *pot, int32_t precision,
+                              double *forces, double *energy, double *virial, void *stream);
+
 /* n_steps of velocity Verlet (the per-particle integration loop of Sec. II.A):
  * cells and list are rebuilt from pos, forces F(x0) computed; then per step
  * v += dt/(2m) F; x += dt v; wrap; if max_i |minimage(x_i - x_i^ref)|^2 >
@@ -271,7 +292,8 @@ int md_set_tuning(md_ctx *ctx, int32_t key, int32_t value);
  * schedule in use (1 static ranges, 2 queue), 15 entries of the current list
  * stored as 16-bit candidate indices (bricks on axes of at least 4 cells
  * whose whole halo fits the LDS stage; the others store 32-bit entries with
- * an image code; synchronises).
+ * an image code; synchronises), 16 bytes of the static scratch array of
+ * md_compute_forces_noalloc.
  * Returns MD_OK, MD_ERR_ARG, MD_ERR_STATE (keys 10 and 15 without a list) or MD_ERR_HIP. */
 int md_query(md_ctx *ctx, int32_t key, int64_t *value);
 

@@ -26,7 +26,7 @@ FLAG_OVERFLOW, FLAG_NONFINITE, FLAG_SCHEDULE = 1, 2, 4
 EXPORTS = ["md_create", "md_destroy", "md_build_cells", "md_build_neighbor_list",
            "md_compute_forces", "md_verlet_step", "md_force_vjp", "md_get_status",
            "md_get_neighbor_list", "md_get_cells", "md_get_waves", "md_get_task_graph", "md_set_tuning", "md_query", "md_profile",
-           "md_profile_detail", "md_last_error"]
+           "md_profile_detail", "md_compute_forces_noalloc", "md_last_error"]
 
 
 class MDError(RuntimeError):
@@ -65,6 +65,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     L.md_build_cells.argtypes = [vp, vp, P(d), d, d, vp]
     L.md_build_neighbor_list.argtypes = [vp, i32, vp]
     L.md_compute_forces.argtypes = [vp, P(md_potential), i32, vp, vp, vp, vp]
+    L.md_compute_forces_noalloc.argtypes = [vp, P(md_potential), i32, vp, vp, vp, vp]
     L.md_verlet_step.argtypes = [vp, P(md_potential), i32, i32, vp, vp, vp, d, d, i32, vp, i32, vp, vp]
     L.md_force_vjp.argtypes = [vp, P(md_potential), i32, vp, vp, vp, vp, vp, vp]
     L.md_get_status.argtypes = [vp, P(i32), P(i64)]
@@ -80,7 +81,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     L.md_profile_detail.argtypes = [vp, P(d), i32]
     L.md_last_error.argtypes = [vp]
     L.md_last_error.restype = C.c_char_p
-    for name in ("md_build_cells", "md_build_neighbor_list", "md_compute_forces", "md_verlet_step",
+    for name in ("md_build_cells", "md_build_neighbor_list", "md_compute_forces", "md_compute_forces_noalloc",
+                 "md_verlet_step",
                  "md_force_vjp", "md_get_status", "md_get_cells", "md_set_tuning", "md_query", "md_profile",
                  "md_profile_detail"):
         getattr(L, name).restype = C.c_int
@@ -195,6 +197,12 @@ def md_compute_forces(ctx: Context, pot: DevicePotential, precision: int, forces
                       virial=None, stream=None):
     _check(ctx.h, load().md_compute_forces(ctx.h, C.byref(pot.s), int(precision), _ptr(forces),
                                            _ptr(energy), _ptr(virial), _stream(stream)))
+
+
+def md_compute_forces_noalloc(ctx: Context, pot: DevicePotential, precision: int, forces, energy=None,
+                              virial=None, stream=None):
+    _check(ctx.h, load().md_compute_forces_noalloc(ctx.h, C.byref(pot.s), int(precision), _ptr(forces),
+                                                   _ptr(energy), _ptr(virial), _stream(stream)))
 
 
 def md_verlet_step(ctx: Context, pot: DevicePotential, precision: int, kind: int, pos, vel, forces,

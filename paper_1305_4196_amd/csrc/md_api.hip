@@ -9,11 +9,22 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "md_brick.h"
 #include "md_waves.h"
+
+// Device memory of md_compute_forces_noalloc: every scratch buffer its kernels
+// use (sorted forces, block partials, counters, brick queue, EAM densities and
+// tables, per-atom energies) is carved out of this array, so the call allocates
+// nothing.  Each device the library runs on holds one copy until the process
+// ends; its address on a device comes from hipGetSymbolAddress (the array's name
+// in host code is a host-side stand-in, never a device address).
+#define MD_NOALLOC_BYTES (48ull << 20)
+static __device__ __align__(256) unsigned char scratch[MD_NOALLOC_BYTES];
 
 namespace {
 
@@ -165,6 +176,7 @@ struct md_ctx {
     int64_t tab_cap = 0;
     DevCtl *ctl = nullptr;
     int32_t *one = nullptr;
+    unsigned char *scratch_dev = nullptr;   // this device's copy of `scratch`
 
     // event timing (md_profile)
     bool prof = false;
@@ -693,6 +705,24 @@ ForceArgs force_args(md_ctx *c, const md_potential *p)
     return a;
 }
 
+// The device address of `scratch` on device dev, looked up once per device
+// (with that device current) and kept.
+std::mutex g_scratch_mu;
+std::map<int, unsigned char *> g_scratch_dev;
+
+int scratch_address(int dev, unsigned char **out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_dev.find(dev);
+    if (it == g_scratch_dev.end()) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return MD_ERR_HIP;
+        it = g_scratch_dev.emplace(dev, static_cast<unsigned char *>(p)).first;
+    }
+    *out = it->second;
+    return MD_OK;
+}
+
 int check_pot(md_ctx *c, const md_potential *p)
 {
     if (p == nullptr) return fail(c, MD_ERR_ARG, "potential is null");
@@ -782,6 +812,10 @@ int md_create(md_ctx **out, int64_t n, int32_t R, const int64_t *off)
     c->R = R;
     c->off.assign(off, off + R + 1);
     if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return MD_ERR_HIP;
+    }
+    if (scratch_address(c->device, &c->scratch_dev) != MD_OK) {
         delete c;
         return MD_ERR_HIP;
     }
@@ -940,6 +974,91 @@ int md_compute_forces(md_ctx *c, const md_potential *p, int32_t precision, doubl
         launch_replica_sums(s, c->R, c->reps, c->eatom, c->watom, energy, virial);
     launch_to_user(s, c->grid_atoms(256), c->n, c->id, c->force, forces);
     return check_hip(c, "md_compute_forces");
+}
+
+int md_compute_forces_noalloc(md_ctx *c, const md_potential *p, int32_t precision, double *forces,
+                              double *energy, double *virial, void *stream)
+{
+    if (c == nullptr) return MD_ERR_ARG;
+    if (forces == nullptr) return fail(c, MD_ERR_ARG, "forces is null");
+    if (precision != MD_FP64 && precision != MD_MIXED) return fail(c, MD_ERR_ARG, "unknown precision");
+    if (!c->have_list) return fail(c, MD_ERR_STATE, "md_build_neighbor_list first");
+    if (c->list_kind != MD_LIST_FULL) return fail(c, MD_ERR_STATE, "md_compute_forces_noalloc needs a full list");
+    int rcode = check_pot(c, p);
+    if (rcode != MD_OK) return rcode;
+    if (c->scratch_dev == nullptr) return fail(c, MD_ERR_STATE, "no scratch address for this device");
+    const bool eam = p->kind == MD_POT_EAM;
+    const bool per_atom = c->R > 1 && (energy != nullptr || virial != nullptr);
+    int64_t ntab = 0;
+    if (eam) {
+        const md_spline *sp[3] = {&p->phi, &p->rho, &p->embed};
+        for (int k = 0; k < 3; k++) ntab += 4 * (int64_t)(sp[k]->n_knots - 1);
+    }
+    // carve the scratch: [counters | brick queue | partials | forces | rho, F' | tables | per-atom E, W]
+    auto up = [](uint64_t b) { return (b + 255) & ~(uint64_t)255; };
+    const uint64_t n = (uint64_t)c->n;
+    uint64_t o_done = 0;
+    uint64_t o_queue = up(o_done + 4 * sizeof(uint32_t));
+    uint64_t o_part = up(o_queue + sizeof(TaskQueue));
+    uint64_t o_force = up(o_part + (uint64_t)c->max_grid() * 4 * sizeof(double));
+    uint64_t o_rho = up(o_force + 3 * n * sizeof(double));
+    uint64_t o_fp = up(o_rho + (eam ? n * sizeof(double) : 0));
+    uint64_t o_t64 = up(o_fp + (eam ? n * sizeof(double) : 0));
+    uint64_t o_t32 = up(o_t64 + (uint64_t)ntab * sizeof(double));
+    uint64_t o_e = up(o_t32 + (uint64_t)ntab * sizeof(float));
+    uint64_t o_w = up(o_e + (per_atom ? n * sizeof(double) : 0));
+    const uint64_t need = up(o_w + (per_atom ? n * sizeof(double) : 0));
+    if (need > MD_NOALLOC_BYTES) {
+        char msg[200];
+        snprintf(msg, sizeof msg, "md_compute_forces_noalloc: this system needs %llu bytes of scratch, "
+                 "the library holds %llu", (unsigned long long)need, (unsigned long long)MD_NOALLOC_BYTES);
+        return fail(c, MD_ERR_ARG, msg);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    c->last = s;
+    unsigned char *base = c->scratch_dev;
+    // the counters and the queue must start at zero (a fill kernel, no memset node)
+    launch_zero(s, 1, reinterpret_cast<double *>(base), (int64_t)(o_part / sizeof(double)));
+    const bool mixed = precision == MD_MIXED;
+    ForceArgs a = force_args(c, p);
+    a.mode = 0;
+    a.done = reinterpret_cast<uint32_t *>(base + o_done);
+    a.ftq = reinterpret_cast<TaskQueue *>(base + o_queue);
+    a.partial = reinterpret_cast<double *>(base + o_part);
+    a.force = reinterpret_cast<double *>(base + o_force);
+    if (eam) {
+        a.rho = reinterpret_cast<double *>(base + o_rho);
+        a.fp = reinterpret_cast<double *>(base + o_fp);
+        double *t64 = reinterpret_cast<double *>(base + o_t64);
+        float *t32 = reinterpret_cast<float *>(base + o_t32);
+        const md_spline *sp[3] = {&p->phi, &p->rho, &p->embed};
+        int64_t o = 0;
+        for (int k = 0; k < 3; k++) {
+            const int64_t m = 4 * (int64_t)(sp[k]->n_knots - 1);
+            if (hipMemcpyAsync(t64 + o, sp[k]->coef, sizeof(double) * m, hipMemcpyDeviceToDevice, s) != hipSuccess)
+                return fail(c, MD_ERR_HIP, "tables: copy");
+            a.tab[k] = t64 + o;
+            a.tabf[k] = t32 + o;
+            o += m;
+        }
+        launch_tables_f32(s, t64, t32, ntab);
+    }
+    if (c->R == 1) {
+        a.outE = energy;
+        a.outW = virial;
+    } else if (per_atom) {
+        a.eatom = reinterpret_cast<double *>(base + o_e);
+        a.watom = reinterpret_cast<double *>(base + o_w);
+    }
+    if (p->kind == MD_POT_LJ) {
+        launch_lj_full(s, c->grid_tasks(0, false), c->threads, mixed, a);
+    } else {
+        launch_eam_density(s, c->grid_density(mixed, p), c->threads, mixed, a);
+        launch_eam_force(s, c->grid_tasks(1, false), c->threads, mixed, a);
+    }
+    if (per_atom) launch_replica_sums(s, c->R, c->reps, a.eatom, a.watom, energy, virial);
+    launch_to_user(s, c->grid_atoms(256), c->n, c->id, a.force, forces);
+    return check_hip(c, "md_compute_forces_noalloc");
 }
 
 int md_verlet_step(md_ctx *c, const md_potential *p, int32_t precision, int32_t kind, double *pos,
@@ -1360,7 +1479,8 @@ int md_query(md_ctx *c, int32_t key, int64_t *value)
         *value = t;
         return MD_OK;
     }
-    default: return fail(c, MD_ERR_ARG, "query: key 0..15");
+    case 16: *value = (int64_t)MD_NOALLOC_BYTES; return MD_OK;
+    default: return fail(c, MD_ERR_ARG, "query: key 0..16");
     }
 }
 
