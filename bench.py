@@ -111,7 +111,7 @@ def cpu_baseline(w, steps: int, threads: int):
 
 
 # ---------------------------------------------------------------------- one MD workload
-def tune_system(B, sysm, args, precision):
+def tune_system(B, sysm, args, precision, w=None):
     """Brick shape and workgroup size: fixed by the flags, else the autotuner's."""
     if args.brick or args.threads:
         if args.brick:
@@ -123,9 +123,10 @@ def tune_system(B, sysm, args, precision):
     if args.no_tune:
         return {"source": "occupancy heuristic"}
     from paper_1305_4196_amd import tune
-    best = tune.tune(sysm, precision=precision)
+    best = tune.tune(sysm, precision=precision, dt=w.dt if w is not None else 0.005,
+                     mass=w.mass if w is not None else 1.0)
     log(f"tuned: brick {best['shape']} on {best['threads']} threads "
-        f"({best['ms'] * 1e3:.1f} us per force + amortised build)")
+        f"({best['ms'] * 1e3:.1f} us per step)")
     return {"source": "autotuner", "shape": "x".join(str(v) for v in best["shape"]), "threads": best["threads"],
             "candidates": [{"shape": "x".join(str(v) for v in c["shape"]), "threads": c["threads"],
                             "us": round(c["ms"] * 1e3, 1)} for c in best.get("candidates", [])]}
@@ -256,7 +257,7 @@ def bench_md(args, name, steps, warmup, thermo, paths=("mixed", "fp64"), errors=
     if args.shell:
         B.md_set_tuning(sysm.ctx, 6, 1)
     prec_of = {"mixed": B.MD_MIXED, "fp64": B.MD_FP64}
-    tuning = tune_system(B, sysm, args, prec_of[paths[0]]) if tune else {"source": "occupancy heuristic"}
+    tuning = tune_system(B, sysm, args, prec_of[paths[0]], w) if tune else {"source": "occupancy heuristic"}
     kind = {"full": B.MD_LIST_FULL, "half": B.MD_LIST_HALF, "waves": B.MD_LIST_WAVES,
             "deps": B.MD_LIST_DEPS}[args.list]
     pos0 = torch.tensor(w.pos, dtype=torch.float64, device="cuda")
@@ -335,7 +336,10 @@ def bench_batch(args, kind, reps=None, cpu=True):
     else:
         theta = torch.tensor(np.concatenate([start.phi.coef.ravel(), start.rho.coef.ravel(),
                                              start.embed.coef.ravel()]), dtype=torch.float64, device="cuda")
-    fit = BatchedFit(sysm, F_star, theta)
+    fit = BatchedFit(sysm, F_star, theta, tune=not (args.brick or args.threads or args.no_tune))
+    if fit.tuning is not None:
+        log(f"{w.name}: tuned brick {fit.tuning['shape']} on {fit.tuning['threads']} threads "
+            f"({fit.tuning['ms'] * 1e3:.1f} us per forces + adjoint)")
     fit.capture()
     for _ in range(3):
         fit.gradient()
@@ -353,7 +357,12 @@ def bench_batch(args, kind, reps=None, cpu=True):
     log(f"{w.name}: graph replay {t * 1e3:.3f} ms per batch gradient, loss {fit.loss():.4e}")
     out = {"batch_gradients_per_s": round(1.0 / t, 2), "replica_gradients_per_s": round(w.n_replicas / t, 1),
            "atom_gradients_per_s": round(n / t, 1), "ms_per_batch_gradient": round(t * 1e3, 4),
-           "replicas": w.n_replicas, "atoms": n, "params": int(theta.numel()), "dtype": "f64", "replays": reps}
+           "replicas": w.n_replicas, "atoms": n, "params": int(theta.numel()), "dtype": "f64", "replays": reps,
+           "tuning": ({"source": "autotuner (forces + adjoint)",
+                       "shape": "x".join(str(v) for v in fit.tuning["shape"]), "threads": fit.tuning["threads"],
+                       "candidates": [{"shape": "x".join(str(v) for v in c["shape"]), "threads": c["threads"],
+                                       "us": round(c["ms"] * 1e3, 1)} for c in fit.tuning.get("candidates", [])]}
+                      if fit.tuning is not None else {"source": "flags or occupancy heuristic"})}
     if cpu:
         m = 16
         F_np = F_star.cpu().numpy()

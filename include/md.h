@@ -140,7 +140,15 @@ int md_build_cells(md_ctx *ctx, const double *pos, const double *boxes_host, dou
  * Errors: MD_ERR_STATE (no cells), MD_ERR_HIP. */
 int md_build_neighbor_list(md_ctx *ctx, int32_t list_kind, void *stream);
 
-/* Forces at the current cells/list.  forces: [3][N] out, user order.
+/* Forces at the current cells/list: the force calculation over the Verlet
+ * lists, the per-cell work of Sec. II.A (pair potential, or the many-body
+ * potential of Sec. II.C in two passes, density then force).  The list of
+ * md_build_neighbor_list decides which pairs are candidates; the r < rc test
+ * runs in binary64 on r2 formed with fused multiply-adds (and, in bricks
+ * staged through their cell images, from the pre-shifted partner position),
+ * so a pair whose r2 lies within a few roundings of rc^2 may be counted where
+ * the exhaustive definition would not, or the other way round; every other
+ * pair is decided exactly as there.  forces: [3][N] out, user order.
  * energy, virial: [n_replicas] out (DEVICE), per replica E and scalar virial
  * W = sum_{i<j} d_ij . f_ij; either may be NULL.  Sums are taken in a fixed
  * order (bitwise repeatable for the full list).
@@ -199,6 +207,10 @@ int md_verlet_step(md_ctx *ctx, const md_potential *pot, int32_t precision, int3
  * (2 doubles); EAM the three tables' shapes back to back, phi then rho then
  * embed ((n_knots-1) x 4 each).  Either output may be NULL.  Parameter
  * histograms use binary64 atomics (last-bit order not deterministic).
+ * The adjoint always evaluates in binary64: precision is checked (MD_FP64 or
+ * MD_MIXED) but both give the binary64 result, the derivative of the FP64
+ * forces.  The adjoint is not in the paper; it differentiates the forces of
+ * Sec. II.A/II.C through the same lists.
  * Errors: MD_ERR_ARG, MD_ERR_STATE, MD_ERR_HIP. */
 int md_force_vjp(md_ctx *ctx, const md_potential *pot, int32_t precision, const double *pos,
                  const double *u_forces, const double *v_energy, double *g_pos,
@@ -277,7 +289,13 @@ int64_t md_get_task_graph(md_ctx *ctx, int32_t *succ_off, int32_t *succ, int64_t
  *   (default) as many as fit beside the stage (the last intervals of the phi
  *   and rho tables, where the pairs fall, and the embedding table when it
  *   fits whole); 0 none (every term a global atomic).  The gradient does not
- *   depend on it beyond the summation order.
+ *   depend on it beyond the summation order;
+ * key 9 = whether the adjoint kernels stage each candidate's cotangent (and,
+ *   for EAM pass B, its F' and F'' rho-dot) in LDS beside its position: 1
+ *   (default) when that larger stage fits a workgroup's LDS without costing
+ *   resident workgroups (LJ, EAM pass A) or LDS room of the parameter sums
+ *   (EAM pass B), 0 never (every pair gathers them from global memory).  The
+ *   result does not depend on it.
  * Returns MD_OK or MD_ERR_ARG. */
 int md_set_tuning(md_ctx *ctx, int32_t key, int32_t value);
 

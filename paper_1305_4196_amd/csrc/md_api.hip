@@ -123,6 +123,7 @@ struct md_ctx {
     TaskQueue *ftq = nullptr;
     int32_t sched_mode = 0;
     int32_t gwin_limit = -1;   // most table intervals the EAM adjoint sums in LDS (-1: as many as fit)
+    int32_t stage_u = 1;       // adjoint kernels stage partner cotangents in LDS when they fit
     bool sparse = false;
     // waves of bricks with disjoint write sets (MD_LIST_WAVES)
     bool waves_valid = false;
@@ -1248,10 +1249,11 @@ int md_force_vjp(md_ctx *c, const md_potential *p, int32_t precision, const doub
     v.gpart = c->partial + (size_t)c->max_grid() * 12;
     v.rdot = c->rdot;
     v.fpp = c->fpp;
+    v.stage_u = c->stage_u;
     const int gh = c->grid_tasks(0, true);
     if (p->kind == MD_POT_LJ) {
         v.gout = g_params;
-        launch_lj_vjp(s, gh, c->threads, v);
+        launch_lj_vjp(s, gh, c->threads, v, c->lds_max);
     } else {
         v.gtab = g_params;
         if (g_params != nullptr) {
@@ -1259,7 +1261,7 @@ int md_force_vjp(md_ctx *c, const md_potential *p, int32_t precision, const doub
                             4 * (int64_t)(p->embed.n_knots - 1);
             launch_zero(s, 64, g_params, total);
         }
-        launch_eam_vjp_a(s, gh, c->threads, v);
+        launch_eam_vjp_a(s, gh, c->threads, v, c->lds_max);
         launch_eam_vjp_b(s, gh, c->threads, v, c->lds_max, c->gwin_limit);
         if (g_params != nullptr) launch_eam_vjp_embed(s, ga, v, c->lds_max, c->gwin_limit);
     }
@@ -1405,6 +1407,10 @@ int md_set_tuning(md_ctx *c, int32_t key, int32_t value)
         c->gwin_limit = value;
         return MD_OK;
     }
+    if (key == 9 && (value == 0 || value == 1)) {
+        c->stage_u = value;
+        return MD_OK;
+    }
     if (key == 6 && (value == 0 || value == 1)) {
         c->shell = value == 1;
         c->have_list = false;
@@ -1416,7 +1422,8 @@ int md_set_tuning(md_ctx *c, int32_t key, int32_t value)
                                "key 3 a brick shape, key 4 threads per task (0 or 128..512, multiple of 64), "
                                "key 5 a wait limit >= 0 (microseconds), key 6 the half-list rule (0 or 1), "
                                "key 7 the brick schedule (0 auto, 1 static ranges, 2 queue), "
-                               "key 8 the EAM adjoint's LDS intervals (>= -1)");
+                               "key 8 the EAM adjoint's LDS intervals (>= -1), "
+                               "key 9 adjoint partner values staged in LDS (0 or 1)");
 }
 
 int md_query(md_ctx *c, int32_t key, int64_t *value)
@@ -1435,7 +1442,7 @@ int md_query(md_ctx *c, int32_t key, int64_t *value)
     case 5: *value = c->B; return MD_OK;
     case 6:
     case 7: {
-        if (c->last != nullptr && hipStreamSynchronize(c->last) != hipSuccess) return fail(c, MD_ERR_HIP, "synchronise");
+        if (hipStreamSynchronize(c->last) != hipSuccess) return fail(c, MD_ERR_HIP, "synchronise");
         DevCtl h{};
         if (hipMemcpy(&h, c->ctl, sizeof(DevCtl), hipMemcpyDeviceToHost) != hipSuccess)
             return fail(c, MD_ERR_HIP, "status readback");
@@ -1446,7 +1453,7 @@ int md_query(md_ctx *c, int32_t key, int64_t *value)
     case 9: *value = c->bricks_valid ? c->grid_tasks(0, false) : 0; return MD_OK;
     case 10: {
         if (!c->have_list) return fail(c, MD_ERR_STATE, "no list");
-        if (c->last != nullptr && hipStreamSynchronize(c->last) != hipSuccess) return fail(c, MD_ERR_HIP, "synchronise");
+        if (hipStreamSynchronize(c->last) != hipSuccess) return fail(c, MD_ERR_HIP, "synchronise");
         std::vector<int32_t> cnt(c->n);
         if (hipMemcpy(cnt.data(), c->cnt, sizeof(int32_t) * c->n, hipMemcpyDeviceToHost) != hipSuccess)
             return fail(c, MD_ERR_HIP, "list length readback");
@@ -1462,7 +1469,7 @@ int md_query(md_ctx *c, int32_t key, int64_t *value)
     case 15: {
         // entries of atoms in bricks whose list uses the 16-bit layout
         if (!c->have_list) return fail(c, MD_ERR_STATE, "no list");
-        if (c->last != nullptr && hipStreamSynchronize(c->last) != hipSuccess) return fail(c, MD_ERR_HIP, "synchronise");
+        if (hipStreamSynchronize(c->last) != hipSuccess) return fail(c, MD_ERR_HIP, "synchronise");
         const int32_t stride = c->bd.stride;
         std::vector<int32_t> cnt(c->n), rec((size_t)(c->B * stride));
         if (hipMemcpy(cnt.data(), c->cnt, sizeof(int32_t) * c->n, hipMemcpyDeviceToHost) != hipSuccess ||
@@ -1514,7 +1521,7 @@ int md_profile(md_ctx *c, int32_t enable, double *force_ms, int64_t *force_n, do
 {
     if (c == nullptr) return MD_ERR_ARG;
     if (enable) {
-        if (c->last != nullptr && hipStreamSynchronize(c->last) != hipSuccess)
+        if (hipStreamSynchronize(c->last) != hipSuccess)
             return fail(c, MD_ERR_HIP, "synchronise");
         c->ev_force.clear();
         c->ev_force_kind.clear();
@@ -1527,7 +1534,7 @@ int md_profile(md_ctx *c, int32_t enable, double *force_ms, int64_t *force_n, do
         return MD_OK;
     }
     c->prof = false;
-    if (c->last != nullptr && hipStreamSynchronize(c->last) != hipSuccess) return fail(c, MD_ERR_HIP, "synchronise");
+    if (hipStreamSynchronize(c->last) != hipSuccess) return fail(c, MD_ERR_HIP, "synchronise");
     auto total = [](const std::vector<std::pair<hipEvent_t, hipEvent_t>> &v, double &ms) {
         ms = 0.0;
         for (auto &p : v) {

@@ -333,12 +333,14 @@ __device__ __forceinline__ double image_shift(uint32_t code, uint32_t add_bit, d
 
 // Copies the record of brick b into LDS and stages its first `cap` candidates
 // (block-wide; ends with a barrier).  extra0/extra1 (may be null) are staged
-// as extras 0 and 1.  A brick with BR_SHIFT = 1 has its candidates staged
-// through their halo cell's image (x_j - shift, so that x_i - x_j' is the
-// shifted difference); pairs of it take no image code.
+// as extras 0 and 1; vec (may be null) as three more extras (its x, y, z)
+// starting at extra vec_at.  A brick with BR_SHIFT = 1 has its candidates
+// staged through their halo cell's image (x_j - shift, so that x_i - x_j' is
+// the shifted difference); pairs of it take no image code.
 __device__ __forceinline__ void brick_load(const Stage &s, const BrickDims &d, const int32_t *grec,
                                            const RepDesc *reps, const double4 *pos,
-                                           const double *extra0, const double *extra1)
+                                           const double *extra0, const double *extra1,
+                                           const double4 *vec = nullptr, int vec_at = 0)
 {
     for (int32_t t = threadIdx.x; t < d.stride; t += blockDim.x) s.rec[t] = grec[t];
     __syncthreads();
@@ -373,6 +375,13 @@ __device__ __forceinline__ void brick_load(const Stage &s, const BrickDims &d, c
         if (s.j != nullptr) s.j[k] = g;
         if (extra0 != nullptr) s.ex[k] = extra0[g];
         if (extra1 != nullptr) s.ex[s.cap + k] = extra1[g];
+        if (vec != nullptr) {
+            const double4 u = vec[g];
+            double *e = s.ex + (size_t)vec_at * s.cap + k;
+            e[0] = u.x;
+            e[s.cap] = u.y;
+            e[2 * (size_t)s.cap] = u.z;
+        }
     }
     __syncthreads();
 }
@@ -632,7 +641,8 @@ __device__ __forceinline__ BrickRange balanced_bricks(const int64_t *w, int64_t 
 // lanes take the brick's atoms (la = a0 + thread) in rounds of blockDim.x.
 // Defines for the body: natoms, rep_r, Lx/Ly/Lz, all_staged, has_img, valid,
 // la, i (sorted index), mm (list length, capped at M).
-#define BRICK_TASK_BEGIN(ST, POS, EXTRA0, EXTRA1)                                          \
+#define BRICK_TASK_BEGIN(ST, POS, EXTRA0, EXTRA1) BRICK_TASK_BEGIN_V(ST, POS, EXTRA0, EXTRA1, nullptr, 0)
+#define BRICK_TASK_BEGIN_V(ST, POS, EXTRA0, EXTRA1, VEC, VEC_AT)                           \
     const bool dyn_ = a.dyn != 0;                                                         \
     const BrickRange br_ = dyn_ ? BrickRange{0, a.B, 1} : balanced_bricks(a.bwork, a.B);  \
     __shared__ int32_t qslot_;                                                            \
@@ -642,7 +652,7 @@ __device__ __forceinline__ BrickRange balanced_bricks(const int64_t *w, int64_t 
         const int32_t natoms = __builtin_amdgcn_readfirstlane(grec_[BR_ATOMS]);           \
         if (natoms == 0) continue;                                                        \
         __syncthreads();                                                                  \
-        brick_load(ST, a.bd, grec_, a.reps, POS, EXTRA0, EXTRA1);                         \
+        brick_load(ST, a.bd, grec_, a.reps, POS, EXTRA0, EXTRA1, VEC, VEC_AT);            \
         const int32_t rep_r = ST.rec[BR_REP];                                             \
         const bool has_img = ST.rec[BR_SHIFT] == 0;                                       \
         const bool all_staged = ST.rec[BR_TOTAL] <= ST.cap;                               \

@@ -16,10 +16,16 @@
 // face).
 //
 // Precision (MIXED = false: all binary64):
-//   displacement, image shift, r2 and the r2 < rc^2 test are always binary64
-//   (the pair set of a force call equals the exhaustive one); with MIXED the
-//   pair scalar (LJ 24 eps (2 q12 - q6)/r2 and V; EAM table polynomials) is
-//   evaluated in binary32, then projected and accumulated in binary64.
+//   displacement, image shift, r2 and the r2 < rc^2 test are always binary64;
+//   with MIXED the pair scalar (LJ 24 eps (2 q12 - q6)/r2 and V; EAM table
+//   polynomials) is evaluated in binary32, then projected and accumulated in
+//   binary64.  The list build forms r2 operation by operation, as the
+//   exhaustive definition does, so lists are exact; here r2 is formed with
+//   fused multiply-adds and, in bricks staged through their cell images, from
+//   the partner's pre-shifted position, so the cutoff test of a force call can
+//   decide differently from the exhaustive one for a pair whose r2 lies within
+//   a few roundings of rc^2 (either decision is a valid result; every other
+//   pair is decided the same way).
 //
 // Integration (mode): once the atom's force is known, its lane applies the
 // velocity-Verlet pieces of this atom (the per-particle loop of Sec. II.A) --

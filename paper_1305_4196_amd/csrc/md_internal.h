@@ -222,16 +222,17 @@ struct VjpArgs {
     double *gx;               // [3][n] sorted out
     double *gpart;            // LJ: [grid][4] parameter partials
     double *gtab;             // EAM: [3][(nk-1)*4] parameter gradient (atomics)
-    double *rdot;             // EAM pass A output
-    double *fpp;              // EAM F''
+    double *rdot;             // EAM pass A output: rho-dot
+    double *fpp;              // EAM pass A output: q = F'' rho-dot
     double *gout;             // LJ: 2 doubles out (final)
     int32_t gw_p, gw_r;       // EAM: trailing intervals of the phi and rho tables whose
                               // parameter gradient a workgroup sums in LDS first
                               // (embedding pass: gw_p = intervals of its table, or 0)
     int32_t gw_off;           // byte offset of those sums in the dynamic LDS
+    int32_t stage_u;          // 1: stage the partners' cotangents (and EAM F', q) in LDS when they fit
 };
-void launch_lj_vjp(hipStream_t s, int grid, int threads, const VjpArgs &a);
-void launch_eam_vjp_a(hipStream_t s, int grid, int threads, const VjpArgs &a);
+void launch_lj_vjp(hipStream_t s, int grid, int threads, const VjpArgs &a, int32_t lds_max);
+void launch_eam_vjp_a(hipStream_t s, int grid, int threads, const VjpArgs &a, int32_t lds_max);
 void launch_eam_vjp_b(hipStream_t s, int grid, int threads, const VjpArgs &a, int32_t lds_max, int32_t limit);
 void launch_eam_vjp_embed(hipStream_t s, int grid, const VjpArgs &a, int32_t lds_max, int32_t limit);
 

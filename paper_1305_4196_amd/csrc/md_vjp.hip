@@ -66,20 +66,36 @@ __device__ __forceinline__ void embed_full(const ForceArgs &a, double rho, doubl
 }
 
 // ---------------------------------------------------------------- LJ
-// two 512-thread workgroups per CU (at most 128 VGPRs)
+// Partner cotangent u_j of candidate k: from the LDS stage (extras ex0..ex0+2)
+// when the kernel stages it (STAGE_U) and k is staged, else gathered from HBM.
+template <bool STAGE_U, bool STAGED>
+__device__ __forceinline__ double4 partner_u(const Stage &st, const BrickDims &bd, const double4 *u, int32_t k,
+                                             int ex0)
+{
+    if (STAGE_U && (STAGED || k < st.cap)) {
+        const double *e = st.ex + (size_t)ex0 * st.cap + k;
+        return make_double4(e[0], e[st.cap], e[2 * (size_t)st.cap], 0.0);
+    }
+    return u[STAGE_U ? candidate_index(st, bd, k) : candidate_j<STAGED>(st, bd, k)];
+}
+
+// two 512-thread workgroups per CU (at most 128 VGPRs).  STAGE_U: the partner
+// cotangents are staged in LDS beside the positions (when the larger stage
+// fits the LDS), instead of gathered from HBM per pair.
+template <bool STAGE_U>
 __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_lj_vjp(VjpArgs v)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ double lds[4 * TASK_MAX_THREADS / 64];
     const ForceArgs &a = v.f;
-    const Stage st = stage_slice(lds_raw, a.cap, 0, true);
+    const Stage st = stage_slice(lds_raw, a.cap, STAGE_U ? 3 : 0, !STAGE_U);
     const int64_t n = a.n;
     const double eps = a.lj[0], sig = a.lj[1];
     const double s2 = sig * sig;
     const double rc2 = a.rc2;
     const double e24 = 24.0 * eps;
     double acc_e = 0.0, acc_s = 0.0;
-    BRICK_TASK_BEGIN(st, a.pos, nullptr, nullptr)
+    BRICK_TASK_BEGIN_V(st, a.pos, nullptr, nullptr, STAGE_U ? v.u : nullptr, 0)
         double F[3] = {0.0, 0.0, 0.0}, Hu[3] = {0.0, 0.0, 0.0};
         const double vE = v.vE[rep_r];
         const double4 xi = a.pos[i];
@@ -89,7 +105,6 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_lj_vjp(VjpArgs v)
             walk_list<STAGED, IMG>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
                 [&](bool ok, int32_t k, double dx, double dy, double dz, double r2) {
                     if (!ok || !(r2 < rc2)) return;
-                    const int32_t j = candidate_j<STAGED>(st, a.bd, k);
                     const double d[3] = {dx, dy, dz};
                     const double ir2 = rcp64(r2);
                     const double q2 = s2 * ir2;
@@ -100,7 +115,7 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_lj_vjp(VjpArgs v)
                     const double fs = e24 * t2r;
                     const double B = -fs;
                     const double C = 96.0 * eps * (7.0 * q12 - 2.0 * q6) * (ir2 * ir2);
-                    const double4 uj = v.u[j];
+                    const double4 uj = partner_u<STAGE_U, STAGED>(st, a.bd, v.u, k, 0);
                     const double uij[3] = {ui[0] - uj.x, ui[1] - uj.y, ui[2] - uj.z};
                     const double du = (d[0] * uij[0] + d[1] * uij[1]) + d[2] * uij[2];
                     const double Cd = C * du;
@@ -128,15 +143,17 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_lj_vjp(VjpArgs v)
 }
 
 // ---------------------------------------------------------------- EAM pass A
+// rho_i, F'_i and q_i = F''_i rho-dot_i (v.fpp holds q: pass B needs F'' only
+// in that product).
+template <bool STAGE_U>
 __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_vjp_a(VjpArgs v)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const ForceArgs &a = v.f;
-    const Stage st = stage_slice(lds_raw, a.cap, 0, true);
-    const int64_t n = a.n;
+    const Stage st = stage_slice(lds_raw, a.cap, STAGE_U ? 3 : 0, !STAGE_U);
     const int nkr = a.nk[1];
     const double x0r = a.x0[1], ihr = a.inv_h[1], rrho2 = a.rrho2;
-    BRICK_TASK_BEGIN(st, a.pos, nullptr, nullptr)
+    BRICK_TASK_BEGIN_V(st, a.pos, nullptr, nullptr, STAGE_U ? v.u : nullptr, 0)
         double rho = 0.0, rdot = 0.0;
         const double4 xi = a.pos[i];
         const double4 ui4 = v.u[i];
@@ -145,12 +162,11 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_vjp_a(VjpArgs v)
             walk_list<STAGED, IMG>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
                 [&](bool ok, int32_t k, double dx, double dy, double dz, double r2) {
                     if (!ok || !(r2 < rrho2)) return;
-                    const int32_t j = candidate_j<STAGED>(st, a.bd, k);
                     const double r = sqrt(r2);
                     int kk;
                     double tt, f, fu, fuu;
                     spl_full(a.tab[1], (r - x0r) * ihr, nkr, kk, tt, f, fu, fuu);
-                    const double4 uj = v.u[j];
+                    const double4 uj = partner_u<STAGE_U, STAGED>(st, a.bd, v.u, k, 0);
                     const double uij[3] = {ui[0] - uj.x, ui[1] - uj.y, ui[2] - uj.z};
                     const double s = ((dx * uij[0] + dy * uij[1]) + dz * uij[2]) * rcp64(r);
                     rho += f;
@@ -164,18 +180,21 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_vjp_a(VjpArgs v)
             embed_full(a, rho, F, Fp, Fpp, kk, tt, lin);
             a.rho[i] = rho;
             a.fp[i] = Fp;
-            v.fpp[i] = Fpp;
+            v.fpp[i] = Fpp * rdot;
             v.rdot[i] = rdot;
         }
     BRICK_TASK_END
 }
 
 // ---------------------------------------------------------------- EAM pass B
+// STAGE_U: the partners' F', q = F'' rho-dot and cotangent are staged in LDS
+// beside their positions (extras 0, 1 and 2..4) instead of gathered per pair.
+template <bool STAGE_U>
 __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_vjp_b(VjpArgs v)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const ForceArgs &a = v.f;
-    const Stage st = stage_slice(lds_raw, a.cap, 0, true);
+    const Stage st = stage_slice(lds_raw, a.cap, STAGE_U ? 5 : 0, true);
     const int64_t n = a.n;
     const int nkp = a.nk[0], nkr = a.nk[1];
     const double x0p = a.x0[0], ihp = a.inv_h[0], x0r = a.x0[1], ihr = a.inv_h[1];
@@ -190,25 +209,36 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_vjp_b(VjpArgs v)
     double *lphi = reinterpret_cast<double *>(lds_raw + v.gw_off), *lrho = lphi + 4 * wp;
     for (int32_t t = threadIdx.x; t < 4 * (wp + wr); t += blockDim.x) lphi[t] = 0.0;
     __syncthreads();
-    BRICK_TASK_BEGIN(st, a.pos, nullptr, nullptr)
+    BRICK_TASK_BEGIN_V(st, a.pos, STAGE_U ? a.fp : nullptr, STAGE_U ? v.fpp : nullptr,
+                       STAGE_U ? v.u : nullptr, 2)
         double F[3] = {0.0, 0.0, 0.0}, Hu[3] = {0.0, 0.0, 0.0};
         const double vE = v.vE[rep_r];
         const double4 xi = a.pos[i];
         const double4 ui4 = v.u[i];
         const double ui[3] = {ui4.x, ui4.y, ui4.z};
         const double fpi = a.fp[i];
-        const double qi = v.fpp[i] * v.rdot[i];
+        const double qi = v.fpp[i];
         STAGE_IMG_SPLIT(all_staged, has_img,
             walk_list<STAGED, IMG>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
                 [&](bool ok, int32_t k, double dx, double dy, double dz, double r2) {
                     const bool in_phi = r2 < rphi2, in_rho = r2 < rrho2;
                     if (!ok || (!in_phi && !in_rho)) return;
+                    // partner index (the parameter sums take each pair once, j > i),
+                    // F'_j and q_j, staged or gathered
                     const int32_t j = candidate_j<STAGED>(st, a.bd, k);
+                    double fpj, qj;
+                    if (STAGE_U && (STAGED || k < st.cap)) {
+                        fpj = st.ex[k];
+                        qj = st.ex[st.cap + k];
+                    } else {
+                        fpj = a.fp[j];
+                        qj = v.fpp[j];
+                    }
                     const double r = sqrt(r2);
                     // one refined reciprocal instead of four divisions
                     const double ir = rcp64(r);
                     const double e[3] = {dx * ir, dy * ir, dz * ir};
-                    const double4 uj = v.u[j];
+                    const double4 uj = partner_u<STAGE_U, STAGED>(st, a.bd, v.u, k, 2);
                     const double uij[3] = {ui[0] - uj.x, ui[1] - uj.y, ui[2] - uj.z};
                     const double s = (e[0] * uij[0] + e[1] * uij[1]) + e[2] * uij[2];
                     double ph = 0.0, php = 0.0, phpp = 0.0, rh = 0.0, rhp = 0.0, rhpp = 0.0;
@@ -226,10 +256,10 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_vjp_b(VjpArgs v)
                         rhp = fu * ihr;
                         rhpp = fuu * (ihr * ihr);
                     }
-                    const double Fs = fpi + a.fp[j];
+                    const double Fs = fpi + fpj;
                     const double gsc = php + Fs * rhp;
                     const double gg = phpp + Fs * rhpp;
-                    const double qq = qi + v.fpp[j] * v.rdot[j];
+                    const double qq = qi + qj;
                     // H u along e and along u_ij: (gg s - (gsc/r) s + qq rho') e + (gsc/r) u_ij
                     const double G = gsc * ir;
                     const double Ae = fma(gg - G, s, qq * rhp);
@@ -319,18 +349,53 @@ __global__ __launch_bounds__(256) void k_eam_vjp_embed(VjpArgs v)
 
 } // namespace
 
-void launch_lj_vjp(hipStream_t s, int grid, int threads, const VjpArgs &a)
+// The staged-cotangent variants need 24 (LJ, pass A) or 40 (pass B) more bytes of
+// LDS per candidate; they run when that stage fits one workgroup's LDS (with
+// room for the kernel's static LDS) and v.stage_u allows it.
+// workgroups of `threads` that one CU holds with `lds` bytes each
+inline int per_cu(const void *kernel, int threads, size_t lds)
 {
-    const size_t lds = stage_bytes(a.f.cap, 0, true, a.f.bd.stride);
-    allow_lds(k_lj_vjp, lds);
-    hipLaunchKernelGGL(k_lj_vjp, dim3(resident_grid(k_lj_vjp, grid, threads, lds)), dim3(threads), lds, s, a);
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, threads, lds) != hipSuccess) return 0;
+    return occ;
 }
 
-void launch_eam_vjp_a(hipStream_t s, int grid, int threads, const VjpArgs &a)
+void launch_lj_vjp(hipStream_t s, int grid, int threads, const VjpArgs &a, int32_t lds_max)
 {
+    const size_t lds_u = stage_bytes(a.f.cap, 3, false, a.f.bd.stride);
+    const size_t lds_g = stage_bytes(a.f.cap, 0, true, a.f.bd.stride);
+    if (a.stage_u && lds_u + 256 <= (size_t)lds_max) allow_lds(k_lj_vjp<true>, lds_u);
+    if (a.stage_u && lds_u + 256 <= (size_t)lds_max &&
+        per_cu(reinterpret_cast<const void *>(k_lj_vjp<true>), threads, lds_u) >=
+            per_cu(reinterpret_cast<const void *>(k_lj_vjp<false>), threads, lds_g)) {
+        allow_lds(k_lj_vjp<true>, lds_u);
+        hipLaunchKernelGGL(k_lj_vjp<true>, dim3(resident_grid(k_lj_vjp<true>, grid, threads, lds_u)), dim3(threads),
+                           lds_u, s, a);
+        return;
+    }
     const size_t lds = stage_bytes(a.f.cap, 0, true, a.f.bd.stride);
-    allow_lds(k_eam_vjp_a, lds);
-    hipLaunchKernelGGL(k_eam_vjp_a, dim3(resident_grid(k_eam_vjp_a, grid, threads, lds)), dim3(threads), lds, s, a);
+    allow_lds(k_lj_vjp<false>, lds);
+    hipLaunchKernelGGL(k_lj_vjp<false>, dim3(resident_grid(k_lj_vjp<false>, grid, threads, lds)), dim3(threads), lds,
+                       s, a);
+}
+
+void launch_eam_vjp_a(hipStream_t s, int grid, int threads, const VjpArgs &a, int32_t lds_max)
+{
+    const size_t lds_u = stage_bytes(a.f.cap, 3, false, a.f.bd.stride);
+    const size_t lds_g = stage_bytes(a.f.cap, 0, true, a.f.bd.stride);
+    if (a.stage_u && lds_u + 256 <= (size_t)lds_max) allow_lds(k_eam_vjp_a<true>, lds_u);
+    if (a.stage_u && lds_u + 256 <= (size_t)lds_max &&
+        per_cu(reinterpret_cast<const void *>(k_eam_vjp_a<true>), threads, lds_u) >=
+            per_cu(reinterpret_cast<const void *>(k_eam_vjp_a<false>), threads, lds_g)) {
+        allow_lds(k_eam_vjp_a<true>, lds_u);
+        hipLaunchKernelGGL(k_eam_vjp_a<true>, dim3(resident_grid(k_eam_vjp_a<true>, grid, threads, lds_u)),
+                           dim3(threads), lds_u, s, a);
+        return;
+    }
+    const size_t lds = stage_bytes(a.f.cap, 0, true, a.f.bd.stride);
+    allow_lds(k_eam_vjp_a<false>, lds);
+    hipLaunchKernelGGL(k_eam_vjp_a<false>, dim3(resident_grid(k_eam_vjp_a<false>, grid, threads, lds)),
+                       dim3(threads), lds, s, a);
 }
 
 // The parameter-gradient sums in LDS take what the workgroups that fit on a CU
@@ -338,17 +403,19 @@ void launch_eam_vjp_a(hipStream_t s, int grid, int threads, const VjpArgs &a)
 // 512-thread workgroup per CU): as many trailing intervals of each pair table
 // as fit, none when the stage alone fills it.  Smaller workgroups would fit
 // several per CU; then the LDS request may leave fewer of them resident.
-void launch_eam_vjp_b(hipStream_t s, int grid, int threads, const VjpArgs &a0, int32_t lds_max, int32_t limit)
+template <bool STAGE_U>
+void launch_eam_vjp_b_t(hipStream_t s, int grid, int threads, const VjpArgs &a0, int32_t lds_max, int32_t limit)
 {
+    auto kernel = k_eam_vjp_b<STAGE_U>;
     VjpArgs a = a0;
-    const size_t stage = (stage_bytes(a.f.cap, 0, true, a.f.bd.stride) + 15) & ~(size_t)15;
+    const size_t stage = (stage_bytes(a.f.cap, STAGE_U ? 5 : 0, true, a.f.bd.stride) + 15) & ~(size_t)15;
     size_t lds = stage;
     a.gw_p = a.gw_r = 0;
     a.gw_off = (int32_t)stage;
     if (a.gtab != nullptr) {
-        allow_lds(k_eam_vjp_b, stage);
+        allow_lds(kernel, stage);
         int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_eam_vjp_b, threads, stage) != hipSuccess || occ < 1) occ = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, threads, stage) != hipSuccess || occ < 1) occ = 1;
         // fewer workgroups per CU when that is what it takes to hold the upper
         // half of the larger pair table (global atomics on the hot intervals
         // cost far more than the lost occupancy); 256 bytes stay free for the
@@ -365,8 +432,28 @@ void launch_eam_vjp_b(hipStream_t s, int grid, int threads, const VjpArgs &a0, i
         a.gw_r = (int32_t)std::min<int64_t>(w, a.f.nk[1] - 1);
         lds = stage + 32 * (size_t)(a.gw_p + a.gw_r);
     }
-    allow_lds(k_eam_vjp_b, lds);
-    hipLaunchKernelGGL(k_eam_vjp_b, dim3(resident_grid(k_eam_vjp_b, grid, threads, lds)), dim3(threads), lds, s, a);
+    allow_lds(kernel, lds);
+    hipLaunchKernelGGL(kernel, dim3(resident_grid(kernel, grid, threads, lds)), dim3(threads), lds, s, a);
+}
+
+// The staged variant only where its larger stage still leaves the parameter
+// sums as many table intervals in LDS as the gathering one gets (or half the
+// larger table): losing them to global atomics costs far more than the
+// gathers it saves.
+void launch_eam_vjp_b(hipStream_t s, int grid, int threads, const VjpArgs &a, int32_t lds_max, int32_t limit)
+{
+    auto window = [&](int nextra) {
+        const int64_t stage = (int64_t)((stage_bytes(a.f.cap, nextra, true, a.f.bd.stride) + 15) & ~(size_t)15);
+        const int64_t room = (int64_t)lds_max - 256 - stage;
+        return room > 0 ? room / 64 : (int64_t)-1;
+    };
+    const int64_t want = (std::max(a.f.nk[0], a.f.nk[1]) - 1) / 2;
+    const int64_t wu = window(5), wg = window(0);
+    const bool fits = a.gtab == nullptr ? wu >= 0 : wu >= std::min(want, wg);
+    if (a.stage_u && fits)
+        launch_eam_vjp_b_t<true>(s, grid, threads, a, lds_max, limit);
+    else
+        launch_eam_vjp_b_t<false>(s, grid, threads, a, lds_max, limit);
 }
 
 // The whole embedding table's gradient goes to LDS when it fits two 256-thread

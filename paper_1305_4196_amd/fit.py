@@ -31,7 +31,9 @@ from .system import MDSystem
 
 class BatchedFit:
     def __init__(self, system: MDSystem, target_forces: torch.Tensor, params: torch.Tensor,
-                 precision: int = B.MD_FP64, with_energy: bool = False):
+                 precision: int = B.MD_FP64, with_energy: bool = False, tune: bool = True):
+        """tune: pick the brick shape and workgroup size with the autotuner,
+        timing forces + adjoint (cached per system signature)."""
         self.s = system
         self.precision = precision
         self.with_energy = with_energy
@@ -47,6 +49,10 @@ class BatchedFit:
         self.g_pos = torch.empty_like(system.pos)
         self.g = torch.zeros(self.dpot.n_params, dtype=torch.float64, device=system.device)
         self.graph: Optional[torch.cuda.CUDAGraph] = None
+        self.tuning = None
+        if tune:
+            from . import tune as tuner
+            self.tuning = tuner.tune(system, precision=precision, objective="fit")
         system.build(B.MD_LIST_FULL)
 
     def set_params(self, theta: torch.Tensor):

@@ -7,8 +7,9 @@ workgroup size) is made per system by timing the candidates on the GPU.
 Candidates come from a score of every shape of 1..4 cells per axis on 128..512
 threads (lanes that hold an atom for a brick two standard deviations above
 the mean, wavefronts per CU the LDS stage allows, halo candidates staged per
-atom); the best-scored few are timed (one list build amortised over
-`rebuild_interval` steps plus one force launch) and the fastest is applied
+atom); the best-scored few and a fixed set of other shapes are timed (for
+dynamics: the step loop of a short velocity-Verlet run, rebuilds included;
+for fitting: one force launch plus one adjoint) and the fastest is applied
 and cached in a JSON file keyed by the system's signature.
 """
 from __future__ import annotations
@@ -70,6 +71,22 @@ def candidates(occ: float, top: int = 6) -> List[Tuple[Tuple[int, int, int], int
     return out
 
 
+# shapes timed besides the best-scored ones: the score models lane use and LDS
+# only, so a few shapes of other aspect and size are always measured too
+EXTRA_SHAPES = [((2, 2, 2), 256), ((3, 3, 2), 512), ((3, 3, 3), 512), ((4, 3, 2), 512),
+                ((4, 4, 2), 512), ((4, 4, 4), 512)]
+
+
+def candidate_set(occ: float, top: int = 4) -> List[Tuple[Tuple[int, int, int], int]]:
+    """The `top` best-scored configurations plus EXTRA_SHAPES (those whose LDS
+    stage fits), without repeats."""
+    out = list(candidates(occ, top))
+    for shape, t in EXTRA_SHAPES:
+        if (shape, t) not in out and score(shape, t, occ) > 0:
+            out.append((shape, t))
+    return out
+
+
 def occupancy(counts: np.ndarray) -> float:
     """Mean occupancy of the non-empty cells."""
     return float(counts.sum() / max(int((counts > 0).sum()), 1))
@@ -104,37 +121,75 @@ def apply(system, shape: Tuple[int, int, int], threads: int):
     B.md_set_tuning(system.ctx, 4, threads)
 
 
-def _time_config(system, shape, threads, precision, kind, rebuild_interval, reps) -> float:
+def _time_config(system, shape, threads, precision, kind, reps, objective="md", steps: int = 40,
+                 dt: float = 0.005, mass: float = 1.0) -> float:
+    """Milliseconds of one candidate: objective "md" = one velocity-Verlet step,
+    the step loop of md_verlet_step timed by the library's events over `steps`
+    steps (rebuilds included as they fall; the system's positions and
+    velocities are restored afterwards); "fit" = one force launch plus one
+    adjoint (a fitting gradient)."""
     import torch
     apply(system, shape, threads)
+    if objective == "md":
+        x0, v0 = system.pos.clone(), system.vel.clone()
+        F = torch.empty_like(system.pos)
+        best = float("inf")
+        try:
+            for _ in range(reps):
+                system.pos.copy_(x0)
+                system.vel.copy_(v0)
+                B.md_build_cells(system.ctx, system.pos, system.boxes, system.pot.rc, system.skin)
+                B.md_verlet_step(system.ctx, system.dpot, precision, kind, system.pos, system.vel, F,
+                                 dt, mass, 2, None, None)
+                B.md_profile(system.ctx, True)
+                B.md_verlet_step(system.ctx, system.dpot, precision, kind, system.pos, system.vel, F,
+                                 dt, mass, steps, None, None)
+                B.md_profile(system.ctx, False)
+                d = B.md_profile_detail(system.ctx)
+                best = min(best, d["loop_ms"] / max(d["loop_steps"], 1))
+        finally:
+            system.pos.copy_(x0)
+            system.vel.copy_(v0)
+        code = B.md_get_status(system.ctx)[0]
+        if code != B.MD_OK:
+            raise B.MDError(code, "tuning run failed")
+        return best
     system.build(kind)                      # sizes the list and the LDS stage
     F = torch.empty_like(system.pos)
     B.md_compute_forces(system.ctx, system.dpot, precision, F, None, None)
+    u = torch.ones_like(system.pos)
+    vE = torch.zeros(system.R, dtype=torch.float64, device=system.device)
+    g = torch.empty_like(system.pos)
+    gp = torch.zeros(system.dpot.n_params, dtype=torch.float64, device=system.device)
+    B.md_force_vjp(system.ctx, system.dpot, precision, None, u, vE, g, gp)
     torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     best = float("inf")
     for _ in range(reps):
         ev[0].record()
-        B.md_build_neighbor_list(system.ctx, kind)
-        ev[1].record()
         B.md_compute_forces(system.ctx, system.dpot, precision, F, None, None)
-        ev[2].record()
+        B.md_force_vjp(system.ctx, system.dpot, precision, None, u, vE, g, gp)
+        ev[1].record()
         torch.cuda.synchronize()
-        t_list = ev[0].elapsed_time(ev[1])
-        t_force = ev[1].elapsed_time(ev[2])
-        best = min(best, t_force + t_list / rebuild_interval)
+        best = min(best, ev[0].elapsed_time(ev[1]))
     code = B.md_get_status(system.ctx)[0]
     if code != B.MD_OK:
         raise B.MDError(code, "tuning run failed")
     return best
 
 
-def tune(system, precision: int = B.MD_MIXED, kind: int = B.MD_LIST_FULL, rebuild_interval: float = 9.0,
-         top: int = 6, reps: int = 3, cache_path: Optional[str] = None, use_cache: bool = True) -> dict:
+def tune(system, precision: int = B.MD_MIXED, kind: int = B.MD_LIST_FULL, top: int = 4, reps: int = 2,
+         cache_path: Optional[str] = None, use_cache: bool = True, objective: str = "md",
+         dt: float = 0.005, mass: float = 1.0) -> dict:
     """Pick and apply the fastest brick shape / workgroup size for `system`
-    (an MDSystem whose cells are built); returns the chosen entry."""
+    (an MDSystem whose cells are built); returns the chosen entry.  objective
+    "md" times velocity-Verlet steps (forces, integration, rebuilds), "fit"
+    the gradient of a fitting batch (forces + adjoint); dt and mass are those of
+    the dynamics the "md" timing runs."""
+    if objective not in ("md", "fit"):
+        raise ValueError("objective is 'md' or 'fit'")
     B.md_build_cells(system.ctx, system.pos, system.boxes, system.pot.rc, system.skin)
-    key = f"{signature(system)}-p{precision}-k{kind}"
+    key = f"{signature(system)}-p{precision}-k{kind}-{objective}"
     cache = load_cache(cache_path) if use_cache else {}
     if key in cache:
         e = cache[key]
@@ -143,11 +198,11 @@ def tune(system, precision: int = B.MD_MIXED, kind: int = B.MD_LIST_FULL, rebuil
     cs, _ = B.md_get_cells(system.ctx)
     occ = occupancy(np.diff(cs))
     results = []
-    for shape, t in candidates(occ, top):
-        ms = _time_config(system, shape, t, precision, kind, rebuild_interval, reps)
+    for shape, t in candidate_set(occ, top):
+        ms = _time_config(system, shape, t, precision, kind, reps, objective, dt=dt, mass=mass)
         results.append({"shape": list(shape), "threads": t, "ms": ms})
     results.sort(key=lambda e: e["ms"])
-    best = dict(results[0], candidates=results)
+    best = dict(results[0], candidates=results, objective=objective)
     apply(system, tuple(best["shape"]), best["threads"])
     if use_cache:
         cache[key] = best

@@ -20,13 +20,13 @@ def flat_params(pot):
                         dtype=torch.float64, device="cuda")
 
 
-def make_fit(kind, n_replicas, window=-1):
+def make_fit(kind, n_replicas, window=-1, tune_fit=False):
     w = W.replica_batch(kind, n_replicas=n_replicas, nmin=200, nmax=1200)
     s = MDSystem.from_workload(w)
     B.md_set_tuning(s.ctx, 8, window)
     F_star, _, _ = s.forces(B.MD_FP64)                      # targets at the reference parameters
     start = W.perturb_params(w.pot)
-    fit = BatchedFit(s, F_star, flat_params(start))
+    fit = BatchedFit(s, F_star, flat_params(start), tune=tune_fit)
     return w, s, start, fit
 
 
@@ -122,7 +122,7 @@ def test_tuner_picks_a_working_configuration(tmp_path):
                                              w.boxes[0]))
     s = MDSystem.from_workload(w)
     best = tune.tune(s, precision=B.MD_FP64, top=3, reps=1, cache_path=str(tmp_path / "t.json"))
-    assert best["threads"] % 64 == 0 and len(best["candidates"]) == 3
+    assert best["threads"] % 64 == 0 and len(best["candidates"]) >= 3
     F, E, Wv = s.forces(B.MD_FP64)
     L = w.boxes[0]
     Fo, Eo, Wo = oracle.forces(oracle.wrap(w.pos, L), L, w.pot, skin=w.skin)
@@ -141,7 +141,7 @@ def test_energies_on_request_leave_the_gradient_unchanged():
     w, s, start, fit = make_fit("lj", 6)
     g0 = fit.gradient().clone()
     F0 = fit.F.clone()
-    fit_e = BatchedFit(s, fit.F_star, fit.params, with_energy=True)
+    fit_e = BatchedFit(s, fit.F_star, fit.params, with_energy=True, tune=False)
     g1 = fit_e.gradient().clone()
     torch.cuda.synchronize()
     assert torch.equal(fit_e.F, F0)
@@ -150,3 +150,25 @@ def test_energies_on_request_leave_the_gradient_unchanged():
     E = torch.zeros(s.R, dtype=torch.float64, device=s.device)
     B.md_compute_forces(s.ctx, fit_e.dpot, B.MD_FP64, F, E)
     assert torch.equal(fit_e.E, E)
+
+
+@pytest.mark.parametrize("kind", ["lj", "eam"])
+def test_batch_gradient_matches_oracle_at_workload_sizes(kind):
+    """64 replicas drawn from the timed batch's size range (200 to 4,000 atoms,
+    up to 5 cells per axis for LJ and 8 for EAM), so that the multi-replica
+    brick tasks run their 16-bit staged-image path in the forward and adjoint
+    kernels; gradient against the oracle's, replica by replica."""
+    w = W.replica_batch(kind, n_replicas=64)
+    sizes = np.diff(w.offsets)
+    assert sizes.max() > 3500 and sizes.min() < 500
+    s = MDSystem.from_workload(w)
+    F_star, _, _ = s.forces(B.MD_FP64)
+    ncell = np.floor(w.boxes / (w.pot.rc + w.skin)).max()
+    assert ncell >= (5 if kind == "lj" else 8)
+    assert B.md_query(s.ctx, 15) > 0, "no list entries in the 16-bit layout"
+    start = W.perturb_params(w.pot)
+    fit = BatchedFit(s, F_star, flat_params(start))          # autotuned for forces + adjoint
+    assert fit.tuning is not None and fit.tuning["objective"] == "fit"
+    g = fit.gradient().cpu().numpy()
+    go = oracle_gradient(w, w.pot, F_star.cpu().numpy(), start)
+    assert np.linalg.norm(g - go) <= 1e-10 * np.linalg.norm(go)

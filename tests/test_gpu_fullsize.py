@@ -98,3 +98,24 @@ def test_fs_eam_1418342():
     print(f"fs_eam: mixed force error {err:.3e}")
     assert err <= MIXED_TOL
     assert Emx.item() == pytest.approx(Eo, rel=1e-7)
+
+
+@pytest.mark.parametrize("name", ["lj_cluster_slab", "fs_eam_1418342"])
+def test_verlet_10_steps_inhomogeneous_and_eam(name):
+    """10 binary64 velocity-Verlet steps of the full cluster + voided slab and
+    of the full EAM crystal against the oracle's run: energies of every step,
+    sampled positions and forces, rebuild counts."""
+    w = W.WORKLOADS[name]()
+    L = w.boxes[0]
+    s = MDSystem.from_workload(w)
+    F, hist, nreb = s.run(10, w.dt, w.mass, B.MD_FP64)
+    xo, vo, Fo, ho, nrebo = oracle.verlet(w.pos, w.vel, L, w.pot, w.dt, w.mass, 10, w.skin)
+    assert np.allclose(hist.cpu().numpy(), ho, rtol=1e-10, atol=1e-8)
+    sample = sample_atoms(w.n, 4096, 6)
+    d = s.pos.cpu().numpy()[:, sample] - xo[:, sample]
+    d -= L[:, None] * np.round(d / L[:, None])
+    assert np.max(np.abs(d)) < 1e-10
+    v = s.vel.cpu().numpy()[:, sample]
+    assert np.max(np.abs(v - vo[:, sample])) < 1e-9
+    assert rel(F.cpu().numpy()[:, sample], Fo[:, sample]) < 1e-9
+    assert nreb == nrebo

@@ -215,12 +215,16 @@ def test_dense_cells_lists(kind, shape, cap):
         assert len(got) == len(pi)
 
 
+# key 9: the adjoint's partner values staged in LDS (1) or gathered (0); with
+# a 64-candidate stage most partners lie beyond it either way
+@pytest.mark.parametrize("stage_u", [1, 0])
 @pytest.mark.parametrize("shape,cap", [((2, 2, 2), 0), ((1, 2, 3), 64)])
-def test_brick_shapes_eam_and_vjp(shape, cap):
+def test_brick_shapes_eam_and_vjp(shape, cap, stage_u):
     w = eam_case(5, 8, sd=0.08)
     L = w.boxes[0]
     x = oracle.wrap(w.pos, L)
     s = shaped_system(w, shape, cap)
+    B.md_set_tuning(s.ctx, 9, stage_u)
     F, E, Wv = s.forces(B.MD_FP64)
     Fo, Eo, Wo = oracle.forces(x, L, w.pot, skin=w.skin)
     assert rel(F.cpu().numpy(), Fo) <= 1e-11
@@ -454,11 +458,13 @@ def test_replica_batch_forces(kind):
 # 4 x 4 x 4 cells: 4 x 3 x 2 bricks wrap onto themselves along x (32-bit
 # entries with image codes), 2 x 2 x 2 bricks are staged through their cell
 # images (16-bit entries)
+@pytest.mark.parametrize("stage_u", [1, 0])
 @pytest.mark.parametrize("shape", [(4, 3, 2), (2, 2, 2)])
-def test_lj_vjp_matches_oracle(shape):
+def test_lj_vjp_matches_oracle(shape, stage_u):
     w = materialise(lj_cases()["fcc2048_thermal"])
     L = w.boxes[0]
     s = shaped_system(w, shape, 0)
+    B.md_set_tuning(s.ctx, 9, stage_u)
     g = np.random.default_rng(20)
     u = g.normal(size=w.pos.shape)
     vE = 0.7
@@ -477,12 +483,14 @@ def test_lj_vjp_matches_oracle(shape):
 # last 400 intervals of the pair tables only (the second neighbour shell; the
 # first lies below them and, with the whole embedding table, goes to the
 # gradient directly)
+@pytest.mark.parametrize("stage_u", [1, 0])
 @pytest.mark.parametrize("window", [-1, 0, 400])
-def test_eam_vjp_matches_oracle(window):
+def test_eam_vjp_matches_oracle(window, stage_u):
     w = eam_case(5, 7, sd=0.08)
     L = w.boxes[0]
     s = MDSystem.from_workload(w)
     B.md_set_tuning(s.ctx, 8, window)
+    B.md_set_tuning(s.ctx, 9, stage_u)
     g = np.random.default_rng(21)
     u = g.normal(size=w.pos.shape)
     vE = -0.4

@@ -35,3 +35,12 @@ def test_cache_round_trip(tmp_path):
     entry = {"shape": [4, 3, 2], "threads": 512, "ms": 0.25}
     tune.save_cache({"k": entry}, path)
     assert tune.load_cache(path) == {"k": entry}
+
+
+def test_candidate_set_adds_the_fixed_shapes():
+    for occ in (6.6, 19.1):
+        cs = tune.candidate_set(occ, top=4)
+        assert cs[:4] == tune.candidates(occ, top=4)
+        assert len(set(cs)) == len(cs)
+        for shape, t in tune.EXTRA_SHAPES:
+            assert ((shape, t) in cs) == (tune.score(shape, t, occ) > 0)
