@@ -201,8 +201,13 @@ def tune(system, precision: int = B.MD_MIXED, kind: int = B.MD_LIST_FULL, top: i
     for shape, t in candidate_set(occ, top):
         ms = _time_config(system, shape, t, precision, kind, reps, objective, dt=dt, mass=mass)
         results.append({"shape": list(shape), "threads": t, "ms": ms})
+    # the first candidate in the order tried (best-scored first) within 2 % of the
+    # fastest: timings of near-equal shapes differ run to run by about that much,
+    # and a stable choice keeps runs comparable
+    fastest = min(e["ms"] for e in results)
+    pick = next(e for e in results if e["ms"] <= 1.02 * fastest)
     results.sort(key=lambda e: e["ms"])
-    best = dict(results[0], candidates=results, objective=objective)
+    best = dict(pick, candidates=results, objective=objective)
     apply(system, tuple(best["shape"]), best["threads"])
     if use_cache:
         cache[key] = best
