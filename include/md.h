@@ -292,10 +292,10 @@ int64_t md_get_task_graph(md_ctx *ctx, int32_t *succ_off, int32_t *succ, int64_t
  *   depend on it beyond the summation order;
  * key 9 = whether the adjoint kernels stage each candidate's cotangent (and,
  *   for EAM pass B, its F' and F'' rho-dot) in LDS beside its position: 1
- *   (default) when that larger stage fits a workgroup's LDS without costing
- *   resident workgroups (LJ, EAM pass A) or LDS room of the parameter sums
- *   (EAM pass B), 0 never (every pair gathers them from global memory).  The
- *   result does not depend on it.
+ *   when that larger stage fits a workgroup's LDS without costing resident
+ *   workgroups (LJ, EAM pass A) or LDS room of the parameter sums (EAM pass
+ *   B), 0 (default) never: every pair gathers them from global memory, which
+ *   measured as fast on the replica batches.  The result does not depend on it.
  * Returns MD_OK or MD_ERR_ARG. */
 int md_set_tuning(md_ctx *ctx, int32_t key, int32_t value);
 

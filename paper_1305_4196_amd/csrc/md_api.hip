@@ -123,7 +123,7 @@ struct md_ctx {
     TaskQueue *ftq = nullptr;
     int32_t sched_mode = 0;
     int32_t gwin_limit = -1;   // most table intervals the EAM adjoint sums in LDS (-1: as many as fit)
-    int32_t stage_u = 1;       // adjoint kernels stage partner cotangents in LDS when they fit
+    int32_t stage_u = 0;       // adjoint kernels stage partner cotangents in LDS when they fit (key 9)
     bool sparse = false;
     // waves of bricks with disjoint write sets (MD_LIST_WAVES)
     bool waves_valid = false;

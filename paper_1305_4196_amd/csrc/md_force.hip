@@ -601,12 +601,13 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_density(ForceArgs a)
 
 // ---------------------------------------------------------------- EAM pass 2: forces
 // EN: the launch returns energy or virial (steps that record no energy skip
-// their per-pair terms).  At most 128 VGPRs, so that two 512-thread
-// workgroups share a CU (the few spills this costs are per atom, outside the
-// pair loop) -- except the binary64 pass with energies, which would spill
-// inside the pair loop and runs one workgroup per CU instead.
+// their per-pair terms).  The mixed pass is held to 128 VGPRs, so that two
+// 512-thread workgroups share a CU (the few spills this costs are per atom,
+// outside the pair loop); the binary64 passes would spill inside the pair loop
+// at that bound (81 VGPRs without energies: 224 MB of scratch writes per launch
+// on the replica batch) and run one workgroup per CU instead (7 % faster).
 template <bool MIXED, bool EN>
-__global__ __launch_bounds__(TASK_MAX_THREADS, (MIXED || !EN) ? 4 : 1) void k_eam_force(ForceArgs a)
+__global__ __launch_bounds__(TASK_MAX_THREADS, MIXED ? 4 : 1) void k_eam_force(ForceArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ double lds[4 * TASK_MAX_THREADS / 64];
