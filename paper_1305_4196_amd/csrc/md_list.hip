@@ -32,12 +32,17 @@ namespace {
 
 // One wavefront, one own cell e of the brick: the cell's stencil rows are
 // concatenated into one candidate sequence, loaded into registers in tiles of
-// TILE x 64 (one candidate per lane and chunk), and every atom of the cell (a
-// uniform value per iteration) is tested against the tile.  The cell's atoms
-// (in groups of up to 128) are held two per lane and broadcast with readlane.  Hits are
-// compacted with a ballot, so atom a's entries keep the candidate order; the
-// running list length is a scalar while the atom is tested and is kept in lane
-// a between tiles.
+// at most TILE chunks of 64 (one candidate per lane and chunk; the chunks are
+// spread evenly over the tiles), and every atom of the cell (a uniform value
+// per iteration) is tested against the tile.  The cell's atoms (in groups of up
+// to 128) are held two per lane and broadcast with readlane.  An atom's tests
+// against all chunks of the tile come before its stores, in one block without
+// branches.  Hits are compacted with a ballot, so atom a's entries keep the
+// candidate order; the running list length is a scalar while the atom is
+// tested and is kept in lane a between tiles.  The atom itself is excluded by
+// its position in the sequence (a scalar test), and the row is written through
+// a buffer descriptor whose range ends at the capacity, so the hardware's range
+// check drops entries beyond it (the overflow is still counted and flagged).
 constexpr int TILE = 4;
 // candidates per cell whose run starts are flagged in LDS (more: binary search)
 constexpr int CRUN = 768;
@@ -106,9 +111,119 @@ __device__ __forceinline__ void build_runs(const Stage &st, const BrickGeom &g, 
     wave_sync();
 }
 
+// Entry p of an atom's row: word (p/4) * 256 + p%4 of the row, or in the
+// narrow layout halfword (p/8) * 512 + p%8, in units of one entry.  The index
+// grows with p, so an atom's entries below the capacity M are exactly those
+// whose index is below entry_index(M).
+template <bool NARROW>
+__device__ __forceinline__ uint32_t entry_index(uint32_t p)
+{
+    return NARROW ? p + __umul24(p >> 3, 504u) : p + __umul24(p >> 2, 252u);
+}
+
+// Structured-buffer stores (records of `stride` bytes, index range-checked
+// against the descriptor's record count: a store at or beyond it is dropped).
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+__device__ void sbuf_store_i16(int16_t v, i32x4 rsrc, int32_t vindex, int32_t voffset, int32_t soffset,
+                               int32_t aux) __asm("llvm.amdgcn.struct.buffer.store.i16");
+__device__ void sbuf_store_i32(int32_t v, i32x4 rsrc, int32_t vindex, int32_t voffset, int32_t soffset,
+                               int32_t aux) __asm("llvm.amdgcn.struct.buffer.store.i32");
+
+// Buffer descriptor of gfx9: base address, stride in bits 16..29 of the
+// second word, record count, and the default data format word.
+__device__ __forceinline__ i32x4 buffer_desc(uintptr_t base, uint32_t stride, uint32_t nrec)
+{
+    i32x4 r;
+    r.x = (int32_t)(uint32_t)base;
+    r.y = (int32_t)(((uint32_t)((uint64_t)base >> 32) & 0xffffu) | (stride << 16));
+    r.z = (int32_t)nrec;
+    r.w = 0x00020000;
+    return r;
+}
+
+// What the tile tests of one cell share.
+struct CellCtx {
+    double L[3], hL[3];
+    double rl2;
+    uintptr_t nbr_addr;          // list rows (interleaved by 64 atoms)
+    int64_t group_bytes;         // bytes of 64 rows
+    uint32_t row_entries;        // entries of a row below the capacity M
+    bool wrap[3];
+};
+
+// The atoms at..at_end of a group (held in ax/ay/az, atom at in lane at - 64 half)
+// against the NCH chunks of candidates in registers.  All NCH tests of an atom
+// come first, so their binary64 chains overlap; then the hits of each chunk are
+// stored in candidate order behind the atom's running length ni.  vself is the
+// position, relative to the tile's first candidate, of the group's first atom.
+template <bool HALF, bool WRAP, bool NARROW, int NCH>
+__device__ __forceinline__ void test_tile(const CellCtx &cc, const double *cx, const double *cy, const double *cz,
+                                          const int32_t *ck, const int64_t *cj, const uint64_t *valid,
+                                          int32_t at_begin, int32_t at_end, int half, double ax, double ay,
+                                          double az, int64_t i0, int32_t vself, bool first, int32_t &cnt)
+{
+    const int lane = threadIdx.x & 63;
+    for (int32_t at = at_begin; at < at_end; at++) {
+        const int64_t i = i0 + at;
+        const int l = at - 64 * half;
+        const double xi = readlane_f64(ax, l);
+        const double yi = readlane_f64(ay, l);
+        const double zi = readlane_f64(az, l);
+        int32_t ni = first ? 0 : __builtin_amdgcn_readlane(cnt, l);
+        // the atom's row: 16 bytes per atom across a group of 64 rows in either layout
+        const i32x4 rs = buffer_desc(cc.nbr_addr + (uintptr_t)((i >> 6) * cc.group_bytes + ((i & 63) << 4)),
+                                     NARROW ? 2u : 4u, cc.row_entries);
+        const int32_t vs = vself + at;
+        uint64_t m[NCH];
+        uint32_t code[NCH];
+        _Pragma("unroll")
+        for (int c = 0; c < NCH; c++) {
+            double dx = xi - cx[c], dy = yi - cy[c], dz = zi - cz[c];
+            code[c] = 0;
+            if (WRAP) {
+                if (cc.wrap[0]) {
+                    const bool gt = dx > cc.hL[0], lt = dx < -cc.hL[0];
+                    dx = gt ? dx - cc.L[0] : (lt ? dx + cc.L[0] : dx);
+                    code[c] |= gt ? 2u : (lt ? 1u : 0u);
+                }
+                if (cc.wrap[1]) {
+                    const bool gt = dy > cc.hL[1], lt = dy < -cc.hL[1];
+                    dy = gt ? dy - cc.L[1] : (lt ? dy + cc.L[1] : dy);
+                    code[c] |= gt ? 8u : (lt ? 4u : 0u);
+                }
+                if (cc.wrap[2]) {
+                    const bool gt = dz > cc.hL[2], lt = dz < -cc.hL[2];
+                    dz = gt ? dz - cc.L[2] : (lt ? dz + cc.L[2] : dz);
+                    code[c] |= gt ? 32u : (lt ? 16u : 0u);
+                }
+            }
+            const double r2 = (dx * dx + dy * dy) + dz * dz;
+            m[c] = valid[c] & __builtin_amdgcn_ballot_w64(r2 < cc.rl2);
+            if ((vs >> 6) == c) m[c] &= ~(1ull << (vs & 63));
+            if (HALF) m[c] &= __builtin_amdgcn_ballot_w64(cj[c] > i);
+        }
+        _Pragma("unroll")
+        for (int c = 0; c < NCH; c++) {
+            if (__builtin_amdgcn_inverse_ballot_w64(m[c])) {
+                const uint32_t p = __builtin_amdgcn_mbcnt_hi((uint32_t)(m[c] >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m[c], (uint32_t)ni));
+                if (NARROW) {
+                    sbuf_store_i16((int16_t)ck[c], rs, (int32_t)entry_index<true>(p), 0, 0, 0);
+                } else {
+                    const uint32_t word = WRAP ? (uint32_t)ck[c] | (code[c] << MD_IDX_BITS) : (uint32_t)ck[c];
+                    sbuf_store_i32((int32_t)word, rs, (int32_t)entry_index<false>(p), 0, 0, 0);
+                }
+            }
+            ni += (int32_t)__popcll(m[c]);
+        }
+        cnt = lane == l ? ni : cnt;
+    }
+}
+
 // WRAP: some axis of the cell needs the minimum-image test; otherwise the
-// test and the image code are compiled out.
-template <bool HALF, bool WRAP>
+// test and the image code are compiled out.  NARROW: the brick is staged
+// through its cell images and stores bare 16-bit candidate indices.
+template <bool HALF, bool WRAP, bool NARROW>
 __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, const BrickGeom &g,
                                           int32_t e, int32_t na_all, const int32_t lc[3],
                                           const bool wrap[3], const int32_t *runs, const uint8_t *crun,
@@ -123,14 +238,35 @@ __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, co
     const int32_t nr = runs[31];
     const int32_t ncand = runs[32 + nr];
     const RepDesc &rep = a.reps[g.r];
-    const double Lx = rep.L[0], Ly = rep.L[1], Lz = rep.L[2];
-    const double hx = rep.hL[0], hy = rep.hL[1], hz = rep.hL[2];
-    const double rl2 = a.rl2;
     const int32_t M = a.nbr == nullptr ? 0 : a.M;
-    // bricks staged through their cell images store bare candidate indices,
-    // 16 bits each (every candidate index is below 65536 there)
-    const bool narrow = st.rec[BR_SHIFT] != 0;
-    const uint32_t cmask = narrow ? 0u : ~0u;
+    CellCtx cc;
+    for (int d = 0; d < 3; d++) {
+        cc.L[d] = rep.L[d];
+        cc.hL[d] = rep.hL[d];
+        cc.wrap[d] = wrap[d];
+    }
+    cc.rl2 = a.rl2;
+    // entries of an atom's row below entry M: the row is addressed as a buffer
+    // of that many entry-sized records, so stores beyond M are dropped by the
+    // buffer's range check, which is the capacity test
+    cc.row_entries = entry_index<NARROW>((uint32_t)M);
+    cc.group_bytes = (int64_t)(M >> 2) << 10;
+    cc.nbr_addr = reinterpret_cast<uintptr_t>(a.nbr);
+    // position of the cell's first atom in the candidate sequence: the cell is
+    // a distinct cell of its own stencil, so exactly one run holds k_own
+    int32_t v_own;
+    {
+        int32_t v = -1;
+        if (lane < nr) {
+            const int32_t vb = runs[32 + lane], ve = runs[32 + lane + 1], off = runs[lane];
+            if (k_own >= vb + off && k_own < ve + off) v = k_own - off;
+        }
+        const uint64_t m = __builtin_amdgcn_ballot_w64(v >= 0);
+        v_own = __builtin_amdgcn_readlane(v, m != 0 ? (int)__builtin_ctzll(m) : 0);
+    }
+    // chunks of 64 candidates, in tiles of at most TILE chunks of balanced sizes
+    const int32_t nchunks = (ncand + 63) >> 6;
+    const int32_t ntiles = (nchunks + TILE - 1) / TILE;
     int32_t tot = 0;
     // the cell's atoms in groups of up to 128 (two per lane)
     for (int32_t g0 = 0; g0 < na_all; g0 += 128) {
@@ -167,8 +303,10 @@ __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, co
         }
     }
     int32_t rbase = 0;                         // runs started before the current chunk
-    for (int32_t t0 = 0; t0 < ncand; t0 += 64 * TILE) {
-        const int32_t nch = min(TILE, (ncand - t0 + 63) >> 6);
+    int32_t c0 = 0;                            // first chunk of the tile
+    for (int32_t t = 0; t < ntiles; t++) {
+        const int32_t nch = nchunks / ntiles + (t < nchunks % ntiles ? 1 : 0);
+        const int32_t t0 = 64 * c0;
         double cx[TILE], cy[TILE], cz[TILE];
         int32_t ck[TILE];
         int64_t cj[TILE];
@@ -214,70 +352,25 @@ __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, co
         uint64_t valid[TILE];
         _Pragma("unroll")
         for (int c = 0; c < TILE; c++) valid[c] = __builtin_amdgcn_ballot_w64(ck[c] >= 0);
+        const int32_t vself = v_own + g0 - t0;
         // atoms 0..63 of the group from the first register set, 64..127 from the second
         for (int half = 0; half < 2; half++) {
             const int32_t at_end = half == 0 ? (na < 64 ? na : 64) : na;
             const double ax = half == 0 ? ax0 : ax1, ay = half == 0 ? ay0 : ay1, az = half == 0 ? az0 : az1;
             int32_t cnt = half == 0 ? cnt0 : cnt1;
-            for (int32_t at = 64 * half; at < at_end; at++) {
-                const int64_t i = i0 + at;
-                const int32_t kself = k_grp + at;
-                const int l = at - 64 * half;
-                const double xi = readlane_f64(ax, l);
-                const double yi = readlane_f64(ay, l);
-                const double zi = readlane_f64(az, l);
-                int32_t ni = t0 == 0 ? 0 : __builtin_amdgcn_readlane(cnt, l);
-                // the atom's row (uniform); entry p at word (p/4) * 256 + p%4 of
-                // it, or in the narrow layout at halfword (p/8) * 512 + p%8
-                uint32_t *base = a.nbr + (((i >> 6) * (int64_t)(a.M >> 2)) << 8) + ((i & 63) << 2);
-                uint16_t *base16 = reinterpret_cast<uint16_t *>(a.nbr) + (((i >> 6) * (int64_t)(a.M >> 2)) << 9) + ((i & 63) << 3);
-                _Pragma("unroll")
-                for (int c = 0; c < TILE; c++) {
-                    if (c < nch) {
-                        double dx = xi - cx[c], dy = yi - cy[c], dz = zi - cz[c];
-                        uint32_t code = 0;
-                        if (WRAP) {
-                            if (wrap[0]) {
-                                const bool gt = dx > hx, lt = dx < -hx;
-                                dx = gt ? dx - Lx : (lt ? dx + Lx : dx);
-                                code |= gt ? 2u : (lt ? 1u : 0u);
-                            }
-                            if (wrap[1]) {
-                                const bool gt = dy > hy, lt = dy < -hy;
-                                dy = gt ? dy - Ly : (lt ? dy + Ly : dy);
-                                code |= gt ? 8u : (lt ? 4u : 0u);
-                            }
-                            if (wrap[2]) {
-                                const bool gt = dz > hz, lt = dz < -hz;
-                                dz = gt ? dz - Lz : (lt ? dz + Lz : dz);
-                                code |= gt ? 32u : (lt ? 16u : 0u);
-                            }
-                        }
-                        const double r2 = (dx * dx + dy * dy) + dz * dz;
-                        // one ballot per comparison (each is a plain compare mask), ANDed as scalars
-                        const bool hit = (ck[c] >= 0) & (r2 < rl2) & (ck[c] != kself) & (!HALF | (cj[c] > i));
-                        uint64_t mask = valid[c] & __builtin_amdgcn_ballot_w64(r2 < rl2) &
-                                        __builtin_amdgcn_ballot_w64(ck[c] != kself);
-                        if (HALF) mask &= __builtin_amdgcn_ballot_w64(cj[c] > i);
-                        if (mask != 0) {
-                            const int32_t p = ni + (int32_t)lanes_below(mask);
-                            if (narrow) {
-                                const uint32_t off = ((uint32_t)p >> 3 << 9) | ((uint32_t)p & 7u);
-                                if (hit && p < M) base16[off] = (uint16_t)ck[c];
-                            } else {
-                                const uint32_t off = ((uint32_t)p >> 2 << 8) | ((uint32_t)p & 3u);
-                                const uint32_t word = WRAP ? (uint32_t)ck[c] | ((code << MD_IDX_BITS) & cmask) : (uint32_t)ck[c];
-                                if (hit && p < M) base[off] = word;
-                            }
-                            ni += (int32_t)__popcll(mask);
-                        }
-                    }
-                }
-                cnt = lane == l ? ni : cnt;
-            }
+            const int32_t at0 = 64 * half;
+            if (nch == 4)
+                test_tile<HALF, WRAP, NARROW, 4>(cc, cx, cy, cz, ck, cj, valid, at0, at_end, half, ax, ay, az, i0, vself, t == 0, cnt);
+            else if (nch == 3)
+                test_tile<HALF, WRAP, NARROW, 3>(cc, cx, cy, cz, ck, cj, valid, at0, at_end, half, ax, ay, az, i0, vself, t == 0, cnt);
+            else if (nch == 2)
+                test_tile<HALF, WRAP, NARROW, 2>(cc, cx, cy, cz, ck, cj, valid, at0, at_end, half, ax, ay, az, i0, vself, t == 0, cnt);
+            else
+                test_tile<HALF, WRAP, NARROW, 1>(cc, cx, cy, cz, ck, cj, valid, at0, at_end, half, ax, ay, az, i0, vself, t == 0, cnt);
             if (half == 0) cnt0 = cnt;
             else cnt1 = cnt;
         }
+        c0 += nch;
     }
     if (lane < na) {
         a.cnt[i0 + lane] = cnt0;
@@ -378,10 +471,14 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_build_list(ListArgs a)
             int32_t *runs = runs_lds + 64 * w;
             uint8_t *crun = crun_lds + CRUN * w;
             build_runs(st, g, lc, np, runs, crun);
-            if (wrap[0] || wrap[1] || wrap[2])
-                scan_cell<HALF, true>(a, st, g, e, na, lc, wrap, runs, crun, my_max, &bpairs);
-            else
-                scan_cell<HALF, false>(a, st, g, e, na, lc, wrap, runs, crun, my_max, &bpairs);
+            const bool any_wrap = wrap[0] || wrap[1] || wrap[2];
+            if (st.rec[BR_SHIFT] != 0) {
+                if (any_wrap) scan_cell<HALF, true, true>(a, st, g, e, na, lc, wrap, runs, crun, my_max, &bpairs);
+                else scan_cell<HALF, false, true>(a, st, g, e, na, lc, wrap, runs, crun, my_max, &bpairs);
+            } else {
+                if (any_wrap) scan_cell<HALF, true, false>(a, st, g, e, na, lc, wrap, runs, crun, my_max, &bpairs);
+                else scan_cell<HALF, false, false>(a, st, g, e, na, lc, wrap, runs, crun, my_max, &bpairs);
+            }
             t = take_cell(&next_cell);
         }
         // copy the freshly sorted state of the brick's atoms into the working buffers
