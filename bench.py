@@ -160,14 +160,16 @@ def run_md(B, torch, sysm, w, prec, kind, steps, warmup, thermo, pos0, vel0):
         B.md_build_neighbor_list(sysm.ctx, B.MD_LIST_FULL)
         B.md_compute_forces(sysm.ctx, sysm.dpot, prec, F, E0, None)
         ke0 = 0.5 * w.mass * float((sysm.vel * sysm.vel).sum().item())
+        x_start, v_start = sysm.pos.clone(), sysm.vel.clone()
         torch.cuda.synchronize()
-        B.md_profile(sysm.ctx, True)
+        # the timed run: events at the ends of the setup and of the step loop only
+        B.md_profile(sysm.ctx, True, launches=False)
         t0 = time.perf_counter()
         B.md_verlet_step(sysm.ctx, sysm.dpot, prec, kind, sysm.pos, sysm.vel, F, w.dt, w.mass, steps, hist,
                          nreb, hist_every=thermo)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        fms, fn, lms, ln = B.md_profile(sysm.ctx, False)
+        B.md_profile(sysm.ctx, False)
         det = B.md_profile_detail(sysm.ctx)
         code, flags, cap = B.md_get_status(sysm.ctx)
         if code != B.MD_ERR_CAPACITY:
@@ -175,6 +177,22 @@ def run_md(B, torch, sysm, w, prec, kind, steps, warmup, thermo, pos0, vel0):
         log(f"list rows overflowed, repeating with capacity {B.md_query(sysm.ctx, 2)}")
     if code != B.MD_OK:
         raise RuntimeError(f"run ended with status {code} (flags {flags})")
+    # the same run again with an event pair around every force and list launch
+    # (per-launch durations; the pairs themselves slow the loop a little)
+    x_end, v_end = sysm.pos.clone(), sysm.vel.clone()
+    sysm.pos.copy_(x_start)
+    sysm.vel.copy_(v_start)
+    hist2 = torch.zeros_like(hist)
+    B.md_profile(sysm.ctx, True)
+    B.md_verlet_step(sysm.ctx, sysm.dpot, prec, kind, sysm.pos, sysm.vel, F, w.dt, w.mass, steps, hist2,
+                     None, hist_every=thermo)
+    fms, fn, lms, ln = B.md_profile(sysm.ctx, False)
+    det_l = B.md_profile_detail(sysm.ctx)
+    code2 = B.md_get_status(sysm.ctx)[0]
+    if code2 != B.MD_OK:
+        raise RuntimeError(f"instrumented run ended with status {code2}")
+    sysm.pos.copy_(x_end)
+    sysm.vel.copy_(v_end)
     h = hist.cpu().numpy()
     e0 = float(E0.item()) + ke0
     etot = np.concatenate([[e0], h[:, 0] + h[:, 1]])
@@ -187,10 +205,11 @@ def run_md(B, torch, sysm, w, prec, kind, steps, warmup, thermo, pos0, vel0):
         "ms_per_step": round(1e3 * loop_s / steps, 5),
         "wall_atom_steps_per_s": round(n * steps / (t1 - t0), 1),
         "setup_ms": round(det["setup_ms"], 3),
-        "force_plain_us": round(1e3 * det["force_plain_ms"] / det["force_plain_n"], 2) if det["force_plain_n"] else None,
-        "force_plain_launches": det["force_plain_n"],
-        "force_energy_us": round(1e3 * det["force_energy_ms"] / det["force_energy_n"], 2) if det["force_energy_n"] else None,
-        "force_energy_launches": det["force_energy_n"],
+        "instrumented_ms_per_step": round(det_l["loop_ms"] / max(det_l["loop_steps"], 1), 5),
+        "force_plain_us": round(1e3 * det_l["force_plain_ms"] / det_l["force_plain_n"], 2) if det_l["force_plain_n"] else None,
+        "force_plain_launches": det_l["force_plain_n"],
+        "force_energy_us": round(1e3 * det_l["force_energy_ms"] / det_l["force_energy_n"], 2) if det_l["force_energy_n"] else None,
+        "force_energy_launches": det_l["force_energy_n"],
         "list_ms_total": round(lms, 3), "list_launches": ln,
         "rebuilds": int(nreb.item()),
         "energy_drift": float(np.max(np.abs(etot - etot[0])) / max(abs(etot[0]), 1e-300)),
@@ -474,7 +493,7 @@ def main():
         "config": {"workload": "lj_fcc_1048576", "atoms": w.n, "cells": "64^3 fcc", "density": 0.8442,
                    "rc": 2.5, "skin": 0.3, "T": 0.72, "dt": 0.005, "list": args.list, "thermo_every": thermo,
                    "parallelism": "single GPU"},
-        "timed_region": "md_verlet_step's step loop (HIP events on its stream); setup excluded, reported beside",
+        "timed_region": "md_verlet_step's step loop (one HIP event at each end, on its stream); setup excluded, reported beside; per-launch durations from a second run of the same steps with an event pair around every launch (instrumented_ms_per_step)",
         "energy_drift": r["energy_drift"],
         "rebuilds": r["rebuilds"],
         "mean_neighbors": r["mean_neighbors"],

@@ -318,7 +318,11 @@ int md_query(md_ctx *ctx, int32_t key, int64_t *value);
 /* Kernel timing with HIP events on the stream of the timed calls.
  * enable = 1: clear the counters and, from the next call on, record an event
  * pair around every force launch (LJ kernel, or EAM density + force pair, or
- * half-list kernel + integration) and every neighbour-list launch.
+ * half-list kernel + integration) and every neighbour-list launch, and one
+ * event at each end of md_verlet_step's setup and step loop.
+ * enable = 2: as 1, but only the setup and loop events (md_profile_detail's
+ * [0..2]); the loop then runs without the per-launch event pairs, which cost
+ * their stream a few microseconds per step.
  * enable = 0: stop, synchronise, and return [host] the summed durations and
  * launch counts (any pointer may be NULL).  List launches include those that
  * exit at once because no rebuild was due. */
@@ -327,6 +331,7 @@ int md_profile(md_ctx *ctx, int32_t enable, double *force_ms, int64_t *force_lau
 
 /* Timings of the md_verlet_step calls made while md_profile was enabled, taken
  * when md_profile(ctx, 0, ...) stopped it (HIP events on the calls' stream).
+ * Entries [3..7] are zero after md_profile(ctx, 2, ...).
  * out [host]: n_out (at most 8) doubles:
  *   [0] ms of the step loops (from the end of the setup to the last step's
  *       last launch: every rebuild test, list rebuild, force and integration

@@ -289,13 +289,14 @@ def md_query(ctx: Context, key: int) -> int:
     return int(v.value)
 
 
-def md_profile(ctx: Context, enable: bool):
+def md_profile(ctx: Context, enable: bool, launches: bool = True):
     """Start (enable=True) or stop event timing; on stop returns
-    (force_ms, force_launches, list_ms, list_launches)."""
+    (force_ms, force_launches, list_ms, list_launches).  launches=False times
+    only md_verlet_step's setup and step loop (no event pair per launch)."""
     fm, ln = C.c_double(), C.c_double()
     fn, lc = C.c_int64(), C.c_int64()
-    _check(ctx.h, load().md_profile(ctx.h, int(bool(enable)), C.byref(fm), C.byref(fn), C.byref(ln),
-                                    C.byref(lc)))
+    mode = 0 if not enable else (1 if launches else 2)
+    _check(ctx.h, load().md_profile(ctx.h, mode, C.byref(fm), C.byref(fn), C.byref(ln), C.byref(lc)))
     if enable:
         return None
     return float(fm.value), int(fn.value), float(ln.value), int(lc.value)

@@ -181,6 +181,7 @@ struct md_ctx {
 
     // event timing (md_profile)
     bool prof = false;
+    bool prof_launches = false;   // event pairs around every force and list launch too
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_force, ev_list;
@@ -774,13 +775,13 @@ template <typename F>
 void timed(md_ctx *c, hipStream_t s, std::vector<std::pair<hipEvent_t, hipEvent_t>> &log, F launch)
 {
     hipEvent_t a = nullptr, b = nullptr;
-    if (c->prof) {
+    if (c->prof && c->prof_launches) {
         a = c->next_event();
         b = c->next_event();
         if (a && b) (void)hipEventRecord(a, s);
     }
     launch();
-    if (c->prof && a && b) {
+    if (c->prof && c->prof_launches && a && b) {
         (void)hipEventRecord(b, s);
         log.emplace_back(a, b);
         if (&log == &c->ev_force) c->ev_force_kind.push_back(c->force_kind);
@@ -1531,6 +1532,7 @@ int md_profile(md_ctx *c, int32_t enable, double *force_ms, int64_t *force_n, do
         c->prof_steps = 0;
         c->ev_used = 0;
         c->prof = true;
+        c->prof_launches = enable != 2;
         return MD_OK;
     }
     c->prof = false;

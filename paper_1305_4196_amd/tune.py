@@ -141,7 +141,7 @@ def _time_config(system, shape, threads, precision, kind, reps, objective="md", 
                 B.md_build_cells(system.ctx, system.pos, system.boxes, system.pot.rc, system.skin)
                 B.md_verlet_step(system.ctx, system.dpot, precision, kind, system.pos, system.vel, F,
                                  dt, mass, 2, None, None)
-                B.md_profile(system.ctx, True)
+                B.md_profile(system.ctx, True, launches=False)
                 B.md_verlet_step(system.ctx, system.dpot, precision, kind, system.pos, system.vel, F,
                                  dt, mass, steps, None, None)
                 B.md_profile(system.ctx, False)

@@ -43,3 +43,19 @@ def test_step_loop_timing_counts(every):
     B.md_verlet_step(s.ctx, s.dpot, B.MD_MIXED, B.MD_LIST_FULL, s.pos, s.vel, F, w.dt, w.mass, 5, None, None)
     B.md_profile(s.ctx, False)
     assert B.md_profile_detail(s.ctx)["loop_steps"] == 5
+
+
+@pytest.mark.gpu
+def test_loop_only_timing_records_no_launch_pairs():
+    w = W.lj_fcc(8)
+    s = MDSystem.from_workload(w)
+    F = torch.empty_like(s.pos)
+    B.md_build_cells(s.ctx, s.pos, s.boxes, w.pot.rc, w.skin)
+    B.md_profile(s.ctx, True, launches=False)
+    B.md_verlet_step(s.ctx, s.dpot, B.MD_MIXED, B.MD_LIST_FULL, s.pos, s.vel, F, w.dt, w.mass, 12, None, None)
+    fms, fn, lms, ln = B.md_profile(s.ctx, False)
+    d = B.md_profile_detail(s.ctx)
+    assert B.md_get_status(s.ctx)[0] == B.MD_OK
+    assert d["loop_steps"] == 12 and d["loop_ms"] > 0 and d["setup_ms"] > 0
+    assert fn == 0 and ln == 0 and fms == 0.0 and lms == 0.0
+    assert d["force_plain_n"] == 0 and d["force_energy_n"] == 0 and d["force_setup_ms"] == 0.0
