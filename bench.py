@@ -475,10 +475,12 @@ def main():
     tf = os.path.join(ROOT, "profiles", "traffic_lj_force.json")
     if os.path.exists(tf):
         with open(tf) as f:
-            t = json.load(f)
-        if (t.get("source_hash") == source_hash(FORCE_SOURCES) and t.get("path") == main_name
-                and t.get("brick") == r["brick"] and t.get("threads") == r["threads"]):
-            traffic = t.get("hbm_bytes_per_launch")
+            recs = json.load(f).get("records", [])
+        # counters taken on the same kernel sources, path and launch shape only
+        for t in recs:
+            if (t.get("source_hash") == source_hash(FORCE_SOURCES) and t.get("path") == main_name
+                    and t.get("brick") == r["brick"] and t.get("threads") == r["threads"]):
+                traffic = t.get("hbm_bytes_per_launch")
     roof = roofline_lj(w, res, main_name, traffic)
     other_paths = {p: res[p] for p in paths if p != main_name}
     line = {

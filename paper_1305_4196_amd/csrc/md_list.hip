@@ -31,18 +31,22 @@
 namespace {
 
 // One wavefront, one own cell e of the brick: the cell's stencil rows are
-// concatenated into one candidate sequence, loaded into registers in tiles of
-// at most TILE chunks of 64 (one candidate per lane and chunk; the chunks are
-// spread evenly over the tiles), and every atom of the cell (a uniform value
-// per iteration) is tested against the tile.  The cell's atoms (in groups of up
-// to 128) are held two per lane and broadcast with readlane.  An atom's tests
-// against all chunks of the tile come before its stores, in one block without
-// branches.  Hits are compacted with a ballot, so atom a's entries keep the
-// candidate order; the running list length is a scalar while the atom is
-// tested and is kept in lane a between tiles.  The atom itself is excluded by
-// its position in the sequence (a scalar test), and the row is written through
-// a buffer descriptor whose range ends at the capacity, so the hardware's range
-// check drops entries beyond it (the overflow is still counted and flagged).
+// concatenated into one candidate sequence, the cell's own atoms first, and
+// loaded into registers in tiles of at most TILE chunks of 64 (one candidate
+// per lane and chunk; the chunks are spread evenly over the tiles).  Every atom
+// of the cell (a uniform value per iteration: read from LDS by all lanes at
+// once, the next atom's issued ahead; up to 128 atoms per pass) is tested
+// against the tile: all of its chunk tests in one block without branches, then
+// its stores.  Hits are compacted with a ballot and mbcnt, so atom a's entries
+// keep the candidate order; the running list lengths live in LDS, one word per
+// atom of the pass.  The atom itself is taken out of the one chunk of the
+// own-cell tiles that holds it (a scalar mask).  Every lane stores: the row is
+// addressed through a buffer descriptor whose record count ends at the
+// capacity, a lane without a hit stores to an index past it, and the
+// hardware's range check drops both that store and entries beyond the
+// capacity (the overflow is still counted and flagged).  Most of the loop is
+// then split about evenly between vector and scalar instructions, which share
+// a CU's issue slots.
 constexpr int TILE = 4;
 // candidates per cell whose run starts are flagged in LDS (more: binary search)
 constexpr int CRUN = 768;
@@ -57,19 +61,23 @@ __device__ __forceinline__ double readlane_f64(double v, int l)
 
 // Runs of the stencil rows of own cell lc, built by the wavefront's lanes in
 // parallel (lane t: layer sz = t / (2 np_y), row sy = (t / 2) % np_y, part t & 1,
-// the order of a plain loop over sz, sy, part) and stored in LDS:
+// the order of a plain loop over sz, sy, part) and stored in LDS, with the own
+// cell's atoms [ko, ko + na) taken out of their row and put first (so an atom's
+// own candidate sits at its index in the cell):
 // runs[0..nr) candidate index minus position (the cell's v-th candidate, v in
 // run r, is v + runs[r]), runs[32..32+nr] prefix of the run lengths,
 // runs[31] = nr.  Along an axis the stencil's halo coordinate is lc + s
 // (s = 0..np-1), reduced by n when the halo covers the axis (lc + s < 2 n).
-// With at most CRUN candidates, crun[v] = 1 exactly where a run starts.
+// With at most CRUN candidates, bit v of the bitmap crun is set exactly where a
+// run starts.
 __device__ __forceinline__ void build_runs(const Stage &st, const BrickGeom &g, const int32_t lc[3],
-                                           const int32_t np[3], int32_t *runs, uint8_t *crun)
+                                           const int32_t np[3], int32_t ko, int32_t na, int32_t *runs,
+                                           uint32_t *crun)
 {
     const int lane = threadIdx.x & 63;
     const int32_t *soff = st.rec + BR_HDR;
     const int32_t nt = 2 * np[1] * np[2];
-    int32_t kb = 0, len = 0;
+    int32_t kb = 0, ke = 0;
     if (lane < nt) {
         const int32_t part = lane & 1, sy = (lane >> 1) % np[1], sz = (lane >> 1) / np[1];
         int32_t hy = lc[1] + sy, hz = lc[2] + sz;
@@ -80,33 +88,50 @@ __device__ __forceinline__ void build_runs(const Stage &st, const BrickGeom &g, 
         const int32_t x1 = xa + np[0] < g.hn[0] ? xa + np[0] : g.hn[0];
         const int32_t x2 = xa + np[0] - x1;
         kb = part == 0 ? soff[rowh + xa] : soff[rowh];
-        const int32_t ke = part == 0 ? soff[rowh + x1] : soff[rowh + x2];
-        len = ke > kb ? ke - kb : 0;
+        ke = part == 0 ? soff[rowh + x1] : soff[rowh + x2];
+        ke = ke > kb ? ke : kb;
     }
-    // exclusive prefix of the lengths over the lanes, then the non-empty runs compacted
-    int32_t inc = len;
+    // the own cell is a distinct cell of its stencil: exactly one lane's range
+    // holds it whole; that range is cut into the parts before and after it
+    const bool own = lane < nt && ko >= kb && ko + na <= ke;
+    const int32_t l1 = own ? ko - kb : ke - kb;          // [kb, kb + l1)
+    const int32_t kb2 = ko + na;
+    const int32_t l2 = own ? ke - kb2 : 0;               // [kb2, kb2 + l2)
+    const int32_t pc = (l1 > 0 ? 1 : 0) + (l2 > 0 ? 1 : 0);
+    // exclusive prefix over the lanes of the lengths (low 24 bits) and piece counts
+    const int32_t packed = (l1 + l2) | (pc << 24);
+    int32_t inc = packed;
     for (int o = 1; o < 64; o <<= 1) {
         const int32_t y = __shfl_up(inc, o, 64);
         if (lane >= o) inc += y;
     }
-    const uint64_t nonempty = __builtin_amdgcn_ballot_w64(len > 0);
-    const int32_t pex = inc - len;
-    if (len > 0) {
-        const int32_t r = (int32_t)lanes_below(nonempty);
-        runs[r] = kb - pex;
-        runs[32 + r] = pex;
+    const int32_t ex = inc - packed;
+    const int32_t pex = na + (ex & 0xffffff);            // after the own cell
+    const int32_t rb = 1 + (ex >> 24);
+    if (l1 > 0) {
+        runs[rb] = kb - pex;
+        runs[32 + rb] = pex;
     }
-    const int32_t nr = (int32_t)__popcll(nonempty);
-    const int32_t total = __shfl(inc, 63, 64);     // with every lane active
+    if (l2 > 0) {
+        const int32_t r = rb + (l1 > 0 ? 1 : 0);
+        runs[r] = kb2 - (pex + l1);
+        runs[32 + r] = pex + l1;
+    }
+    const int32_t last = __shfl(inc, 63, 64);            // with every lane active
+    const int32_t nr = 1 + (last >> 24);
+    const int32_t total = na + (last & 0xffffff);
     if (lane == 0) {
+        runs[0] = ko;
+        runs[32] = 0;
         runs[32 + nr] = total;
         runs[31] = nr;
     }
     if (total <= CRUN) {
-        uint32_t *w32 = reinterpret_cast<uint32_t *>(crun);
-        for (int32_t q = lane; q < (total + 3) >> 2; q += 64) w32[q] = 0u;
+        for (int32_t q = lane; q < (total + 31) >> 5; q += 64) crun[q] = 0u;
         wave_sync();
-        if (len > 0) crun[pex] = 1;
+        if (lane == 0) atomicOr(&crun[0], 1u);
+        if (l1 > 0) atomicOr(&crun[pex >> 5], 1u << (pex & 31));
+        if (l2 > 0) atomicOr(&crun[(pex + l1) >> 5], 1u << ((pex + l1) & 31));
     }
     wave_sync();
 }
@@ -145,34 +170,59 @@ __device__ __forceinline__ i32x4 buffer_desc(uintptr_t base, uint32_t stride, ui
 struct CellCtx {
     double L[3], hL[3];
     double rl2;
-    uintptr_t nbr_addr;          // list rows (interleaved by 64 atoms)
-    int64_t group_bytes;         // bytes of 64 rows
-    uint32_t row_entries;        // entries of a row below the capacity M
+    i32x4 rows;                  // the rows from the cell's first atom's group of 64 on
+    int32_t group_bytes;         // bytes of 64 rows
+    int32_t row_entries;         // entries of a row below the capacity M (records of `rows`)
     bool wrap[3];
 };
 
 // The atoms at..at_end of a group (held in ax/ay/az, atom at in lane at - 64 half)
 // against the NCH chunks of candidates in registers.  All NCH tests of an atom
 // come first, so their binary64 chains overlap; then the hits of each chunk are
-// stored in candidate order behind the atom's running length ni.  vself is the
-// position, relative to the tile's first candidate, of the group's first atom.
-template <bool HALF, bool WRAP, bool NARROW, int NCH>
+// stored in candidate order behind the atom's running length ni, by every lane:
+// a lane without a hit stores to an index past the row, which the buffer's
+// range check drops (no branch on the hit mask).  SELF: the tile holds
+// candidates at sequence positions vself + at, the atoms themselves (the own
+// cell comes first in the sequence), which are taken out of the masks.  i0:
+// sorted index of the cell's first atom, g0: the group's first atom in the cell.
+template <bool HALF, bool WRAP, bool NARROW, int NCH, bool SELF, bool ALL>
 __device__ __forceinline__ void test_tile(const CellCtx &cc, const double *cx, const double *cy, const double *cz,
                                           const int32_t *ck, const int64_t *cj, const uint64_t *valid,
                                           int32_t at_begin, int32_t at_end, int half, double ax, double ay,
-                                          double az, int64_t i0, int32_t vself, bool first, int32_t &cnt)
+                                          double az, const double *own, int64_t i0, int32_t g0, int32_t vself,
+                                          int32_t *cnt)
 {
     const int lane = threadIdx.x & 63;
+    // ALL: the group's atoms are staged, own[3 at ..] (broadcast LDS reads,
+    // the next atom's issued ahead); else they come from lanes of ax/ay/az
+    double xn = 0.0, yn = 0.0, zn = 0.0;
+    if (ALL && at_begin < at_end) {
+        xn = own[3 * at_begin];
+        yn = own[3 * at_begin + 1];
+        zn = own[3 * at_begin + 2];
+    }
     for (int32_t at = at_begin; at < at_end; at++) {
-        const int64_t i = i0 + at;
-        const int l = at - 64 * half;
-        const double xi = readlane_f64(ax, l);
-        const double yi = readlane_f64(ay, l);
-        const double zi = readlane_f64(az, l);
-        int32_t ni = first ? 0 : __builtin_amdgcn_readlane(cnt, l);
-        // the atom's row: 16 bytes per atom across a group of 64 rows in either layout
-        const i32x4 rs = buffer_desc(cc.nbr_addr + (uintptr_t)((i >> 6) * cc.group_bytes + ((i & 63) << 4)),
-                                     NARROW ? 2u : 4u, cc.row_entries);
+        const int64_t i = i0 + g0 + at;
+        double xi, yi, zi;
+        if (ALL) {
+            xi = xn;
+            yi = yn;
+            zi = zn;
+            const int32_t an = at + 1 < at_end ? at + 1 : at;
+            xn = own[3 * an];
+            yn = own[3 * an + 1];
+            zn = own[3 * an + 2];
+        } else {
+            const int l = at - 64 * half;
+            xi = readlane_f64(ax, l);
+            yi = readlane_f64(ay, l);
+            zi = readlane_f64(az, l);
+        }
+        // the atom's running list length (per wavefront in LDS)
+        int32_t ni = cnt[at];
+        // the atom's row: 16 bytes per atom across a group of 64 rows, in either
+        // layout, from the group of the cell's first atom on
+        const int32_t row_off = (int32_t)((i >> 6) - (i0 >> 6)) * cc.group_bytes + (int32_t)((i & 63) << 4);
         const int32_t vs = vself + at;
         uint64_t m[NCH];
         uint32_t code[NCH];
@@ -199,35 +249,35 @@ __device__ __forceinline__ void test_tile(const CellCtx &cc, const double *cx, c
             }
             const double r2 = (dx * dx + dy * dy) + dz * dz;
             m[c] = valid[c] & __builtin_amdgcn_ballot_w64(r2 < cc.rl2);
-            if ((vs >> 6) == c) m[c] &= ~(1ull << (vs & 63));
+            if (SELF && (vs >> 6) == c) m[c] &= ~(1ull << (vs & 63));
             if (HALF) m[c] &= __builtin_amdgcn_ballot_w64(cj[c] > i);
         }
         _Pragma("unroll")
         for (int c = 0; c < NCH; c++) {
-            if (__builtin_amdgcn_inverse_ballot_w64(m[c])) {
-                const uint32_t p = __builtin_amdgcn_mbcnt_hi((uint32_t)(m[c] >> 32),
-                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m[c], (uint32_t)ni));
-                if (NARROW) {
-                    sbuf_store_i16((int16_t)ck[c], rs, (int32_t)entry_index<true>(p), 0, 0, 0);
-                } else {
-                    const uint32_t word = WRAP ? (uint32_t)ck[c] | (code[c] << MD_IDX_BITS) : (uint32_t)ck[c];
-                    sbuf_store_i32((int32_t)word, rs, (int32_t)entry_index<false>(p), 0, 0, 0);
-                }
+            const uint32_t p = __builtin_amdgcn_mbcnt_hi((uint32_t)(m[c] >> 32),
+                               __builtin_amdgcn_mbcnt_lo((uint32_t)m[c], (uint32_t)ni));
+            const bool hit = __builtin_amdgcn_inverse_ballot_w64(m[c]);
+            const int32_t idx = hit ? (int32_t)entry_index<NARROW>(p) : cc.row_entries;
+            if (NARROW) {
+                sbuf_store_i16((int16_t)ck[c], cc.rows, idx, 0, row_off, 0);
+            } else {
+                const uint32_t word = WRAP ? (uint32_t)ck[c] | (code[c] << MD_IDX_BITS) : (uint32_t)ck[c];
+                sbuf_store_i32((int32_t)word, cc.rows, idx, 0, row_off, 0);
             }
             ni += (int32_t)__popcll(m[c]);
         }
-        cnt = lane == l ? ni : cnt;
+        if (lane == 0) cnt[at] = ni;
     }
 }
 
 // WRAP: some axis of the cell needs the minimum-image test; otherwise the
 // test and the image code are compiled out.  NARROW: the brick is staged
 // through its cell images and stores bare 16-bit candidate indices.
-template <bool HALF, bool WRAP, bool NARROW>
+template <bool HALF, bool WRAP, bool NARROW, bool ALL>
 __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, const BrickGeom &g,
                                           int32_t e, int32_t na_all, const int32_t lc[3],
-                                          const bool wrap[3], const int32_t *runs, const uint8_t *crun,
-                                          int32_t &my_max, int32_t *bpairs)
+                                          const bool wrap[3], const int32_t *runs, const uint32_t *crun,
+                                          int32_t *cnt_w, int32_t &my_max, int32_t *bpairs)
 {
     const int lane = threadIdx.x & 63;
     const int32_t *soff = st.rec + br_soff(a.bd);
@@ -246,25 +296,16 @@ __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, co
         cc.wrap[d] = wrap[d];
     }
     cc.rl2 = a.rl2;
-    // entries of an atom's row below entry M: the row is addressed as a buffer
-    // of that many entry-sized records, so stores beyond M are dropped by the
-    // buffer's range check, which is the capacity test
-    cc.row_entries = entry_index<NARROW>((uint32_t)M);
-    cc.group_bytes = (int64_t)(M >> 2) << 10;
-    cc.nbr_addr = reinterpret_cast<uintptr_t>(a.nbr);
-    // position of the cell's first atom in the candidate sequence: the cell is
-    // a distinct cell of its own stencil, so exactly one run holds k_own
-    int32_t v_own;
-    {
-        int32_t v = -1;
-        if (lane < nr) {
-            const int32_t vb = runs[32 + lane], ve = runs[32 + lane + 1], off = runs[lane];
-            if (k_own >= vb + off && k_own < ve + off) v = k_own - off;
-        }
-        const uint64_t m = __builtin_amdgcn_ballot_w64(v >= 0);
-        v_own = __builtin_amdgcn_readlane(v, m != 0 ? (int)__builtin_ctzll(m) : 0);
-    }
+    // entries of an atom's row below entry M: a row is addressed as a buffer of
+    // that many entry-sized records (the atom's row offset as the buffer's
+    // scalar offset), so stores beyond M are dropped by the buffer's range
+    // check, which is the capacity test
+    cc.row_entries = (int32_t)entry_index<NARROW>((uint32_t)M);
+    cc.group_bytes = (M >> 2) << 10;
+    cc.rows = buffer_desc(reinterpret_cast<uintptr_t>(a.nbr) + (uintptr_t)((i0_all >> 6) * (int64_t)cc.group_bytes),
+                          NARROW ? 2u : 4u, (uint32_t)cc.row_entries);
     // chunks of 64 candidates, in tiles of at most TILE chunks of balanced sizes
+    const bool all_staged = ALL;                 // every candidate of the brick is in LDS
     const int32_t nchunks = (ncand + 63) >> 6;
     const int32_t ntiles = (nchunks + TILE - 1) / TILE;
     int32_t tot = 0;
@@ -273,12 +314,15 @@ __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, co
     const int32_t na = na_all - g0 < 128 ? na_all - g0 : 128;
     const int64_t i0 = i0_all + g0;
     const int32_t k_grp = k_own + g0;
-    int32_t cnt0 = 0, cnt1 = 0;                // list lengths of atoms lane and 64 + lane
+    // running list lengths of the group's atoms
+    cnt_w[lane] = 0;
+    cnt_w[64 + lane] = 0;
+    wave_sync();
     double ax0 = 0.0, ay0 = 0.0, az0 = 0.0, ax1 = 0.0, ay1 = 0.0, az1 = 0.0;
-    {
+    if (!ALL) {
         const int32_t k0 = k_grp + lane, k1 = k_grp + 64 + lane;
         if (lane < na) {
-            if (k0 < st.cap) {
+            if (ALL || k0 < st.cap) {
                 ax0 = st.xyz[3 * k0];
                 ay0 = st.xyz[3 * k0 + 1];
                 az0 = st.xyz[3 * k0 + 2];
@@ -290,7 +334,7 @@ __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, co
             }
         }
         if (lane + 64 < na) {
-            if (k1 < st.cap) {
+            if (ALL || k1 < st.cap) {
                 ax1 = st.xyz[3 * k1];
                 ay1 = st.xyz[3 * k1 + 1];
                 az1 = st.xyz[3 * k1 + 2];
@@ -318,7 +362,7 @@ __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, co
                 // run of candidate v: the runs started before this chunk plus
                 // the starts flagged up to v within it
                 if (c < nch) {
-                    const bool st0 = v < ncand && crun[v] != 0;
+                    const bool st0 = v < ncand && ((crun[v >> 5] >> (v & 31)) & 1u) != 0;
                     const uint64_t sm = __builtin_amdgcn_ballot_w64(st0);
                     const int32_t r = rbase + (int32_t)lanes_below(sm) + (st0 ? 1 : 0) - 1;
                     rbase += (int32_t)__popcll(sm);
@@ -334,7 +378,8 @@ __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, co
             }
             ck[c] = (c < nch && v < ncand) ? k : -1;
             cj[c] = 0;
-            if (k < st.cap) {
+            // (a wholly staged halo reads LDS only: no flat loads merging the two)
+            if (all_staged || k < st.cap) {
                 const double *q = st.xyz + 3 * k;
                 cx[c] = q[0];
                 cy[c] = q[1];
@@ -352,26 +397,34 @@ __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, co
         uint64_t valid[TILE];
         _Pragma("unroll")
         for (int c = 0; c < TILE; c++) valid[c] = __builtin_amdgcn_ballot_w64(ck[c] >= 0);
-        const int32_t vself = v_own + g0 - t0;
+        // the cell's atoms come first in the sequence: atom g0 + at is candidate g0 + at
+        const int32_t vself = g0 - t0;
+        const bool self = t0 < na_all;
         // atoms 0..63 of the group from the first register set, 64..127 from the second
+        const double *own = st.xyz + 3 * (int64_t)k_grp;
         for (int half = 0; half < 2; half++) {
             const int32_t at_end = half == 0 ? (na < 64 ? na : 64) : na;
             const double ax = half == 0 ? ax0 : ax1, ay = half == 0 ? ay0 : ay1, az = half == 0 ? az0 : az1;
-            int32_t cnt = half == 0 ? cnt0 : cnt1;
             const int32_t at0 = 64 * half;
-            if (nch == 4)
-                test_tile<HALF, WRAP, NARROW, 4>(cc, cx, cy, cz, ck, cj, valid, at0, at_end, half, ax, ay, az, i0, vself, t == 0, cnt);
-            else if (nch == 3)
-                test_tile<HALF, WRAP, NARROW, 3>(cc, cx, cy, cz, ck, cj, valid, at0, at_end, half, ax, ay, az, i0, vself, t == 0, cnt);
-            else if (nch == 2)
-                test_tile<HALF, WRAP, NARROW, 2>(cc, cx, cy, cz, ck, cj, valid, at0, at_end, half, ax, ay, az, i0, vself, t == 0, cnt);
-            else
-                test_tile<HALF, WRAP, NARROW, 1>(cc, cx, cy, cz, ck, cj, valid, at0, at_end, half, ax, ay, az, i0, vself, t == 0, cnt);
-            if (half == 0) cnt0 = cnt;
-            else cnt1 = cnt;
+#define MD_TILE(NCH, SELF) test_tile<HALF, WRAP, NARROW, NCH, SELF, ALL>(cc, cx, cy, cz, ck, cj, valid, at0, at_end, \
+                                                                         half, ax, ay, az, own, i0_all, g0, vself, cnt_w)
+            if (self) {
+                if (nch == 4) MD_TILE(4, true);
+                else if (nch == 3) MD_TILE(3, true);
+                else if (nch == 2) MD_TILE(2, true);
+                else MD_TILE(1, true);
+            } else {
+                if (nch == 4) MD_TILE(4, false);
+                else if (nch == 3) MD_TILE(3, false);
+                else if (nch == 2) MD_TILE(2, false);
+                else MD_TILE(1, false);
+            }
+#undef MD_TILE
         }
         c0 += nch;
     }
+    wave_sync();
+    const int32_t cnt0 = cnt_w[lane], cnt1 = cnt_w[64 + lane];
     if (lane < na) {
         a.cnt[i0 + lane] = cnt0;
         my_max = cnt0 > my_max ? cnt0 : my_max;
@@ -402,8 +455,9 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_build_list(ListArgs a)
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ int32_t smax[TASK_MAX_THREADS / 64], stot[TASK_MAX_THREADS / 64], sbr[TASK_MAX_THREADS / 64];
     __shared__ int32_t runs_lds[64 * (TASK_MAX_THREADS / 64)];
-    __shared__ uint8_t crun_lds[CRUN * (TASK_MAX_THREADS / 64)];
+    __shared__ uint32_t crun_lds[CRUN / 32 * (TASK_MAX_THREADS / 64)];
     __shared__ int32_t order[64];
+    __shared__ int32_t cnt_lds[128 * (TASK_MAX_THREADS / 64)];
     const Stage st = stage_slice(lds_raw, a.cap, 0, HALF);
     const int lane = threadIdx.x & 63;
     // the wavefront index as a scalar, so that everything derived per cell is uniform
@@ -469,15 +523,20 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_build_list(ListArgs a)
                 wrap[d] = !(g.nc[d] >= 5 && c >= 1 && c <= g.nc[d] - 2);
             }
             int32_t *runs = runs_lds + 64 * w;
-            uint8_t *crun = crun_lds + CRUN * w;
-            build_runs(st, g, lc, np, runs, crun);
+            uint32_t *crun = crun_lds + CRUN / 32 * w;
+            const int32_t hown = (lc[0] + 1) % g.nc[0] + g.hn[0] * ((lc[1] + 1) % g.nc[1] + g.hn[1] * ((lc[2] + 1) % g.nc[2]));
+            build_runs(st, g, lc, np, st.rec[BR_HDR + hown], na, runs, crun);
             const bool any_wrap = wrap[0] || wrap[1] || wrap[2];
+            // (bricks staged through their cell images have their whole halo in LDS)
             if (st.rec[BR_SHIFT] != 0) {
-                if (any_wrap) scan_cell<HALF, true, true>(a, st, g, e, na, lc, wrap, runs, crun, my_max, &bpairs);
-                else scan_cell<HALF, false, true>(a, st, g, e, na, lc, wrap, runs, crun, my_max, &bpairs);
+                if (any_wrap) scan_cell<HALF, true, true, true>(a, st, g, e, na, lc, wrap, runs, crun, cnt_lds + 128 * w, my_max, &bpairs);
+                else scan_cell<HALF, false, true, true>(a, st, g, e, na, lc, wrap, runs, crun, cnt_lds + 128 * w, my_max, &bpairs);
+            } else if (st.rec[BR_TOTAL] <= st.cap) {
+                if (any_wrap) scan_cell<HALF, true, false, true>(a, st, g, e, na, lc, wrap, runs, crun, cnt_lds + 128 * w, my_max, &bpairs);
+                else scan_cell<HALF, false, false, true>(a, st, g, e, na, lc, wrap, runs, crun, cnt_lds + 128 * w, my_max, &bpairs);
             } else {
-                if (any_wrap) scan_cell<HALF, true, false>(a, st, g, e, na, lc, wrap, runs, crun, my_max, &bpairs);
-                else scan_cell<HALF, false, false>(a, st, g, e, na, lc, wrap, runs, crun, my_max, &bpairs);
+                if (any_wrap) scan_cell<HALF, true, false, false>(a, st, g, e, na, lc, wrap, runs, crun, cnt_lds + 128 * w, my_max, &bpairs);
+                else scan_cell<HALF, false, false, false>(a, st, g, e, na, lc, wrap, runs, crun, cnt_lds + 128 * w, my_max, &bpairs);
             }
             t = take_cell(&next_cell);
         }
