@@ -47,7 +47,7 @@ namespace {
 // capacity (the overflow is still counted and flagged).  Most of the loop is
 // then split about evenly between vector and scalar instructions, which share
 // a CU's issue slots.
-constexpr int TILE = 4;
+constexpr int TILE = 5;
 // candidates per cell whose run starts are flagged in LDS (more: binary search)
 constexpr int CRUN = 768;
 
@@ -409,12 +409,14 @@ __device__ __forceinline__ void scan_cell(const ListArgs &a, const Stage &st, co
 #define MD_TILE(NCH, SELF) test_tile<HALF, WRAP, NARROW, NCH, SELF, ALL>(cc, cx, cy, cz, ck, cj, valid, at0, at_end, \
                                                                          half, ax, ay, az, own, i0_all, g0, vself, cnt_w)
             if (self) {
-                if (nch == 4) MD_TILE(4, true);
+                if (nch == 5) MD_TILE(5, true);
+                else if (nch == 4) MD_TILE(4, true);
                 else if (nch == 3) MD_TILE(3, true);
                 else if (nch == 2) MD_TILE(2, true);
                 else MD_TILE(1, true);
             } else {
-                if (nch == 4) MD_TILE(4, false);
+                if (nch == 5) MD_TILE(5, false);
+                else if (nch == 4) MD_TILE(4, false);
                 else if (nch == 3) MD_TILE(3, false);
                 else if (nch == 2) MD_TILE(2, false);
                 else MD_TILE(1, false);
