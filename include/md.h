@@ -125,8 +125,12 @@ void md_destroy(md_ctx *ctx);
  * n_c = floor(L_d / (rc + skin)) cells per dimension (width >= rc + skin),
  * cell index x fastest, and the context's internal copy of the atoms is
  * sorted by (cell, user index).  The cell grid is re-planned only when a box,
- * rc or skin changes.  Errors: MD_ERR_ARG (rc <= 0, skin < 0, non-finite or
- * non-positive L), MD_ERR_BOX (L_d < 2 (rc + skin)), MD_ERR_HIP. */
+ * rc or skin changes.  A non-finite position (here or at a rebuild inside
+ * md_verlet_step) raises the device's non-finite flag (md_get_status) and the
+ * atom is placed in cell i mod (its replica's cell count), where it has no
+ * partners; results involving it are invalid.  Errors: MD_ERR_ARG (rc <= 0,
+ * skin < 0, non-finite or non-positive L), MD_ERR_BOX (L_d < 2 (rc + skin)),
+ * MD_ERR_HIP. */
 int md_build_cells(md_ctx *ctx, const double *pos, const double *boxes_host, double rc,
                    double skin, void *stream);
 
@@ -217,7 +221,7 @@ int md_force_vjp(md_ctx *ctx, const md_potential *pot, int32_t precision, const 
                  double *g_params, void *stream);
 
 /* Device status (synchronises the context's last stream).  device_flags
- * [host]: bit 0 list overflow, bit 1 non-finite force, bit 2 a dependent-
+ * [host]: bit 0 list overflow, bit 1 non-finite force or position, bit 2 a dependent-
  * schedule wait past its limit; cleared after reading.
  * required_capacity [host]: per-atom list capacity now allocated or required.
  * Returns MD_ERR_CAPACITY / MD_ERR_NONFINITE / MD_ERR_TIMEOUT if the flag is

@@ -322,7 +322,7 @@ void sort_into_tmp(md_ctx *c, const int32_t *pred, bool with_vel, hipStream_t s)
 {
     const int ga = c->grid_atoms(256);
     launch_bin(s, ga, pred, c->n, c->R, c->reps, c->rep_of, c->pos[c->cur], c->cell_of, c->slot,
-               c->count);
+               c->count, &c->ctl->err);
     launch_scan(s, pred, c->C, c->count, c->start, c->ctl);
     launch_scatter(s, ga, pred, c->n, c->cell_of, c->slot, c->start, c->perm);
     launch_sort_cells(s, c->grid_cells(4, 8), pred, c->C, c->start, c->perm, c->id, c->pos[c->cur],

@@ -47,10 +47,16 @@ __global__ void k_load_user(int64_t n, const double *__restrict__ pos_user,
 // Atoms arrive in the previous cell order, so neighbouring lanes usually fall
 // into the same cell: each run of equal cells among consecutive lanes of a
 // wavefront takes its slots with one atomic add by the run's first lane.
+//
+// A non-finite position (a run that blew up, or bad input) raises
+// MD_FLAG_NONFINITE and puts the atom in cell i mod (its replica's cells): such
+// atoms stay spread over the cells instead of all falling into cell 0, where
+// the list build would test each of them against all the others; their tests
+// fail (NaN compares false), so they get no partners.
 __global__ void k_bin(const int32_t *__restrict__ pred, int64_t n, const RepDesc *__restrict__ reps,
                       const int32_t *__restrict__ rep_of, double4 *__restrict__ pos,
                       int32_t *__restrict__ cell_of, int32_t *__restrict__ slot,
-                      int32_t *__restrict__ count)
+                      int32_t *__restrict__ count, int32_t *__restrict__ err)
 {
     if (*pred == 0) return;
     const int lane = threadIdx.x & 63;
@@ -66,10 +72,15 @@ __global__ void k_bin(const int32_t *__restrict__ pred, int64_t n, const RepDesc
             p.y = wrap1(p.y, r.L[1]);
             p.z = wrap1(p.z, r.L[2]);
             pos[i] = p;
-            const int32_t cx = cell_coord(p.x, r.nc[0], r.L[0]);
-            const int32_t cy = cell_coord(p.y, r.nc[1], r.L[1]);
-            const int32_t cz = cell_coord(p.z, r.nc[2], r.L[2]);
-            c = (int32_t)(r.cell_off + cx + (int64_t)r.nc[0] * (cy + (int64_t)r.nc[1] * cz));
+            if (isfinite(p.x) && isfinite(p.y) && isfinite(p.z)) {
+                const int32_t cx = cell_coord(p.x, r.nc[0], r.L[0]);
+                const int32_t cy = cell_coord(p.y, r.nc[1], r.L[1]);
+                const int32_t cz = cell_coord(p.z, r.nc[2], r.L[2]);
+                c = (int32_t)(r.cell_off + cx + (int64_t)r.nc[0] * (cy + (int64_t)r.nc[1] * cz));
+            } else {
+                atomicOr(err, MD_FLAG_NONFINITE);
+                c = (int32_t)(r.cell_off + i % ((int64_t)r.nc[0] * r.nc[1] * r.nc[2]));
+            }
             cell_of[i] = c;
         }
         const int32_t prev = __shfl_up(c, 1, 64);
@@ -272,11 +283,11 @@ void launch_load_user(hipStream_t s, int grid, int64_t n, const double *pos_user
 
 void launch_bin(hipStream_t s, int grid, const int32_t *pred, int64_t n, int32_t R,
                 const RepDesc *reps, const int32_t *rep_of, double4 *pos, int32_t *cell_of,
-                int32_t *slot, int32_t *count)
+                int32_t *slot, int32_t *count, int32_t *err)
 {
     (void)R;
     hipLaunchKernelGGL(k_bin, dim3(grid), dim3(256), 0, s, pred, n, reps, rep_of, pos, cell_of,
-                       slot, count);
+                       slot, count, err);
 }
 
 void launch_scan(hipStream_t s, const int32_t *pred, int64_t C, int32_t *count, int32_t *start,

@@ -77,7 +77,7 @@ void launch_load_user(hipStream_t s, int grid, int64_t n, const double *pos_user
                       const double *vel_user, double4 *pos, double *vel, int32_t *id);
 void launch_bin(hipStream_t s, int grid, const int32_t *pred, int64_t n, int32_t R,
                 const RepDesc *reps, const int32_t *rep_of, double4 *pos, int32_t *cell_of,
-                int32_t *slot, int32_t *count);
+                int32_t *slot, int32_t *count, int32_t *err);
 void launch_scan(hipStream_t s, const int32_t *pred, int64_t C, int32_t *count,
                  int32_t *start, DevCtl *ctl);
 void launch_scatter(hipStream_t s, int grid, const int32_t *pred, int64_t n,

@@ -521,3 +521,34 @@ def test_autograd_function_gradients():
     gxo, gpo = oracle.lj_vjp(x, L, pi, pj, u, 0.01, eps=1.05, sigma=0.98)
     assert rel(pos.grad.cpu().numpy(), gxo) <= 1e-11
     assert np.allclose(params.grad.cpu().numpy(), gpo, rtol=1e-10)
+
+
+def test_nonfinite_positions_are_flagged_and_spread():
+    # a run that blows up: a quarter of the atoms get infinite velocities, so
+    # their positions turn non-finite after the first drift; the rebuilds that
+    # follow flag them and keep them spread over the cells (no cell collects
+    # them all), and the status reports the non-finite values
+    w = W.lj_fcc(8)
+    s = MDSystem.from_workload(w)
+    F = torch.empty_like(s.pos)
+    B.md_build_cells(s.ctx, s.pos, s.boxes, w.pot.rc, w.skin)
+    B.md_verlet_step(s.ctx, s.dpot, B.MD_FP64, B.MD_LIST_FULL, s.pos, s.vel, F, w.dt, w.mass, 2, None, None)
+    assert s.status()[0] == B.MD_OK
+    brick0 = B.md_query(s.ctx, 7)
+    vel = s.vel.clone()
+    vel[0, ::4] = float("inf")
+    s.vel.copy_(vel)
+    nreb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    B.md_verlet_step(s.ctx, s.dpot, B.MD_FP64, B.MD_LIST_FULL, s.pos, s.vel, F, w.dt, w.mass, 5, None, nreb)
+    code, flags, _ = s.status()
+    assert code == B.MD_ERR_NONFINITE and flags & B.FLAG_NONFINITE
+    assert int(nreb.item()) >= 1
+    cs, _ = B.md_get_cells(s.ctx)
+    assert int(np.diff(cs).max()) <= 2 * int(np.diff(cs).mean()) + 8
+    assert B.md_query(s.ctx, 7) <= brick0 + 64
+    # finite positions again: the context recovers
+    w2 = W.lj_fcc(8)
+    s.pos.copy_(torch.as_tensor(w2.pos, device="cuda"))
+    F2, _, _ = s.forces(B.MD_FP64)
+    assert s.status()[0] == B.MD_OK
+    assert bool(torch.isfinite(F2).all())
