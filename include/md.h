@@ -303,7 +303,11 @@ int64_t md_get_task_graph(md_ctx *ctx, int32_t *succ_off, int32_t *succ, int64_t
  * Returns MD_OK or MD_ERR_ARG. */
 int md_set_tuning(md_ctx *ctx, int32_t key, int32_t value);
 
-/* Current configuration [host out]: key 0 LDS stage (candidates), 1 workgroups
+/* Current configuration [host out]: key 0 LDS stage of the force and adjoint
+ * tasks (candidates; unless set with md_set_tuning, sized at the first list
+ * build from the largest halo, and for LJ grown to the largest stage that
+ * keeps as many workgroups resident per CU, so that halos that grow later stay
+ * in LDS), 1 workgroups
  * per CU, 2 per-atom list capacity, 3 brick shape (bx | by << 8 | bz << 16 of
  * replica 0), 4 threads per brick task, 5 bricks in total, 6 largest brick halo
  * (candidates) and 7 largest brick (atoms) seen by the list builds since the
@@ -315,7 +319,10 @@ int md_set_tuning(md_ctx *ctx, int32_t key, int32_t value);
  * stored as 16-bit candidate indices (bricks on axes of at least 4 cells
  * whose whole halo fits the LDS stage; the others store 32-bit entries with
  * an image code; synchronises), 16 bytes of the static scratch array of
- * md_compute_forces_noalloc.
+ * md_compute_forces_noalloc, 17 candidates the list build stages per brick
+ * (at most key 0: its own static LDS is larger than the force tasks'; a halo
+ * between the two is listed with its last candidates read from global memory
+ * and still gets 16-bit entries).
  * Returns MD_OK, MD_ERR_ARG, MD_ERR_STATE (keys 10 and 15 without a list) or MD_ERR_HIP. */
 int md_query(md_ctx *ctx, int32_t key, int64_t *value);
 

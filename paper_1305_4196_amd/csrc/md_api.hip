@@ -160,6 +160,7 @@ struct md_ctx {
     bool have_list = false;
     int list_kind = MD_LIST_FULL;
     int32_t cap = 256;       // candidates staged in LDS per brick task
+    int32_t cap_list = 256;  // candidates the list build stages (<= cap: its static LDS is larger)
     bool cap_user = false;
     int32_t M = 0;
     int64_t need_M = 0;
@@ -236,6 +237,15 @@ struct md_ctx {
     {
         return grid_with(stage_bytes(cap, 0, false, bd.stride) +
                          (density_table_in_lds(mixed, p) ? (size_t)(p->rho.n_knots - 1) * 16 : 0));
+    }
+    // the list build's grid: its own stage plus its static LDS
+    int grid_list(int half) const
+    {
+        const size_t per_block = stage_bytes(cap_list, 0, half != 0, bd.stride) + list_static_lds(half) + 512;
+        int per_cu = (int)std::min<size_t>((size_t)wgpc, std::max<size_t>(1, (160 * 1024) / per_block));
+        per_cu = std::max(1, std::min(per_cu, 32 / (threads / 64)));
+        const int64_t g = std::min<int64_t>(B, (int64_t)n_cu * per_cu);
+        return (int)std::max<int64_t>(1, g);
     }
     int grid_tasks(int nextra, bool with_j) const
     {
@@ -350,7 +360,8 @@ ListArgs list_args(md_ctx *c, const int32_t *pred, const double4 *src, int half)
     a.M = c->M;
     a.rl2 = c->rl * c->rl;
     a.half = half;
-    a.cap = c->cap;
+    a.cap = c->cap_list;
+    a.shift_cap = c->cap;
     a.ctl = c->ctl;
     return a;
 }
@@ -563,6 +574,7 @@ int fit_wave_stage(md_ctx *c)
     const int64_t fit = (room - 16 - 4 * (int64_t)c->bd.stride) / (6 * 8 + 4 + 2) / 64 * 64;
     if (fit < 64) return fail(c, MD_ERR_STATE, "wave-scheduled list: brick record leaves no LDS stage");
     c->cap = (int32_t)fit;
+    c->cap_list = std::min(c->cap_list, c->cap);
     return MD_OK;
 }
 
@@ -605,7 +617,7 @@ int size_list(md_ctx *c, const double4 *src, int half, hipStream_t s, int per_ca
         int rc = plan_bricks(c, s);
         if (rc != MD_OK) return rc;
     }
-    if (!c->cap_user) c->cap = (int32_t)std::min<int64_t>(cap_limit(c), 2048);
+    if (!c->cap_user) c->cap = c->cap_list = (int32_t)std::min<int64_t>(cap_limit(c), 2048);
     ListArgs a = list_args(c, c->one, src, half);
     a.M = 0;
     a.nbr = nullptr;
@@ -614,7 +626,7 @@ int size_list(md_ctx *c, const double4 *src, int half, hipStream_t s, int per_ca
         hipMemcpyAsync(&c->ctl->max_nbhd, &zero3[1], sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(&c->ctl->max_brick, &zero3[2], sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess)
         return fail(c, MD_ERR_HIP, "list sizing: reset");
-    launch_build_list(s, c->grid_tasks(0, half != 0), c->threads, a);
+    launch_build_list(s, c->grid_list(half), c->threads, a);
     int32_t mx = 0, nbhd = 0;
     if (hipMemcpyAsync(&mx, &c->ctl->max_cnt, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipMemcpyAsync(&nbhd, &c->ctl->max_nbhd, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -622,12 +634,33 @@ int size_list(md_ctx *c, const double4 *src, int half, hipStream_t s, int per_ca
         return fail(c, MD_ERR_HIP, "list sizing: readback");
     // LDS stage: the largest halo seen plus 5 %, in multiples of 64, within
     // half a CU's LDS for the kernels' layout (larger halos read their last
-    // candidates from global memory)
+    // candidates from global memory).  Without EAM, the stage then grows to
+    // the largest that leaves as many workgroups resident per CU: halos that
+    // grow as the system evolves (a free cluster contracting to its
+    // equilibrium density) stay wholly staged, and their bricks keep the
+    // 16-bit entries, at no cost in occupancy.  (The mixed EAM density pass
+    // adds its table to the stage, so EAM stages keep the smallest size.)
+    // The list build, whose static LDS is larger, grows its own stage under
+    // the same rule; a halo that fits the force tasks' stage but not the list
+    // build's is listed with some candidates read from global memory.
     if (!c->cap_user) {
         // (1 KB kept free for the allocation granularity)
-        const int64_t half_cu = ((160 * 1024) / 2 - 512 - 1024 - 4 * (int64_t)c->bd.stride) / per_cand / 64 * 64;
-        c->cap = (int32_t)std::max<int64_t>(
-            64, std::min<int64_t>(std::min<int64_t>(cap_limit(c), half_cu), ((int64_t)(1.05 * nbhd) + 63) / 64 * 64));
+        const int64_t cu = 160 * 1024, fixed = 512 + 1024 + 4 * (int64_t)c->bd.stride;
+        const int64_t waves = 32 / (c->threads / 64);
+        const int64_t want = ((int64_t)(1.05 * nbhd) + 63) / 64 * 64;
+        auto grown = [&](int64_t bytes, int64_t extra) {
+            const int64_t lim = std::min<int64_t>(cap_limit(c), (cu / 2 - fixed - extra) / bytes / 64 * 64);
+            int64_t cap = std::max<int64_t>(64, std::min<int64_t>(lim, want));
+            if (!c->eam_seen) {
+                const int64_t per_cu = std::max<int64_t>(
+                    1, std::min<int64_t>({(int64_t)c->wgpc, waves, cu / (cap * bytes + fixed + extra)}));
+                cap = std::max<int64_t>(cap, std::min<int64_t>(lim, (cu / per_cu - fixed - extra) / bytes / 64 * 64));
+            }
+            return std::max<int64_t>(64, cap);
+        };
+        c->cap = (int32_t)grown(per_cand, 0);
+        c->cap_list = (int32_t)std::min<int64_t>(
+            c->cap, grown(3 * 8 + 2 + (half ? 4 : 0), (int64_t)list_static_lds(half)));
     }
     // rows: kept if they are already allocated and no overflow asked for more
     if (c->M > 0 && c->need_M <= c->M) return MD_OK;
@@ -654,7 +687,7 @@ int builder_half(const md_ctx *c, int half) { return half && !c->shell ? 1 : 0; 
 // one list build (la made with builder_half), and the filter of the 14-cell half list
 void build_list(md_ctx *c, hipStream_t s, int half, const ListArgs &la)
 {
-    launch_build_list(s, c->grid_tasks(0, la.half != 0), c->threads, la);
+    launch_build_list(s, c->grid_list(la.half), c->threads, la);
     if (half && c->shell) launch_shell_filter(s, c->grid_tasks(0, false), c->threads, la);
 }
 
@@ -1355,7 +1388,7 @@ int md_set_tuning(md_ctx *c, int32_t key, int32_t value)
     const int64_t cap_max = (c->lds_max - 4096 - 4 * (int64_t)br_stride(512, 64)) / (int64_t)(4 * sizeof(double) + sizeof(uint16_t));
     if (key == 0 && value >= 64 && value <= 4096 && value % 64 == 0 && value <= cap_max) {
         // the list's entry format depends on which halos fit the stage
-        c->cap = value;
+        c->cap = c->cap_list = value;
         c->cap_user = true;
         c->have_list = false;
         return MD_OK;
@@ -1488,7 +1521,8 @@ int md_query(md_ctx *c, int32_t key, int64_t *value)
         return MD_OK;
     }
     case 16: *value = (int64_t)MD_NOALLOC_BYTES; return MD_OK;
-    default: return fail(c, MD_ERR_ARG, "query: key 0..16");
+    case 17: *value = c->cap_list; return MD_OK;
+    default: return fail(c, MD_ERR_ARG, "query: key 0..17");
     }
 }
 

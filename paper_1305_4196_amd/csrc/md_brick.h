@@ -237,7 +237,7 @@ __device__ __forceinline__ void wave_scan_lds(int32_t *a, int32_t n)
 
 // Builds the record of brick g in LDS (block-wide; ends with a barrier).
 __device__ __forceinline__ void brick_setup(const Stage &s, const BrickDims &d, const BrickGeom &g,
-                                            const int32_t *start)
+                                            const int32_t *start, int32_t shift_cap)
 {
     int32_t *rec = s.rec;
     int32_t *soff = rec + br_soff(d), *sbeg = rec + br_sbeg(d);
@@ -287,7 +287,7 @@ __device__ __forceinline__ void brick_setup(const Stage &s, const BrickDims &d, 
         bool img = false;
         for (int k = 0; k < 3; k++) img |= g.nc[k] < 4 || g.e[k] + 2 > g.nc[k];
         rec[BR_IMG] = img ? 1 : 0;
-        rec[BR_SHIFT] = !img && soff[H] <= s.cap && soff[H] <= 65536 ? 1 : 0;
+        rec[BR_SHIFT] = !img && soff[H] <= shift_cap && soff[H] <= 65536 ? 1 : 0;
     }
     __syncthreads();
 }

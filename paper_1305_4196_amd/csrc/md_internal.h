@@ -125,7 +125,10 @@ struct ListArgs {
     int32_t M;
     double rl2;
     int half;
-    int32_t cap;              // candidates staged in LDS per brick task
+    int32_t cap;              // candidates the list build stages in LDS per brick
+    int32_t shift_cap;        // stage of the force and adjoint tasks: bricks whose whole
+                              // halo fits it (and no axis wraps onto itself) get BR_SHIFT
+                              // and 16-bit entries, whatever the list build stages itself
     // optional copy of the freshly sorted state into the working buffers
     const double *vel_src;
     const int32_t *id_src;
@@ -137,6 +140,7 @@ struct ListArgs {
 };
 void launch_shell_filter(hipStream_t s, int grid, int threads, const ListArgs &a);
 void launch_build_list(hipStream_t s, int grid, int threads, const ListArgs &a);
+size_t list_static_lds(int half);   // static LDS of the list build kernel (bytes)
 
 // forces
 struct ForceArgs {

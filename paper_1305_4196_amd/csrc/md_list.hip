@@ -475,7 +475,7 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_build_list(ListArgs a)
             next_cell = (int32_t)(blockDim.x >> 6);
         }
         const BrickGeom g = brick_geom(a.reps, a.R, b);
-        brick_setup(st, a.bd, g, a.start);
+        brick_setup(st, a.bd, g, a.start, a.shift_cap);
         int32_t *grec = a.brec + b * (int64_t)a.bd.stride;
         for (int32_t t = threadIdx.x; t < a.bd.stride; t += blockDim.x) grec[t] = st.rec[t];
         const int32_t natoms = st.rec[BR_ATOMS];
@@ -529,10 +529,14 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_build_list(ListArgs a)
             const int32_t hown = (lc[0] + 1) % g.nc[0] + g.hn[0] * ((lc[1] + 1) % g.nc[1] + g.hn[1] * ((lc[2] + 1) % g.nc[2]));
             build_runs(st, g, lc, np, st.rec[BR_HDR + hown], na, runs, crun);
             const bool any_wrap = wrap[0] || wrap[1] || wrap[2];
-            // (bricks staged through their cell images have their whole halo in LDS)
-            if (st.rec[BR_SHIFT] != 0) {
+            // (bricks staged through their cell images have their whole halo in
+            // the force tasks' stage, which may be larger than this one)
+            if (st.rec[BR_SHIFT] != 0 && st.rec[BR_TOTAL] <= st.cap) {
                 if (any_wrap) scan_cell<HALF, true, true, true>(a, st, g, e, na, lc, wrap, runs, crun, cnt_lds + 128 * w, my_max, &bpairs);
                 else scan_cell<HALF, false, true, true>(a, st, g, e, na, lc, wrap, runs, crun, cnt_lds + 128 * w, my_max, &bpairs);
+            } else if (st.rec[BR_SHIFT] != 0) {
+                if (any_wrap) scan_cell<HALF, true, true, false>(a, st, g, e, na, lc, wrap, runs, crun, cnt_lds + 128 * w, my_max, &bpairs);
+                else scan_cell<HALF, false, true, false>(a, st, g, e, na, lc, wrap, runs, crun, cnt_lds + 128 * w, my_max, &bpairs);
             } else if (st.rec[BR_TOTAL] <= st.cap) {
                 if (any_wrap) scan_cell<HALF, true, false, true>(a, st, g, e, na, lc, wrap, runs, crun, cnt_lds + 128 * w, my_max, &bpairs);
                 else scan_cell<HALF, false, false, true>(a, st, g, e, na, lc, wrap, runs, crun, cnt_lds + 128 * w, my_max, &bpairs);
@@ -691,6 +695,17 @@ void launch_shell_filter(hipStream_t s, int grid, int threads, const ListArgs &a
     const size_t lds = stage_bytes(0, 0, false, a.bd.stride);
     allow_lds(k_shell_filter, lds);
     hipLaunchKernelGGL(k_shell_filter, dim3(grid), dim3(threads), lds, s, a);
+}
+
+size_t list_static_lds(int half)
+{
+    auto query = [](const void *k) -> size_t {
+        hipFuncAttributes attr{};
+        return hipFuncGetAttributes(&attr, k) == hipSuccess ? attr.sharedSizeBytes : 8192;
+    };
+    static const size_t bytes[2] = {query(reinterpret_cast<const void *>(k_build_list<false>)),
+                                    query(reinterpret_cast<const void *>(k_build_list<true>))};
+    return bytes[half != 0];
 }
 
 void launch_build_list(hipStream_t s, int grid, int threads, const ListArgs &a)

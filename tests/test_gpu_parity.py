@@ -552,3 +552,48 @@ def test_nonfinite_positions_are_flagged_and_spread():
     F2, _, _ = s.forces(B.MD_FP64)
     assert s.status()[0] == B.MD_OK
     assert bool(torch.isfinite(F2).all())
+
+
+def test_contracting_system_keeps_16bit_entries():
+    # The stage is sized once, on the first configuration; an LJ stage is then
+    # grown to the largest that keeps as many workgroups resident.  A system
+    # that contracts afterwards (a free cluster relaxing to a denser state) has
+    # larger halos: they stay wholly staged for the force tasks, so every brick
+    # keeps the 16-bit entries, while the list build, whose own stage is
+    # smaller, reads the last candidates of such halos from global memory.
+    w = W.lj_fcc(17)                                   # 10 cells per axis, 19,652 atoms
+    w.pos = thermal(w, 0.05, 4)
+    L = w.boxes[0]
+    s = MDSystem.from_workload(w)
+    B.md_set_tuning(s.ctx, 3, 4 | 3 << 8 | 2 << 16)
+    B.md_set_tuning(s.ctx, 4, 512)
+    F = torch.empty_like(s.pos)
+    B.md_build_cells(s.ctx, s.pos, s.boxes, w.pot.rc, w.skin)
+    B.md_verlet_step(s.ctx, s.dpot, B.MD_FP64, B.MD_LIST_FULL, s.pos.clone(), s.vel.clone(), F,
+                     w.dt, w.mass, 1, None, None)
+    assert s.status()[0] == B.MD_OK
+    cap, cap_list, halo0 = B.md_query(s.ctx, 0), B.md_query(s.ctx, 17), B.md_query(s.ctx, 6)
+    assert halo0 <= cap_list < cap
+    c = 0.5 * np.asarray(L).reshape(3, 1)
+    x0 = oracle.wrap(w.pos, L)
+    for f in (0.98, 0.97, 0.96, 0.95, 0.94):
+        x = np.ascontiguousarray(c + f * (x0 - c))
+        s.pos.copy_(torch.as_tensor(x, device="cuda"))
+        s.build(B.MD_LIST_FULL)
+        assert s.status()[0] == B.MD_OK
+        if B.md_query(s.ctx, 6) > cap_list:
+            break
+    # the sizing did not run again; the largest halo lies between the stages
+    assert B.md_query(s.ctx, 0) == cap and B.md_query(s.ctx, 17) == cap_list
+    assert cap_list < B.md_query(s.ctx, 6) <= cap
+    total, narrow = B.md_query(s.ctx, 10), B.md_query(s.ctx, 15)
+    assert narrow == total > 0
+    start, nbr = s.neighbor_list()
+    os_, on = oracle.neighbor_list(x, L, w.pot.rc + w.skin, full=True)
+    assert np.array_equal(start, os_)
+    assert user_pairs(start, nbr) == user_pairs(os_, on)
+    Fo, Eo, _ = oracle.forces(x, L, w.pot, skin=w.skin)
+    for prec, tol in ((B.MD_FP64, FP64_TOL), (B.MD_MIXED, MIXED_TOL)):
+        Fg, E, _ = s.forces(prec, B.MD_LIST_FULL, rebuild=False)
+        assert rel(Fg.cpu().numpy(), Fo) <= tol
+        assert E.item() == pytest.approx(Eo, rel=10 * tol)
