@@ -597,3 +597,11 @@ def test_contracting_system_keeps_16bit_entries():
         Fg, E, _ = s.forces(prec, B.MD_LIST_FULL, rebuild=False)
         assert rel(Fg.cpu().numpy(), Fo) <= tol
         assert E.item() == pytest.approx(Eo, rel=10 * tol)
+    # the half list of the same bricks (its list build also stages sorted indices)
+    s.build(B.MD_LIST_HALF)
+    assert s.status()[0] == B.MD_OK
+    assert B.md_query(s.ctx, 15) == B.md_query(s.ctx, 10) > 0
+    hs, hn = oracle.neighbor_list(x, L, w.pot.rc + w.skin, full=False)
+    assert user_pairs(*s.neighbor_list()) == user_pairs(hs, hn)
+    Fh, _, _ = s.forces(B.MD_FP64, B.MD_LIST_HALF, rebuild=False)
+    assert rel(Fh.cpu().numpy(), Fo) <= FP64_TOL
