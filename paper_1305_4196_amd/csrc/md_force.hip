@@ -52,7 +52,8 @@ __device__ __forceinline__ void spl64(const double *tab, double u, int nk, doubl
 {
     const int k = seg(u, nk);
     const double t = u - (double)k;
-    const double4 c = reinterpret_cast<const double4 *>(tab)[k];
+    // (a 32-bit unsigned byte offset: one scalar base plus a vector offset)
+    const double4 c = *reinterpret_cast<const double4 *>(reinterpret_cast<const char *>(tab) + (uint32_t)k * 32u);
     f = c.x + t * (c.y + t * (c.z + t * c.w));
     fu = c.y + t * (2.0 * c.z + 3.0 * t * c.w);
 }
@@ -61,10 +62,10 @@ __device__ __forceinline__ void spl64(const double *tab, double u, int nk, doubl
 // picks the same segment as floor once clamped to [0, nk-2]
 __device__ __forceinline__ void spl32f(const float *tab, float u, int nk, float &f, float &fu)
 {
-    int k = (int)u;
-    k = k > nk - 2 ? nk - 2 : (k < 0 ? 0 : k);
+    // (u clamped to [0, nk-2] by one median-of-three, then truncated)
+    const int k = (int)__builtin_amdgcn_fmed3f(u, 0.0f, (float)(nk - 2));
     const float t = u - (float)k;
-    const float4 c = reinterpret_cast<const float4 *>(tab)[k];
+    const float4 c = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tab) + (uint32_t)k * 16u);
     f = c.x + t * (c.y + t * (c.z + t * c.w));
     fu = c.y + t * (2.0f * c.z + 3.0f * t * c.w);
 }
@@ -571,25 +572,31 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_density(ForceArgs a)
     BRICK_TASK_BEGIN(st, a.pos, nullptr, nullptr)
         double rho = 0.0;
         const double4 xi = a.pos[i];
-        STAGE_IMG_SPLIT(all_staged, has_img,
-            walk_list<STAGED, IMG, true>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
-                [&](bool ok, int32_t, double, double, double, double r2) {
-                    const bool in = ok && r2 < rrho2;
-                    double f;
-                    if (MIXED) {
-                        // r and the table argument in binary32, like the table
-                        float ff, fu;
-                        const float uf = (__builtin_sqrtf((float)r2) - x0f) * ihf;
-                        if (lt) spl32f(reinterpret_cast<const float *>(ltab), uf, nk, ff, fu);
-                        else spl32f(a.tabf[1], uf, nk, ff, fu);
-                        f = (double)ff;
-                    } else {
-                        double fu;
-                        spl64(a.tab[1], (sqrt(r2) - x0) * ih, nk, f, fu);
-                    }
-                    rho += in ? f : 0.0;
-                });
-        )
+        // the pair loop once per table location, so that each copy reads its
+        // table through one address space (LDS or global, never flat)
+        auto pairs = [&](const float *tabf) __attribute__((always_inline)) {
+            STAGE_IMG_SPLIT(all_staged, has_img,
+                walk_list<STAGED, IMG, true>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
+                    [&](bool ok, int32_t, double, double, double, double r2) {
+                        const bool in = ok && r2 < rrho2;
+                        double f;
+                        if (MIXED) {
+                            // r (hardware square root) and the table argument in
+                            // binary32, like the table
+                            float ff, fu;
+                            const float uf = (__builtin_amdgcn_sqrtf((float)r2) - x0f) * ihf;
+                            spl32f(tabf, uf, nk, ff, fu);
+                            f = (double)ff;
+                        } else {
+                            double fu;
+                            spl64(a.tab[1], (sqrt(r2) - x0) * ih, nk, f, fu);
+                        }
+                        rho += in ? f : 0.0;
+                    });
+            )
+        };
+        if (lt) pairs(reinterpret_cast<const float *>(ltab));
+        else pairs(a.tabf[1]);
         if (valid) {
             double F, Fp;
             embed64(a, rho, F, Fp);
@@ -631,7 +638,7 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, MIXED ? 4 : 1) void k_eam_force(F
                     if (MIXED) {
                         // pair scalar in binary32 (r, table arguments, dV/dr / r with
                         // the binary32 reciprocal); r2 and the cutoff tests stay binary64
-                        const float rf = __builtin_sqrtf((float)r2);
+                        const float rf = __builtin_amdgcn_sqrtf((float)r2);
                         float f, fu, g, h;
                         spl32f(a.tabf[0], (rf - x0pf) * ihpf, nkp, f, fu);
                         spl32f(a.tabf[1], (rf - x0rf) * ihrf, nkr, g, h);
