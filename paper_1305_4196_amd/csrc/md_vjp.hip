@@ -65,6 +65,12 @@ __device__ __forceinline__ void embed_full(const ForceArgs &a, double rho, doubl
     lin = false;
 }
 
+// binary64 add to an LDS word shared by the workgroup's lanes
+__device__ __forceinline__ void lds_add(double *p, double v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // ---------------------------------------------------------------- LJ
 // Partner cotangent u_j of candidate k: from the LDS stage (extras ex0..ex0+2)
 // when the kernel stages it (STAGE_U) and k is staged, else gathered from HBM.
@@ -274,9 +280,10 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_vjp_b(VjpArgs v)
                             const double dp[4] = {0.0, 1.0, 2.0 * tp, 3.0 * t2};
                             double gv[4];
                             for (int p = 0; p < 4; p++) gv[p] = vE * pw[p] - s * dp[p] * ihp;
-                            // separate branches keep LDS and global atomics apart (no flat atomics)
+                            // LDS sums at workgroup scope, HBM sums at agent scope: the
+                            // two kinds of atomics cannot be merged into flat atomics
                             if (kp >= kp0)
-                                for (int p = 0; p < 4; p++) atomicAdd(&lphi[4 * (kp - kp0) + p], gv[p]);
+                                for (int p = 0; p < 4; p++) lds_add(&lphi[4 * (kp - kp0) + p], gv[p]);
                             else
                                 for (int p = 0; p < 4; p++) atomicAdd(&gphi[4 * (int64_t)kp + p], gv[p]);
                         }
@@ -287,7 +294,7 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_vjp_b(VjpArgs v)
                             double gv[4];
                             for (int p = 0; p < 4; p++) gv[p] = vE * Fs * pw[p] - (s * Fs * dp[p] * ihr + qq * pw[p]);
                             if (kr >= kr0)
-                                for (int p = 0; p < 4; p++) atomicAdd(&lrho[4 * (kr - kr0) + p], gv[p]);
+                                for (int p = 0; p < 4; p++) lds_add(&lrho[4 * (kr - kr0) + p], gv[p]);
                             else
                                 for (int p = 0; p < 4; p++) atomicAdd(&grho[4 * (int64_t)kr + p], gv[p]);
                         }
