@@ -397,6 +397,23 @@ __device__ __forceinline__ double rcp64(double x)
     return fma(r, e, r);
 }
 
+// sqrt(x) in binary64 for a pair's squared distance (x positive and normal;
+// x = 0, which only dummy slots see, gives NaN, which their masks discard):
+// the hardware reciprocal square root y, then one coupled Newton step on
+// g = x y and h = y / 2 and one residual correction of g (within about an
+// ulp, without the scaling of the general square root for tiny, huge and
+// special arguments)
+__device__ __forceinline__ double sqrt_pair(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-h, g, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double d = fma(-g, g, x);
+    return fma(d, h, g);
+}
+
 // Position of candidate k.  STAGED = true: the whole halo is in LDS (pure LDS
 // reads); false: candidates past the staged part come from global memory.  The
 // two are separate instantiations chosen once per brick, so the common path

@@ -589,7 +589,7 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_density(ForceArgs a)
                             f = (double)ff;
                         } else {
                             double fu;
-                            spl64(a.tab[1], (sqrt(r2) - x0) * ih, nk, f, fu);
+                            spl64(a.tab[1], (sqrt_pair(r2) - x0) * ih, nk, f, fu);
                         }
                         rho += in ? f : 0.0;
                     });
@@ -650,7 +650,7 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, MIXED ? 4 : 1) void k_eam_force(F
                         ep = in_phi ? (double)f : 0.0;
                         r = (double)rf;
                     } else {
-                        r = sqrt(r2);
+                        r = sqrt_pair(r2);
                         double f, fu, g, h;
                         spl64(a.tab[0], (r - x0p) * ihp, nkp, f, fu);
                         spl64(a.tab[1], (r - x0r) * ihr, nkr, g, h);

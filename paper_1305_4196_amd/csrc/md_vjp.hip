@@ -168,7 +168,7 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_vjp_a(VjpArgs v)
             walk_list<STAGED, IMG>(st, a.bd, a.pos, a.nbr, i, a.M, mm, xi, Lx, Ly, Lz,
                 [&](bool ok, int32_t k, double dx, double dy, double dz, double r2) {
                     if (!ok || !(r2 < rrho2)) return;
-                    const double r = sqrt(r2);
+                    const double r = sqrt_pair(r2);
                     int kk;
                     double tt, f, fu, fuu;
                     spl_full(a.tab[1], (r - x0r) * ihr, nkr, kk, tt, f, fu, fuu);
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_vjp_b(VjpArgs v)
                         fpj = a.fp[j];
                         qj = v.fpp[j];
                     }
-                    const double r = sqrt(r2);
+                    const double r = sqrt_pair(r2);
                     // one refined reciprocal instead of four divisions
                     const double ir = rcp64(r);
                     const double e[3] = {dx * ir, dy * ir, dz * ir};
