@@ -65,6 +65,14 @@ __device__ __forceinline__ void embed_full(const ForceArgs &a, double rho, doubl
     lin = false;
 }
 
+// p[j] for a sorted atom index j (below 2^26): a 32-bit unsigned byte offset,
+// so that the gather takes one scalar base plus a vector offset
+template <typename T>
+__device__ __forceinline__ T at32(const T *p, int32_t j)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(p) + (uint32_t)j * (uint32_t)sizeof(T));
+}
+
 // binary64 add to an LDS word shared by the workgroup's lanes
 __device__ __forceinline__ void lds_add(double *p, double v)
 {
@@ -82,7 +90,8 @@ __device__ __forceinline__ double4 partner_u(const Stage &st, const BrickDims &b
         const double *e = st.ex + (size_t)ex0 * st.cap + k;
         return make_double4(e[0], e[st.cap], e[2 * (size_t)st.cap], 0.0);
     }
-    return u[STAGE_U ? candidate_index(st, bd, k) : candidate_j<STAGED>(st, bd, k)];
+    const int32_t j = STAGE_U ? candidate_index(st, bd, k) : candidate_j<STAGED>(st, bd, k);
+    return at32(u, j);
 }
 
 // two 512-thread workgroups per CU (at most 128 VGPRs).  STAGE_U: the partner
@@ -237,8 +246,8 @@ __global__ __launch_bounds__(TASK_MAX_THREADS) void k_eam_vjp_b(VjpArgs v)
                         fpj = st.ex[k];
                         qj = st.ex[st.cap + k];
                     } else {
-                        fpj = a.fp[j];
-                        qj = v.fpp[j];
+                        fpj = at32(a.fp, j);
+                        qj = at32(v.fpp, j);
                     }
                     const double r = sqrt_pair(r2);
                     // one refined reciprocal instead of four divisions
