@@ -21,12 +21,14 @@
 // atoms at most two cell widths (plus rounding) apart; a different image would
 // move them by L >= 4 cell widths, so the list's minimum-image code of every
 // entry equals the image of its candidate's halo cell.  Such bricks, when
-// their whole halo fits the LDS stage (BR_SHIFT = 1), stage their candidates
-// already shifted by the cell image, their list entries carry no code and the
-// pair loops apply none; the others (an axis of fewer than 4 cells, a halo
-// that covers its axis, or one only partly staged) keep the per-entry codes.
-// The stage capacity is fixed when the list is built (changing it drops the
-// list), so the flag the list build records holds for every later task.
+// their whole halo fits the force and adjoint tasks' LDS stage (BR_SHIFT = 1),
+// stage their candidates already shifted by the cell image, their list
+// entries carry no code and the pair loops apply none; the others (an axis of
+// fewer than 4 cells, a halo that covers its axis, or one only partly staged)
+// keep the per-entry codes.  The stage capacity is fixed when the list is
+// built (changing it drops the list), so the flag the list build records holds
+// for every later task.  (The list build stages up to its own, possibly
+// smaller, capacity; BR_SHIFT follows the tasks' stage.)
 //
 // Each lane owns one atom of its brick (lane t of a workgroup of T threads
 // takes the brick's atoms t, t + T, ...; T is a multiple of 64 up to 512), so
