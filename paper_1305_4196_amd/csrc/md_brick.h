@@ -41,6 +41,9 @@
 //   [BR_E] own cells  [BR_IMG] 1 if pairs need the per-entry image codes
 //   [BR_SHIFT] 1 if the halo is staged through the cell images (entries carry no
 //              code and use the narrow 16-bit layout)
+//   [BR_FACE] 1 if some halo cell is seen through an image (the brick touches a
+//              face of the box); staging through the images of a brick without
+//              one is a plain copy
 //   soff[Hm+1]  sbeg[Hm]  aoff[Em+1]  abeg[Em]  himg[Hm]
 // (aoff/abeg: the same for the brick's own cells, in x-fastest order; himg:
 // the image code of each halo cell, in the list-entry encoding.)
@@ -64,7 +67,7 @@
 
 constexpr int TASK_MAX_THREADS = 512;
 
-enum { BR_TOTAL = 0, BR_ATOMS = 1, BR_REP = 2, BR_H = 3, BR_E = 4, BR_IMG = 5, BR_SHIFT = 6, BR_HDR = 8 };
+enum { BR_TOTAL = 0, BR_ATOMS = 1, BR_REP = 2, BR_H = 3, BR_E = 4, BR_IMG = 5, BR_SHIFT = 6, BR_FACE = 7, BR_HDR = 8 };
 
 __host__ __device__ inline int32_t br_soff(const BrickDims &d) { (void)d; return BR_HDR; }
 __host__ __device__ inline int32_t br_sbeg(const BrickDims &d) { return BR_HDR + d.Hm + 1; }
@@ -290,6 +293,9 @@ __device__ __forceinline__ void brick_setup(const Stage &s, const BrickDims &d, 
         for (int k = 0; k < 3; k++) img |= g.nc[k] < 4 || g.e[k] + 2 > g.nc[k];
         rec[BR_IMG] = img ? 1 : 0;
         rec[BR_SHIFT] = !img && soff[H] <= shift_cap && soff[H] <= 65536 ? 1 : 0;
+        int32_t face = 0;
+        for (int32_t h = 0; h < H; h++) face |= himg[h];
+        rec[BR_FACE] = face != 0 ? 1 : 0;
     }
     __syncthreads();
 }
@@ -348,7 +354,8 @@ __device__ __forceinline__ void brick_load(const Stage &s, const BrickDims &d, c
     __syncthreads();
     const int32_t total = s.rec[BR_TOTAL];
     const int32_t lim = total < s.cap ? total : s.cap;
-    const bool shifted = s.rec[BR_SHIFT] != 0;
+    // (a brick away from the box faces sees every halo cell directly)
+    const bool shifted = s.rec[BR_SHIFT] != 0 && s.rec[BR_FACE] != 0;
     const RepDesc &rep = reps[s.rec[BR_REP]];
     const double Lx = rep.L[0], Ly = rep.L[1], Lz = rep.L[2];
     // the halo cell of every staged candidate, one cell per thread, so that
