@@ -339,6 +339,14 @@ __device__ __forceinline__ double image_shift(uint32_t code, uint32_t add_bit, d
     return (code & add_bit) ? L : ((code & (add_bit << 1)) ? -L : 0.0);
 }
 
+// p[j] for a sorted atom index j (below 2^26): a 32-bit unsigned byte offset,
+// so that the gather takes one scalar base plus a vector offset
+template <typename T>
+__device__ __forceinline__ T at32(const T *p, int32_t j)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(p) + (uint32_t)j * (uint32_t)sizeof(T));
+}
+
 // Copies the record of brick b into LDS and stages its first `cap` candidates
 // (block-wide; ends with a barrier).  extra0/extra1 (may be null) are staged
 // as extras 0 and 1; vec (may be null) as three more extras (its x, y, z)
@@ -370,7 +378,7 @@ __device__ __forceinline__ void brick_load(const Stage &s, const BrickDims &d, c
     for (int32_t k = threadIdx.x; k < lim; k += blockDim.x) {
         const int32_t h = hc[k];
         const int32_t g = s.rec[br_sbeg(d) + h] + (k - s.rec[BR_HDR + h]);
-        const double4 p = pos[g];
+        const double4 p = at32(pos, g);
         if (shifted) {
             const uint32_t c = (uint32_t)s.rec[br_himg(d) + h];
             s.xyz[3 * k] = p.x - image_shift(c, 1u, Lx);
@@ -382,10 +390,10 @@ __device__ __forceinline__ void brick_load(const Stage &s, const BrickDims &d, c
             s.xyz[3 * k + 2] = p.z;
         }
         if (s.j != nullptr) s.j[k] = g;
-        if (extra0 != nullptr) s.ex[k] = extra0[g];
-        if (extra1 != nullptr) s.ex[s.cap + k] = extra1[g];
+        if (extra0 != nullptr) s.ex[k] = at32(extra0, g);
+        if (extra1 != nullptr) s.ex[s.cap + k] = at32(extra1, g);
         if (vec != nullptr) {
-            const double4 u = vec[g];
+            const double4 u = at32(vec, g);
             double *e = s.ex + (size_t)vec_at * s.cap + k;
             e[0] = u.x;
             e[s.cap] = u.y;

@@ -489,7 +489,7 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_build_list(ListArgs a)
         const int32_t lim = total < st.cap ? total : st.cap;
         for (int32_t k = threadIdx.x; k < lim; k += blockDim.x) {
             const int32_t jj = candidate_index(st, a.bd, k);
-            const double4 p = a.src[jj];
+            const double4 p = at32(a.src, jj);
             st.xyz[3 * k] = p.x;
             st.xyz[3 * k + 1] = p.y;
             st.xyz[3 * k + 2] = p.z;

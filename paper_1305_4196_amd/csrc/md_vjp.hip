@@ -65,14 +65,6 @@ __device__ __forceinline__ void embed_full(const ForceArgs &a, double rho, doubl
     lin = false;
 }
 
-// p[j] for a sorted atom index j (below 2^26): a 32-bit unsigned byte offset,
-// so that the gather takes one scalar base plus a vector offset
-template <typename T>
-__device__ __forceinline__ T at32(const T *p, int32_t j)
-{
-    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(p) + (uint32_t)j * (uint32_t)sizeof(T));
-}
-
 // binary64 add to an LDS word shared by the workgroup's lanes
 __device__ __forceinline__ void lds_add(double *p, double v)
 {
