@@ -163,8 +163,8 @@ int md_compute_forces(md_ctx *ctx, const md_potential *pot, int32_t precision, d
 /* md_compute_forces for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): the same arguments, kernels and results, but every scratch
- * buffer the call's kernels use -- sorted forces, block partials, counters,
- * the brick queue, EAM densities and staged tables, per-atom energies of a
+ * buffer the call's kernels use -- sorted forces, block partials, the brick
+ * queue, EAM densities and staged tables, per-atom energies of a
  * multi-replica context -- lies in one static device array of the library,
  * MD_NOALLOC_BYTES = 48 MiB per device (md_query key 16), held by every device
  * the library runs on until the process ends.  The call allocates nothing and
@@ -174,7 +174,7 @@ int md_compute_forces(md_ctx *ctx, const md_potential *pot, int32_t precision, d
  * multi-replica context, and about 130 KiB besides (LJ up to about 2.0M atoms,
  * EAM up to about 1.2M); a larger system is rejected with MD_ERR_ARG before
  * anything is enqueued.  Every call on a device shares that device's array
- * (the counters it needs zeroed are cleared at the start of each call), so
+ * (the queue counters it needs zeroed are cleared at the start of each call), so
  * calls that overlap in time on one device -- on different streams or from
  * different threads -- race and give wrong results; serialise them.
  * Errors: as md_compute_forces, plus MD_ERR_STATE (list kind other than full). */

@@ -720,7 +720,6 @@ ForceArgs force_args(md_ctx *c, const md_potential *p)
     a.rho = c->rho;
     a.fp = c->fp;
     a.partial = c->partial;
-    a.done = &c->ctl->done[0];
     a.ctl = c->ctl;
     a.mass = 1.0;
     if (p->kind == MD_POT_EAM) {
@@ -1029,11 +1028,10 @@ int md_compute_forces_noalloc(md_ctx *c, const md_potential *p, int32_t precisio
         const md_spline *sp[3] = {&p->phi, &p->rho, &p->embed};
         for (int k = 0; k < 3; k++) ntab += 4 * (int64_t)(sp[k]->n_knots - 1);
     }
-    // carve the scratch: [counters | brick queue | partials | forces | rho, F' | tables | per-atom E, W]
+    // carve the scratch: [brick queue | partials | forces | rho, F' | tables | per-atom E, W]
     auto up = [](uint64_t b) { return (b + 255) & ~(uint64_t)255; };
     const uint64_t n = (uint64_t)c->n;
-    uint64_t o_done = 0;
-    uint64_t o_queue = up(o_done + 4 * sizeof(uint32_t));
+    uint64_t o_queue = 0;
     uint64_t o_part = up(o_queue + sizeof(TaskQueue));
     uint64_t o_force = up(o_part + (uint64_t)c->max_grid() * 4 * sizeof(double));
     uint64_t o_rho = up(o_force + 3 * n * sizeof(double));
@@ -1052,12 +1050,11 @@ int md_compute_forces_noalloc(md_ctx *c, const md_potential *p, int32_t precisio
     hipStream_t s = (hipStream_t)stream;
     c->last = s;
     unsigned char *base = c->scratch_dev;
-    // the counters and the queue must start at zero (a fill kernel, no memset node)
+    // the queue must start at zero (a fill kernel, no memset node)
     launch_zero(s, 1, reinterpret_cast<double *>(base), (int64_t)(o_part / sizeof(double)));
     const bool mixed = precision == MD_MIXED;
     ForceArgs a = force_args(c, p);
     a.mode = 0;
-    a.done = reinterpret_cast<uint32_t *>(base + o_done);
     a.ftq = reinterpret_cast<TaskQueue *>(base + o_queue);
     a.partial = reinterpret_cast<double *>(base + o_part);
     a.force = reinterpret_cast<double *>(base + o_force);
@@ -1175,13 +1172,12 @@ int md_verlet_step(md_ctx *c, const md_potential *p, int32_t precision, int32_t 
             g.outE = nullptr;
             g.outW = nullptr;
             g.outK = mode >= 2 ? a.outK : nullptr;
-            g.done = &c->ctl->done[2];
             g.partial = c->partial + (size_t)c->max_grid() * 8;
             timed(c, s, c->ev_force, [&] {
                 launch_waves(c, s, mixed, f);
                 if (en)
                     launch_atom_sums(s, c->grid_atoms(1024), c->n, c->eatom, c->watom, a.outE, a.outW,
-                                     c->partial, &c->ctl->done[0]);
+                                     c->partial);
                 launch_integrate(s, ga, g);
             });
         } else if (p->kind == MD_POT_LJ && half) {
@@ -1193,13 +1189,11 @@ int md_verlet_step(md_ctx *c, const md_potential *p, int32_t precision, int32_t 
             f.flag_set = nullptr;
             f.outE = mode >= 2 ? a.outE : nullptr;
             f.outW = mode >= 2 ? a.outW : nullptr;
-            f.done = &c->ctl->done[1];
             f.partial = c->partial + (size_t)c->max_grid() * 4;
             ForceArgs g = a;
             g.outE = nullptr;
             g.outW = nullptr;
             g.outK = mode >= 2 ? a.outK : nullptr;
-            g.done = &c->ctl->done[2];
             g.partial = c->partial + (size_t)c->max_grid() * 8;
             timed(c, s, c->ev_force, [&] {
                 launch_lj_half(s, gh, c->threads, mixed, f);
@@ -1276,7 +1270,6 @@ int md_force_vjp(md_ctx *c, const md_potential *p, int32_t precision, const doub
     launch_from_user(s, ga, c->n, c->id, u, reinterpret_cast<double4 *>(c->u_s));
     VjpArgs v{};
     v.f = force_args(c, p);
-    v.f.done = &c->ctl->done[3];
     v.u = reinterpret_cast<const double4 *>(c->u_s);
     v.vE = vE != nullptr ? vE : c->zeros_R;
     v.gx = c->gx_s;

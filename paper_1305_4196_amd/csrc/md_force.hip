@@ -149,11 +149,7 @@ __device__ __forceinline__ void finish_block(const ForceArgs &a, double accE, do
 {
     if (a.outE == nullptr && a.outK == nullptr && a.outW == nullptr) return;
     double v[4] = {accE, accW, accK, 0.0};
-    if (mdred::last_block_sum4(v, a.partial, a.done, lds) && threadIdx.x == 0) {
-        if (a.outE) *a.outE = v[0];
-        if (a.outW) *a.outW = v[1];
-        if (a.outK) *a.outK = 0.5 * a.mass * v[2];
-    }
+    mdred::block_to_partial4(v, a.partial, lds);
 }
 
 // ---------------------------------------------------------------- LJ pair scalar
@@ -505,11 +501,10 @@ __global__ __launch_bounds__(256) void k_deps_init(int32_t T, const int32_t *__r
 }
 
 // E and W summed over all atoms: per-workgroup partials over fixed strided
-// ranges, added in workgroup order by the last workgroup (fixed grid, so the
-// sums are bitwise repeatable)
+// ranges (added in workgroup order by k_sum_partials; fixed grid, so the sums
+// are bitwise repeatable)
 __global__ __launch_bounds__(256) void k_atom_sums(int64_t n, const double *__restrict__ eatom,
-                                                   const double *__restrict__ watom, double *energy,
-                                                   double *virial, double *partial, uint32_t *done)
+                                                   const double *__restrict__ watom, double *partial)
 {
     __shared__ double lds[4 * 256 / 64];
     double v[4] = {0.0, 0.0, 0.0, 0.0};
@@ -517,10 +512,20 @@ __global__ __launch_bounds__(256) void k_atom_sums(int64_t n, const double *__re
         v[0] += eatom[i];
         v[1] += watom[i];
     }
-    if (mdred::last_block_sum4(v, partial, done, lds) && threadIdx.x == 0) {
-        if (energy) *energy = v[0];
-        if (virial) *virial = v[1];
-    }
+    mdred::block_to_partial4(v, partial, lds);
+}
+
+// The totals of a launch's per-workgroup partials (g workgroups), added in
+// workgroup order by one workgroup of the producing launch's size: o[c] =
+// scale[c] * total c where o[c] is given.
+__global__ __launch_bounds__(1024) void k_sum_partials(const double *__restrict__ partial, int32_t g, SumOut o)
+{
+    __shared__ double lds[4 * 1024 / 64];
+    double v[4];
+    mdred::sum_partials4(partial, g, v, lds);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 4; c++)
+            if (o.out[c] != nullptr) *o.out[c] = o.scale[c] * v[c];
 }
 
 // velocity-Verlet pieces for forces already in a.force (half-list path); the
@@ -547,8 +552,7 @@ __global__ __launch_bounds__(256) void k_integrate(ForceArgs a)
     }
     double v[4] = {0.0, 0.0, accK, 0.0};
     if (a.outK == nullptr) return;
-    if (mdred::last_block_sum4(v, a.partial, a.done, lds) && threadIdx.x == 0)
-        *a.outK = 0.5 * a.mass * v[2];
+    mdred::block_to_partial4(v, a.partial, lds);
 }
 
 // ---------------------------------------------------------------- EAM pass 1: density
@@ -762,15 +766,23 @@ __global__ __launch_bounds__(256) void k_replica_sums(const RepDesc *__restrict_
 
 #define MD_LAUNCH_TASKS(KERNEL, NEXTRA, WITH_J)                                          \
     const size_t lds = stage_bytes(a.cap, NEXTRA, WITH_J, a.bd.stride);                    \
+    int used_ = 0;                                                                          \
     if (mixed) {                                                                            \
         allow_lds(KERNEL<true>, lds);                                                       \
-        hipLaunchKernelGGL((KERNEL<true>), dim3(resident_grid(KERNEL<true>, grid, threads, lds)), \
-                           dim3(threads), lds, s, a);                                       \
+        used_ = resident_grid(KERNEL<true>, grid, threads, lds);                            \
+        hipLaunchKernelGGL((KERNEL<true>), dim3(used_), dim3(threads), lds, s, a);          \
     } else {                                                                                \
         allow_lds(KERNEL<false>, lds);                                                      \
-        hipLaunchKernelGGL((KERNEL<false>), dim3(resident_grid(KERNEL<false>, grid, threads, lds)), \
-                           dim3(threads), lds, s, a);                                       \
+        used_ = resident_grid(KERNEL<false>, grid, threads, lds);                           \
+        hipLaunchKernelGGL((KERNEL<false>), dim3(used_), dim3(threads), lds, s, a);         \
     }
+
+// the energy, virial and kinetic-energy totals of a force launch of g workgroups
+void finish_sums(hipStream_t s, const ForceArgs &a, int g, int threads)
+{
+    if (a.outE == nullptr && a.outW == nullptr && a.outK == nullptr) return;
+    launch_sum_partials(s, a.partial, g, threads, SumOut{{a.outE, a.outW, a.outK, nullptr}, {1.0, 1.0, 0.5 * a.mass, 0.0}});
+}
 
 } // namespace
 
@@ -778,9 +790,11 @@ void launch_lj_full(hipStream_t s, int grid, int threads, bool mixed, const Forc
 {
     const size_t lds = stage_bytes(a.cap, 0, false, a.bd.stride);
     const bool en = a.outE != nullptr || a.outW != nullptr || a.eatom != nullptr;
+    int used = 0;
     auto go = [&](auto kernel) {
         allow_lds(kernel, lds);
-        hipLaunchKernelGGL(kernel, dim3(resident_grid(kernel, grid, threads, lds)), dim3(threads), lds, s, a);
+        used = resident_grid(kernel, grid, threads, lds);
+        hipLaunchKernelGGL(kernel, dim3(used), dim3(threads), lds, s, a);
     };
     if (mixed) {
         if (en) go(k_lj_full<true, true>);
@@ -789,11 +803,13 @@ void launch_lj_full(hipStream_t s, int grid, int threads, bool mixed, const Forc
         if (en) go(k_lj_full<false, true>);
         else go(k_lj_full<false, false>);
     }
+    finish_sums(s, a, used, threads);
 }
 
 void launch_lj_half(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a)
 {
     MD_LAUNCH_TASKS(k_lj_half, 0, true)
+    finish_sums(s, a, used_, threads);
 }
 
 void launch_eam_density(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a)
@@ -814,9 +830,11 @@ void launch_eam_force(hipStream_t s, int grid, int threads, bool mixed, const Fo
 {
     const size_t lds = stage_bytes(a.cap, 1, false, a.bd.stride);
     const bool en = a.outE != nullptr || a.outW != nullptr || a.eatom != nullptr;
+    int used = 0;
     auto go = [&](auto kernel) {
         allow_lds(kernel, lds);
-        hipLaunchKernelGGL(kernel, dim3(resident_grid(kernel, grid, threads, lds)), dim3(threads), lds, s, a);
+        used = resident_grid(kernel, grid, threads, lds);
+        hipLaunchKernelGGL(kernel, dim3(used), dim3(threads), lds, s, a);
     };
     if (mixed) {
         if (en) go(k_eam_force<true, true>);
@@ -825,6 +843,7 @@ void launch_eam_force(hipStream_t s, int grid, int threads, bool mixed, const Fo
         if (en) go(k_eam_force<false, true>);
         else go(k_eam_force<false, false>);
     }
+    finish_sums(s, a, used, threads);
 }
 
 void launch_lj_wave(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a)
@@ -847,14 +866,21 @@ void launch_lj_deps(hipStream_t s, int grid, int threads, bool mixed, const Forc
 }
 
 void launch_atom_sums(hipStream_t s, int grid, int64_t n, const double *eatom, const double *watom,
-                      double *energy, double *virial, double *partial, uint32_t *done)
+                      double *energy, double *virial, double *partial)
 {
-    hipLaunchKernelGGL(k_atom_sums, dim3(grid), dim3(256), 0, s, n, eatom, watom, energy, virial, partial, done);
+    hipLaunchKernelGGL(k_atom_sums, dim3(grid), dim3(256), 0, s, n, eatom, watom, partial);
+    launch_sum_partials(s, partial, grid, 256, SumOut{{energy, virial, nullptr, nullptr}, {1.0, 1.0, 0.0, 0.0}});
 }
 
 void launch_integrate(hipStream_t s, int grid, const ForceArgs &a)
 {
     hipLaunchKernelGGL(k_integrate, dim3(grid), dim3(256), 0, s, a);
+    finish_sums(s, a, grid, 256);
+}
+
+void launch_sum_partials(hipStream_t s, const double *partial, int g, int threads, SumOut o)
+{
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(threads), 0, s, partial, (int32_t)g, o);
 }
 
 void launch_zero(hipStream_t s, int grid, double *p, int64_t n)

@@ -67,7 +67,6 @@ struct DevCtl {
     int32_t nrebuild;     // rebuilds performed inside md_verlet_step
     int32_t max_nbhd;     // largest brick halo (candidates) seen
     int32_t max_brick;    // largest brick (atoms) seen
-    uint32_t done[4];     // last-block counters (one per reduction site)
     int32_t sched[4];     // dependent-schedule slot counters and abort word
 };
 
@@ -185,7 +184,6 @@ struct ForceArgs {
     int32_t *flag_clear;      // this step's request, cleared by block 0 (may be null)
     // reductions
     double *partial;          // [grid][4]
-    uint32_t *done;
     double *outE;             // final sums of this launch (each may be null):
     double *outK;             //   potential energy, kinetic energy,
     double *outW;             //   scalar virial
@@ -202,7 +200,16 @@ void launch_lj_wave(hipStream_t s, int grid, int threads, bool mixed, const Forc
 void launch_lj_deps(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a, const DepArgs &d,
                     const int32_t *npred, const int32_t *init_q, int32_t nroots);
 void launch_atom_sums(hipStream_t s, int grid, int64_t n, const double *eatom, const double *watom,
-                      double *energy, double *virial, double *partial, uint32_t *done);
+                      double *energy, double *virial, double *partial);
+// where the totals of a launch's per-workgroup partial sums go: out[c] (if not
+// null) receives scale[c] times total c
+struct SumOut {
+    double *out[4];
+    double scale[4];
+};
+// adds the partials of a launch of g workgroups in workgroup order (one
+// workgroup of `threads`, the producing launch's size, which fixes the order)
+void launch_sum_partials(hipStream_t s, const double *partial, int g, int threads, SumOut o);
 void launch_eam_density(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a);
 void launch_eam_force(hipStream_t s, int grid, int threads, bool mixed, const ForceArgs &a);
 void launch_integrate(hipStream_t s, int grid, const ForceArgs &a);

@@ -1,10 +1,12 @@
 // md_reduce.h -- fixed-order reductions shared by the force and adjoint kernels.
 //
 // Each workgroup reduces its threads' partial sums with a fixed butterfly and a
-// fixed cross-wave order, writes them to partial[block][4], and the last
-// workgroup to finish (device-scope counter) adds all blocks' partials in block
-// order.  The result is therefore bitwise repeatable for a given grid size,
-// which plays the role of the thread-local energy accumulators of Sec. II.C.
+// fixed cross-wave order and writes them to partial[block][4]; a one-workgroup
+// launch that follows the producing launch on its stream adds all blocks'
+// partials in block order (the launch boundary orders the two, so no
+// workgroup waits on a device-wide fence).  The result is therefore bitwise
+// repeatable for a given grid size, which plays the role of the thread-local
+// energy accumulators of Sec. II.C.
 #pragma once
 
 #include "md_internal.h"
@@ -17,7 +19,7 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// sums v[0..3] over a block of up to 512 threads (a multiple of 64); every
+// sums v[0..3] over a block of up to 1024 threads (a multiple of 64); every
 // thread receives the totals, added wave by wave in wave order
 __device__ __forceinline__ void block_sum4(double v[4], double *lds /* [4 * waves] */)
 {
@@ -36,40 +38,25 @@ __device__ __forceinline__ void block_sum4(double v[4], double *lds /* [4 * wave
     __syncthreads();
 }
 
-__device__ __forceinline__ void store_agent(double *p, double v)
+// Writes this block's totals of v[0..3] to partial[block][4] (every thread
+// receives the totals in v).
+__device__ __forceinline__ void block_to_partial4(double v[4], double *partial, double *lds)
 {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ double load_agent(const double *p)
-{
-    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Writes this block's partial sums; returns true (in every thread) for the
-// last block to finish, which then holds every block's partials in v[] summed
-// in block order.
-__device__ __forceinline__ bool last_block_sum4(double v[4], double *partial, uint32_t *done,
-                                                double *lds)
-{
-    __shared__ int is_last;
     block_sum4(v, lds);
-    if (threadIdx.x == 0) {
-        for (int c = 0; c < 4; c++) store_agent(&partial[blockIdx.x * 4 + c], v[c]);
-        __threadfence();
-        const uint32_t prev = atomicAdd(done, 1u);
-        is_last = (prev == gridDim.x - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 4; c++) partial[blockIdx.x * 4 + c] = v[c];
+}
+
+// The totals of the partials of g blocks, added in block order: thread t takes
+// blocks t, t + T, ..., then the block sums its threads as block_sum4 does
+// (every thread receives the totals in v).
+__device__ __forceinline__ void sum_partials4(const double *partial, int32_t g, double v[4], double *lds)
+{
     double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x)
-        for (int c = 0; c < 4; c++) s[c] += load_agent(&partial[b * 4 + c]);
+    for (int32_t b = threadIdx.x; b < g; b += blockDim.x)
+        for (int c = 0; c < 4; c++) s[c] += partial[b * 4 + c];
     block_sum4(s, lds);
     for (int c = 0; c < 4; c++) v[c] = s[c];
-    if (threadIdx.x == 0) *done = 0u;
-    return true;
 }
 
 } // namespace mdred

@@ -143,10 +143,7 @@ __global__ __launch_bounds__(TASK_MAX_THREADS, 4) void k_lj_vjp(VjpArgs v)
     BRICK_TASK_END
     // each unordered pair is visited twice: half weight
     double s[4] = {2.0 * acc_e, 12.0 * eps * acc_s / sig, 0.0, 0.0};
-    if (mdred::last_block_sum4(s, v.gpart, a.done, lds) && threadIdx.x == 0 && v.gout != nullptr) {
-        v.gout[0] = s[0];
-        v.gout[1] = s[1];
-    }
+    if (v.gout != nullptr) mdred::block_to_partial4(s, v.gpart, lds);
 }
 
 // ---------------------------------------------------------------- EAM pass A
@@ -377,14 +374,18 @@ void launch_lj_vjp(hipStream_t s, int grid, int threads, const VjpArgs &a, int32
         per_cu(reinterpret_cast<const void *>(k_lj_vjp<true>), threads, lds_u) >=
             per_cu(reinterpret_cast<const void *>(k_lj_vjp<false>), threads, lds_g)) {
         allow_lds(k_lj_vjp<true>, lds_u);
-        hipLaunchKernelGGL(k_lj_vjp<true>, dim3(resident_grid(k_lj_vjp<true>, grid, threads, lds_u)), dim3(threads),
-                           lds_u, s, a);
+        const int used = resident_grid(k_lj_vjp<true>, grid, threads, lds_u);
+        hipLaunchKernelGGL(k_lj_vjp<true>, dim3(used), dim3(threads), lds_u, s, a);
+        if (a.gout != nullptr)
+            launch_sum_partials(s, a.gpart, used, threads, SumOut{{a.gout, a.gout + 1, nullptr, nullptr}, {1.0, 1.0, 0.0, 0.0}});
         return;
     }
     const size_t lds = stage_bytes(a.f.cap, 0, true, a.f.bd.stride);
     allow_lds(k_lj_vjp<false>, lds);
-    hipLaunchKernelGGL(k_lj_vjp<false>, dim3(resident_grid(k_lj_vjp<false>, grid, threads, lds)), dim3(threads), lds,
-                       s, a);
+    const int used = resident_grid(k_lj_vjp<false>, grid, threads, lds);
+    hipLaunchKernelGGL(k_lj_vjp<false>, dim3(used), dim3(threads), lds, s, a);
+    if (a.gout != nullptr)
+        launch_sum_partials(s, a.gpart, used, threads, SumOut{{a.gout, a.gout + 1, nullptr, nullptr}, {1.0, 1.0, 0.0, 0.0}});
 }
 
 void launch_eam_vjp_a(hipStream_t s, int grid, int threads, const VjpArgs &a, int32_t lds_max)
