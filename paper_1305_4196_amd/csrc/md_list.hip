@@ -166,6 +166,16 @@ __device__ __forceinline__ i32x4 buffer_desc(uintptr_t base, uint32_t stride, ui
     return r;
 }
 
+// a where the lane's bit of mask is set, else b: one v_cndmask on the mask
+// (a select on the inverse ballot compiles to a branch on exec instead, two
+// scalar instructions more)
+__device__ __forceinline__ int32_t select_lanes(uint64_t mask, int32_t a, int32_t b)
+{
+    int32_t r;
+    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(b), "v"(a), "s"(mask));
+    return r;
+}
+
 // What the tile tests of one cell share.
 struct CellCtx {
     double L[3], hL[3];
@@ -256,8 +266,7 @@ __device__ __forceinline__ void test_tile(const CellCtx &cc, const double *cx, c
         for (int c = 0; c < NCH; c++) {
             const uint32_t p = __builtin_amdgcn_mbcnt_hi((uint32_t)(m[c] >> 32),
                                __builtin_amdgcn_mbcnt_lo((uint32_t)m[c], (uint32_t)ni));
-            const bool hit = __builtin_amdgcn_inverse_ballot_w64(m[c]);
-            const int32_t idx = hit ? (int32_t)entry_index<NARROW>(p) : cc.row_entries;
+            const int32_t idx = select_lanes(m[c], (int32_t)entry_index<NARROW>(p), cc.row_entries);
             if (NARROW) {
                 sbuf_store_i16((int16_t)ck[c], cc.rows, idx, 0, row_off, 0);
             } else {
