@@ -437,6 +437,72 @@ def test_nonfinite_force_is_flagged():
     assert s.status()[0] == B.MD_OK          # flags are cleared after reading
 
 
+# ---------------------------------------------------------------- degenerate systems
+def dilute(n_side=4, spacing=5.0, vmax=0.3, seed=7):
+    """n_side^3 atoms on a simple cubic lattice `spacing` apart, more than either
+    potential's list radius (LJ 2.8, FS-EAM 3.9): every neighbour list is empty."""
+    g = np.random.default_rng(seed)
+    ax = (np.arange(n_side) + 0.5) * spacing
+    X, Y, Z = np.meshgrid(ax, ax, ax, indexing="ij")
+    pos = np.ascontiguousarray(np.stack([X.ravel(), Y.ravel(), Z.ravel()]))
+    vel = np.ascontiguousarray(g.uniform(-vmax, vmax, size=pos.shape))
+    L = n_side * spacing
+    return pos, vel, np.array([[L, L, L]])
+
+
+@pytest.mark.parametrize("kind", ["lj", "eam"])
+@pytest.mark.parametrize("prec", [B.MD_FP64, B.MD_MIXED])
+def test_isolated_atoms_have_empty_lists(kind, prec):
+    """No pair within the list radius: empty lists, zero forces and virial, and
+    the energy the oracle gives (LJ 0; EAM the embedding energy at zero density)."""
+    pos, vel, boxes = dilute()
+    pot = W.lj_potential() if kind == "lj" else W.fs_eam_potential()
+    s = MDSystem(pos, boxes, [0, pos.shape[1]], pot, 0.3, vel=vel)
+    F, E, Wv = s.forces(prec)
+    assert B.md_query(s.ctx, 10) == 0
+    Fo, Eo, Wo = oracle.forces(pos, boxes[0], pot, skin=0.3)
+    assert np.all(Fo == 0.0) and Wo == 0.0
+    assert torch.count_nonzero(F).item() == 0
+    assert Wv.item() == 0.0
+    assert E.item() == pytest.approx(Eo, rel=1e-12, abs=0.0)
+
+
+@pytest.mark.parametrize("kind", ["lj", "eam"])
+def test_single_atom(kind):
+    pot = W.lj_potential() if kind == "lj" else W.fs_eam_potential()
+    pos = np.array([[1.25], [7.5], [3.0]])
+    boxes = np.array([[9.0, 10.0, 11.0]])
+    s = MDSystem(pos, boxes, [0, 1], pot, 0.3)
+    F, E, Wv = s.forces(B.MD_FP64)
+    Fo, Eo, Wo = oracle.forces(pos, boxes[0], pot, skin=0.3)
+    assert torch.count_nonzero(F).item() == 0 and Wv.item() == 0.0
+    assert E.item() == pytest.approx(Eo, rel=1e-12, abs=0.0)
+
+
+@pytest.mark.parametrize("prec", [B.MD_FP64, B.MD_MIXED])
+def test_isolated_atoms_fly_free(prec):
+    """Velocity Verlet without forces: velocities unchanged bit for bit, positions
+    and the rebuilds those moves trigger as in the oracle, the kinetic energy
+    constant and the potential energy and virial zero in every recorded step."""
+    pos, vel, boxes = dilute()
+    L = boxes[0]
+    pot = W.lj_potential()
+    s = MDSystem(pos, boxes, [0, pos.shape[1]], pot, 0.3, vel=vel)
+    v0 = s.vel.clone()
+    F, hist, nreb = s.run(200, 0.005, 1.0, prec)
+    xo, vo, Fo, ho, nrebo = oracle.verlet(pos, vel, L, pot, 0.005, 1.0, 200, 0.3)
+    assert torch.equal(s.vel, v0) and np.array_equal(vo, vel)
+    assert torch.count_nonzero(F).item() == 0
+    assert nreb == nrebo and nreb > 0
+    d = s.pos.cpu().numpy() - xo
+    d -= L[:, None] * np.round(d / L[:, None])
+    assert np.max(np.abs(d)) < 1e-12
+    h = hist.cpu().numpy()
+    assert np.all(h[:, 0] == 0.0) and np.all(h[:, 2] == 0.0)
+    assert np.allclose(h[:, 1], 0.5 * np.sum(vel * vel), rtol=1e-13, atol=0.0)
+    assert np.allclose(h, ho, rtol=1e-13, atol=0.0)
+
+
 # ---------------------------------------------------------------- batched replicas
 @pytest.mark.parametrize("kind", ["lj", "eam"])
 def test_replica_batch_forces(kind):
