@@ -108,11 +108,12 @@ typedef struct {
 
 typedef struct md_ctx md_ctx;
 
-/* Create a context for n_atoms_total atoms in n_replicas replicas.
- * replica_offsets [host]: n_replicas + 1 int64, offsets[0] = 0,
+/* Create a context for n_atoms_total atoms in n_replicas replicas,
+ * 1 <= n_atoms_total <= 2^26 (67,108,864: a list entry holds a 26-bit atom
+ * index).  replica_offsets [host]: n_replicas + 1 int64, offsets[0] = 0,
  * offsets[n_replicas] = n_atoms_total, non-decreasing with every replica
  * non-empty.  Allocates the per-atom workspace on the current device.
- * Errors: MD_ERR_ARG, MD_ERR_HIP. */
+ * Errors: MD_ERR_ARG (including n_atoms_total out of range), MD_ERR_HIP. */
 int md_create(md_ctx **ctx, int64_t n_atoms_total, int32_t n_replicas,
               const int64_t *replica_offsets);
 
