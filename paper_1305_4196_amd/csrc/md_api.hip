@@ -335,7 +335,7 @@ void sort_into_tmp(md_ctx *c, const int32_t *pred, bool with_vel, hipStream_t s)
                c->count, &c->ctl->err);
     launch_scan(s, pred, c->C, c->count, c->start, c->ctl);
     launch_scatter(s, ga, pred, c->n, c->cell_of, c->slot, c->start, c->perm);
-    launch_sort_cells(s, c->grid_cells(4, 8), pred, c->C, c->start, c->perm, c->id, c->pos[c->cur],
+    launch_sort_cells(s, c->grid_cells(4, 8), pred, c->C, c->start, c->count, c->perm, c->id, c->pos[c->cur],
                       with_vel ? c->vel : nullptr, c->n, c->pos_t, with_vel ? c->vel_t : nullptr,
                       c->id_t);
 }

@@ -102,81 +102,110 @@ __global__ void k_bin(const int32_t *__restrict__ pred, int64_t n, const RepDesc
     }
 }
 
-// Exclusive scan of the cell counts by one workgroup of 1024 threads, in
-// chunks of 8192 cells: each thread takes 8 consecutive counts, the threads'
-// totals are scanned across the workgroup, and a carry links the chunks.  The
-// counts are cleared for the next build.
+// Exclusive scan of the cell counts.  The counts are left in place: k_sort_cells,
+// which visits every cell, clears them for the next build.
+constexpr int SCAN_CHUNK = 8192;           // cells per chunk: 8 per thread of 1024
+constexpr int SCAN_MAX_CHUNKS = 64;        // chunks scanned by k_scan_chunks
+
+// Sum over the workgroup of 1024 threads (every thread gets it).
+__device__ __forceinline__ int32_t block_sum_1024(int32_t v, int32_t *wsum)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if (lane == 0) wsum[wv] = v;
+    __syncthreads();
+    int32_t t = 0;
+    for (int w = 0; w < 16; w++) t += wsum[w];
+    return t;
+}
+
+// One chunk of SCAN_CHUNK cells from c0 on, given the sum of the counts before
+// it: each thread takes 8 consecutive counts, the threads' totals are scanned
+// across the workgroup; returns the chunk's total.
+__device__ __forceinline__ int32_t scan_chunk(int64_t C, int64_t c0, int32_t carry,
+                                              const int32_t *__restrict__ count,
+                                              int32_t *__restrict__ start, int32_t *wsum)
+{
+    const int t = threadIdx.x;
+    const int lane = t & 63, wv = t >> 6;
+    const int64_t k0 = c0 + 8 * (int64_t)t;
+    int32_t v[8];
+    if (k0 + 8 <= C) {
+        const int4 a = reinterpret_cast<const int4 *>(count + k0)[0];
+        const int4 b = reinterpret_cast<const int4 *>(count + k0)[1];
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+        for (int q = 0; q < 8; q++) v[q] = k0 + q < C ? count[k0 + q] : 0;
+    }
+    int32_t s = 0;
+    for (int q = 0; q < 8; q++) s += v[q];
+    int32_t inc = s;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    __syncthreads();
+    if (lane == 63) wsum[wv] = inc;
+    __syncthreads();
+    int32_t before = 0, total = 0;
+    for (int w = 0; w < 16; w++) {
+        const int32_t ws = wsum[w];
+        before += w < wv ? ws : 0;
+        total += ws;
+    }
+    int32_t run = carry + before + inc - s;
+    int32_t o[8];
+    for (int q = 0; q < 8; q++) {
+        o[q] = run;
+        run += v[q];
+    }
+    if (k0 + 8 <= C) {
+        reinterpret_cast<int4 *>(start + k0)[0] = make_int4(o[0], o[1], o[2], o[3]);
+        reinterpret_cast<int4 *>(start + k0)[1] = make_int4(o[4], o[5], o[6], o[7]);
+    } else {
+        for (int q = 0; q < 8; q++)
+            if (k0 + q < C) start[k0 + q] = o[q];
+    }
+    return total;
+}
+
+// Up to SCAN_MAX_CHUNKS chunks, one workgroup each: a workgroup first sums the
+// counts of every chunk before its own (read from L2; no workgroup waits for
+// another), so the chunks are scanned in parallel rather than one after the
+// other by one CU, whose bandwidth to L2 bounds a single-workgroup scan.
+__global__ __launch_bounds__(1024) void k_scan_chunks(const int32_t *__restrict__ pred, int64_t C,
+                                                      const int32_t *__restrict__ count,
+                                                      int32_t *__restrict__ start, DevCtl *ctl)
+{
+    if (*pred == 0) return;
+    __shared__ int32_t wsum[16];
+    const int64_t c0 = (int64_t)blockIdx.x * SCAN_CHUNK;
+    int32_t part = 0;
+    for (int64_t k = 4 * (int64_t)threadIdx.x; k < c0; k += 4 * 1024) {
+        const int4 a = *reinterpret_cast<const int4 *>(count + k);
+        part += (a.x + a.y) + (a.z + a.w);
+    }
+    const int32_t carry = block_sum_1024(part, wsum);
+    const int32_t total = scan_chunk(C, c0, carry, count, start, wsum);
+    if (threadIdx.x == 0) {
+        if (blockIdx.x == gridDim.x - 1) start[C] = carry + total;
+        if (blockIdx.x == 0) ctl->nrebuild += 1;
+    }
+}
+
+// More chunks: one workgroup takes them in order, a carry linking them.
 __global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ pred, int64_t C,
-                                               int32_t *__restrict__ count,
+                                               const int32_t *__restrict__ count,
                                                int32_t *__restrict__ start, DevCtl *ctl)
 {
     if (*pred == 0) return;
     __shared__ int32_t wsum[16];
-    __shared__ int32_t wmax[16];
-    const int t = threadIdx.x;
-    const int lane = t & 63, wv = t >> 6;
-    int32_t carry = 0, mx = 0;
-    for (int64_t c0 = 0; c0 < C; c0 += 8192) {
-        const int64_t k0 = c0 + 8 * (int64_t)t;
-        int32_t v[8];
-        if (k0 + 8 <= C) {
-            const int4 a = reinterpret_cast<const int4 *>(count + k0)[0];
-            const int4 b = reinterpret_cast<const int4 *>(count + k0)[1];
-            v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-            v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
-        } else {
-            for (int q = 0; q < 8; q++) v[q] = k0 + q < C ? count[k0 + q] : 0;
-        }
-        int32_t s = 0;
-        for (int q = 0; q < 8; q++) {
-            s += v[q];
-            mx = v[q] > mx ? v[q] : mx;
-        }
-        int32_t inc = s;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int32_t y = __shfl_up(inc, o, 64);
-            if (lane >= o) inc += y;
-        }
-        if (lane == 63) wsum[wv] = inc;
-        __syncthreads();
-        int32_t before = 0, total = 0;
-        for (int w = 0; w < 16; w++) {
-            const int32_t ws = wsum[w];
-            before += w < wv ? ws : 0;
-            total += ws;
-        }
-        int32_t run = carry + before + inc - s;
-        int32_t o[8];
-        for (int q = 0; q < 8; q++) {
-            o[q] = run;
-            run += v[q];
-        }
-        if (k0 + 8 <= C) {
-            reinterpret_cast<int4 *>(start + k0)[0] = make_int4(o[0], o[1], o[2], o[3]);
-            reinterpret_cast<int4 *>(start + k0)[1] = make_int4(o[4], o[5], o[6], o[7]);
-            reinterpret_cast<int4 *>(count + k0)[0] = make_int4(0, 0, 0, 0);
-            reinterpret_cast<int4 *>(count + k0)[1] = make_int4(0, 0, 0, 0);
-        } else {
-            for (int q = 0; q < 8; q++)
-                if (k0 + q < C) {
-                    start[k0 + q] = o[q];
-                    count[k0 + q] = 0;
-                }
-        }
-        carry += total;
-        __syncthreads();
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        const int32_t y = __shfl_xor(mx, o, 64);
-        mx = y > mx ? y : mx;
-    }
-    if (lane == 0) wmax[wv] = mx;
-    __syncthreads();
-    if (t == 0) {
-        int32_t m = 0;
-        for (int w = 0; w < 16; w++) m = wmax[w] > m ? wmax[w] : m;
+    int32_t carry = 0;
+    for (int64_t c0 = 0; c0 < C; c0 += SCAN_CHUNK) carry += scan_chunk(C, c0, carry, count, start, wsum);
+    if (threadIdx.x == 0) {
         start[C] = carry;
-        ctl->max_cell = m;
         ctl->nrebuild += 1;
     }
 }
@@ -195,6 +224,7 @@ __global__ void k_scatter(const int32_t *__restrict__ pred, int64_t n,
 // (positions, velocities, ids) to their final slots in the output buffers.
 __global__ __launch_bounds__(256) void k_sort_cells(
     const int32_t *__restrict__ pred, int64_t C, const int32_t *__restrict__ start,
+    int32_t *__restrict__ count,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ id,
     const double4 *__restrict__ pos, const double *__restrict__ vel, int64_t n,
     double4 *__restrict__ pos_out, double *__restrict__ vel_out, int32_t *__restrict__ id_out)
@@ -206,6 +236,7 @@ __global__ __launch_bounds__(256) void k_sort_cells(
     for (int64_t c = wave; c < C; c += nwaves) {
         const int32_t s = start[c];
         const int32_t m = start[c + 1] - s;
+        if (lane == 0) count[c] = 0;              // for the next build's counting
         if (m <= 64) {
             int32_t old = 0, key = 0x7fffffff;
             if (lane < m) {
@@ -293,7 +324,11 @@ void launch_bin(hipStream_t s, int grid, const int32_t *pred, int64_t n, int32_t
 void launch_scan(hipStream_t s, const int32_t *pred, int64_t C, int32_t *count, int32_t *start,
                  DevCtl *ctl)
 {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, pred, C, count, start, ctl);
+    const int64_t chunks = (C + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    if (chunks <= SCAN_MAX_CHUNKS)
+        hipLaunchKernelGGL(k_scan_chunks, dim3((unsigned)chunks), dim3(1024), 0, s, pred, C, count, start, ctl);
+    else
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, pred, C, count, start, ctl);
 }
 
 void launch_scatter(hipStream_t s, int grid, const int32_t *pred, int64_t n,
@@ -304,11 +339,11 @@ void launch_scatter(hipStream_t s, int grid, const int32_t *pred, int64_t n,
 }
 
 void launch_sort_cells(hipStream_t s, int grid, const int32_t *pred, int64_t C,
-                       const int32_t *start, const int32_t *perm, const int32_t *id,
+                       const int32_t *start, int32_t *count, const int32_t *perm, const int32_t *id,
                        const double4 *pos, const double *vel, int64_t n, double4 *pos_out,
                        double *vel_out, int32_t *id_out)
 {
-    hipLaunchKernelGGL(k_sort_cells, dim3(grid), dim3(256), 0, s, pred, C, start, perm, id, pos,
+    hipLaunchKernelGGL(k_sort_cells, dim3(grid), dim3(256), 0, s, pred, C, start, count, perm, id, pos,
                        vel, n, pos_out, vel_out, id_out);
 }
 

@@ -63,7 +63,6 @@ struct DevCtl {
     int32_t rebuild[2];   // rebuild request, indexed by step parity
     int32_t err;          // sticky MD_FLAG_* bits
     int32_t max_cnt;      // largest per-atom list length of the last build
-    int32_t max_cell;     // largest cell occupancy of the last build
     int32_t nrebuild;     // rebuilds performed inside md_verlet_step
     int32_t max_nbhd;     // largest brick halo (candidates) seen
     int32_t max_brick;    // largest brick (atoms) seen
@@ -83,7 +82,7 @@ void launch_scatter(hipStream_t s, int grid, const int32_t *pred, int64_t n,
                     const int32_t *cell_of, const int32_t *slot, const int32_t *start,
                     int32_t *perm);
 void launch_sort_cells(hipStream_t s, int grid, const int32_t *pred, int64_t C,
-                       const int32_t *start, const int32_t *perm, const int32_t *id,
+                       const int32_t *start, int32_t *count, const int32_t *perm, const int32_t *id,
                        const double4 *pos, const double *vel, int64_t n, double4 *pos_out,
                        double *vel_out, int32_t *id_out);
 void launch_copy_back(hipStream_t s, int grid, const int32_t *pred, int64_t n,
