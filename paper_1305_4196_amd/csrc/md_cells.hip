@@ -220,8 +220,74 @@ __global__ void k_scatter(const int32_t *__restrict__ pred, int64_t n,
         perm[start[cell_of[i]] + slot[i]] = (int32_t)i;
 }
 
-// One wavefront per cell: rank the cell's atoms by user index and move them
-// (positions, velocities, ids) to their final slots in the output buffers.
+// Moves atom `old` of a cell to its slot d (positions, velocities, id).
+__device__ __forceinline__ void move_atom(int32_t old, int64_t d, int32_t key, const double4 *__restrict__ pos,
+                                          const double *__restrict__ vel, int64_t n,
+                                          double4 *__restrict__ pos_out, double *__restrict__ vel_out,
+                                          int32_t *__restrict__ id_out)
+{
+    pos_out[d] = pos[old];
+    if (vel != nullptr) {
+        vel_out[d] = vel[old];
+        vel_out[n + d] = vel[n + old];
+        vel_out[2 * n + d] = vel[2 * n + old];
+    }
+    id_out[d] = key;
+}
+
+// Cells of at most G atoms, 64 / G of them at once: lane g0 + l (g0 the first
+// lane of its group of G) holds atom l of its cell (start s, m atoms), whose
+// rank is the number of the cell's atoms with a smaller user index; mmax is
+// the largest m of the wavefront's cells (lanes past their cell hold the
+// largest key, which counts for no atom).
+__device__ __forceinline__ void sort_groups(int G, int32_t s, int32_t m, int32_t mmax,
+                                            const int32_t *__restrict__ perm, const int32_t *__restrict__ id,
+                                            const double4 *__restrict__ pos, const double *__restrict__ vel,
+                                            int64_t n, double4 *__restrict__ pos_out, double *__restrict__ vel_out,
+                                            int32_t *__restrict__ id_out)
+{
+    const int lane = threadIdx.x & 63;
+    const int g0 = lane & ~(G - 1), l = lane & (G - 1);
+    int32_t old = 0, key = 0x7fffffff;
+    if (l < m) {
+        old = perm[s + l];
+        key = id[old];
+    }
+    int32_t rank = 0;
+    for (int q = 0; q < mmax; q++) {
+        const int32_t kq = __shfl(key, g0 + q, 64);
+        rank += kq < key ? 1 : 0;
+    }
+    if (l < m) move_atom(old, (int64_t)s + rank, key, pos, vel, n, pos_out, vel_out, id_out);
+}
+
+// A cell of more than 64 atoms, 64 at a time (ranks counted over the whole cell).
+__device__ __forceinline__ void sort_large(int32_t s, int32_t m, const int32_t *__restrict__ perm,
+                                           const int32_t *__restrict__ id, const double4 *__restrict__ pos,
+                                           const double *__restrict__ vel, int64_t n,
+                                           double4 *__restrict__ pos_out, double *__restrict__ vel_out,
+                                           int32_t *__restrict__ id_out)
+{
+    const int lane = threadIdx.x & 63;
+    for (int32_t b = 0; b < m; b += 64) {
+        const int32_t k = b + lane;
+        int32_t old = 0, key = 0;
+        if (k < m) {
+            old = perm[s + k];
+            key = id[old];
+        }
+        int32_t rank = 0;
+        for (int32_t l = 0; l < m; l++) rank += id[perm[s + l]] < key ? 1 : 0;
+        if (k < m) move_atom(old, (int64_t)s + rank, key, pos, vel, n, pos_out, vel_out, id_out);
+    }
+}
+
+// Ranks each cell's atoms by user index and moves them (positions, velocities,
+// ids) to their final slots in the output buffers, and clears the cell counts
+// for the next build.  A wavefront takes four consecutive cells at a time:
+// all four together in groups of 16 lanes when none holds more than 16 atoms,
+// else each pair together in groups of 32 when both fit, else one cell at a
+// time (the chain of dependent loads per cell, not the lanes, sets the time).
 __global__ __launch_bounds__(256) void k_sort_cells(
     const int32_t *__restrict__ pred, int64_t C, const int32_t *__restrict__ start,
     int32_t *__restrict__ count,
@@ -233,51 +299,36 @@ __global__ __launch_bounds__(256) void k_sort_cells(
     const int lane = threadIdx.x & 63;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t c = wave; c < C; c += nwaves) {
-        const int32_t s = start[c];
-        const int32_t m = start[c + 1] - s;
-        if (lane == 0) count[c] = 0;              // for the next build's counting
-        if (m <= 64) {
-            int32_t old = 0, key = 0x7fffffff;
-            if (lane < m) {
-                old = perm[s + lane];
-                key = id[old];
+    for (int64_t c0 = 4 * wave; c0 < C; c0 += 4 * nwaves) {
+        const int32_t nc = (int32_t)(C - c0 < 4 ? C - c0 : 4);
+        // starts of the (up to) four cells and the end of the last, lanes 0..nc
+        const int32_t st = lane <= nc ? start[c0 + lane] : 0;
+        if (lane < nc) count[c0 + lane] = 0;
+        int32_t sk[4], mk[4];
+        for (int k = 0; k < 4; k++) {
+            sk[k] = __shfl(st, k, 64);
+            mk[k] = k < nc ? __shfl(st, k + 1, 64) - sk[k] : 0;
+        }
+        const int32_t m01 = max(mk[0], mk[1]), m23 = max(mk[2], mk[3]);
+        if (max(m01, m23) <= 16) {
+            const int k = lane >> 4;
+            const int32_t s = k == 0 ? sk[0] : (k == 1 ? sk[1] : (k == 2 ? sk[2] : sk[3]));
+            const int32_t m = k == 0 ? mk[0] : (k == 1 ? mk[1] : (k == 2 ? mk[2] : mk[3]));
+            sort_groups(16, s, m, max(m01, m23), perm, id, pos, vel, n, pos_out, vel_out, id_out);
+            continue;
+        }
+        for (int p = 0; p < 2; p++) {
+            const int32_t sa = sk[2 * p], ma = mk[2 * p], sb = sk[2 * p + 1], mb = mk[2 * p + 1];
+            if (max(ma, mb) <= 32) {
+                const bool hi = lane >= 32;
+                sort_groups(32, hi ? sb : sa, hi ? mb : ma, max(ma, mb), perm, id, pos, vel, n, pos_out,
+                            vel_out, id_out);
+                continue;
             }
-            int32_t rank = 0;
-            for (int l = 0; l < m; l++) {
-                int32_t kl = __shfl(key, l, 64);
-                rank += kl < key ? 1 : 0;
-            }
-            if (lane < m) {
-                const int64_t d = s + rank;
-                pos_out[d] = pos[old];
-                if (vel != nullptr) {
-                    vel_out[d] = vel[old];
-                    vel_out[n + d] = vel[n + old];
-                    vel_out[2 * n + d] = vel[2 * n + old];
-                }
-                id_out[d] = key;
-            }
-        } else {
-            for (int32_t b = 0; b < m; b += 64) {
-                const int32_t k = b + lane;
-                int32_t old = 0, key = 0;
-                if (k < m) {
-                    old = perm[s + k];
-                    key = id[old];
-                }
-                int32_t rank = 0;
-                for (int32_t l = 0; l < m; l++) rank += id[perm[s + l]] < key ? 1 : 0;
-                if (k < m) {
-                    const int64_t d = s + rank;
-                    pos_out[d] = pos[old];
-                    if (vel != nullptr) {
-                        vel_out[d] = vel[old];
-                        vel_out[n + d] = vel[n + old];
-                        vel_out[2 * n + d] = vel[2 * n + old];
-                    }
-                    id_out[d] = key;
-                }
+            for (int h = 0; h < 2; h++) {
+                const int32_t s = h ? sb : sa, m = h ? mb : ma;
+                if (m <= 64) sort_groups(64, s, m, m, perm, id, pos, vel, n, pos_out, vel_out, id_out);
+                else sort_large(s, m, perm, id, pos, vel, n, pos_out, vel_out, id_out);
             }
         }
     }
