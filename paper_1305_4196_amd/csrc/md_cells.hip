@@ -5,8 +5,8 @@
 // cell index x fastest.  Within a cell atoms are ordered by ascending user index,
 // so the sorted order -- and every sum taken in it -- is deterministic.
 //
-// Kernels run on a fixed persistent grid with grid-stride loops.  Each takes a
-// predicate word: inside the integration loop it is the device-side rebuild
+// Kernels run on a fixed persistent grid with grid-stride loops (the count scan
+// on one workgroup per chunk of cells).  Each takes a predicate word: inside the integration loop it is the device-side rebuild
 // request, so an unneeded rebuild costs only an early exit and no host sync.
 #include "md_internal.h"
 
