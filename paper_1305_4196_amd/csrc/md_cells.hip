@@ -67,11 +67,16 @@ __global__ void k_bin(const int32_t *__restrict__ pred, int64_t n, const RepDesc
         int32_t c = -1;
         if (valid) {
             const RepDesc &r = reps[rep_of[i]];
-            double4 p = pos[i];
-            p.x = wrap1(p.x, r.L[0]);
-            p.y = wrap1(p.y, r.L[1]);
-            p.z = wrap1(p.z, r.L[2]);
-            pos[i] = p;
+            const double4 q = pos[i];
+            double4 p = q;
+            p.x = wrap1(q.x, r.L[0]);
+            p.y = wrap1(q.y, r.L[1]);
+            p.z = wrap1(q.z, r.L[2]);
+            // stored only where wrapping changed a bit (most atoms are inside the box)
+            if (__double_as_longlong(p.x) != __double_as_longlong(q.x) ||
+                __double_as_longlong(p.y) != __double_as_longlong(q.y) ||
+                __double_as_longlong(p.z) != __double_as_longlong(q.z))
+                pos[i] = p;
             if (isfinite(p.x) && isfinite(p.y) && isfinite(p.z)) {
                 const int32_t cx = cell_coord(p.x, r.nc[0], r.L[0]);
                 const int32_t cy = cell_coord(p.y, r.nc[1], r.L[1]);
